@@ -1,0 +1,41 @@
+"""CPU oracle for the space-time block-preconditioned solve of linearised resistive MHD.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check of the entry
+module and the CPU-baseline leg of the benchmark may import this package.  The
+library (the HIP path) never imports, links or calls it, and it shares no code
+with the library: the only common module is the seeded input generator, which
+holds none of the method's arithmetic.
+
+It is plain, slow, float64 NumPy/SciPy code written from the paper
+(Danieli, Southworth, Schroder, "Space-time block preconditioning for
+incompressible resistive magnetohydrodynamics", arXiv:2309.00768):
+
+* ``fem``        Q2/Q1 bases, Gauss quadrature, mesh, assembly;
+* ``blocks``     the single-step Jacobian blocks, eq. (jacobianDiscrete), the
+                 PCD operator of eq. (Fp) and the mean field of the wave
+                 approximation (Sec. "An inner wave approximation");
+* ``spacetime``  the space-time Jacobian, eq. (jacobianSTDiscrete), the
+                 preconditioner P_T, eq. (PT), with exact inner solves
+                 (sequential time stepping + sparse LU, Sec. "Performance of
+                 preconditioner"), its transpose, right-preconditioned GMRES,
+                 and the direct forward/backward substitutions in time;
+* ``nonlinear``  the residual of the recurrence, eq. (recurrence), used to pin
+                 the Jacobian by finite differences.
+
+Parity status: every function here is pinned by a ``-m "not gpu"`` test against
+closed forms, invariants, brute force or finite differences, except the PCD
+boundary treatment of K_p and F_p (pure Neumann, no Robin term), which the
+paper defers to its companion work: parity unpinned for that choice.
+"""
+from .fem import Mesh, RefSquare, gauss01, lagrange1d  # noqa: F401
+from .blocks import ConstantBlocks, SlabBlocks, current_from_potential, mean_field  # noqa: F401
+from .spacetime import SpaceTimeSystem, gmres, solve_fgmres  # noqa: F401
+from .nonlinear import slab_residual, spacetime_residual  # noqa: F401
+
+
+def system_from_config(cfg, ubar=None, Abar=None, jbar=None):
+    """Build the oracle system of an input configuration (``inputs.Config``)."""
+    from paper_2309_00768_amd import inputs
+    if ubar is None or Abar is None:
+        ubar, Abar = inputs.state(cfg)
+    return SpaceTimeSystem(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ubar, Abar, jbar)
