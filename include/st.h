@@ -1,0 +1,187 @@
+/*
+ * st.h -- C ABI of libst: the all-at-once space-time solve of linearised
+ * incompressible resistive MHD, preconditioned by the block upper-triangular
+ * space-time preconditioner P_T of Danieli, Southworth & Schroder,
+ * "Space-time block preconditioning for incompressible resistive MHD"
+ * (arXiv:2309.00768).
+ *
+ * Problem (paper, Sec. "Problem definition and discretisation"): backward
+ * Euler in time with Nt slabs, Taylor-Hood Q2-Q1 velocity/pressure and Q1
+ * current/vector potential on a uniform n x n mesh of the unit square.  The
+ * space-time Jacobian J (eq. (jacobianSTDiscrete)) is block lower-bidiagonal
+ * in time; P_T (eq. (PT)) = Ubar_ujA * Utilde_up uses the pressure
+ * convection-diffusion Schur approximation (eq. (Fp)) and the wave-based
+ * magnetic Schur approximation C_A (eqs. (CAspacetime), (CAs),
+ * (ASchurApprox)).
+ *
+ * Vector layout (every vector argument): float64, device memory, slab-major,
+ * length N = Nt * Ns with, per slab, [u_x | u_y | p | j | A]:
+ *   u_x, u_y : (2n-1)^2 interior Q2 nodes each (homogeneous Dirichlet),
+ *   p, j     : (n+1)^2 Q1 nodes (all nodes),
+ *   A        : (n-1)^2 interior Q1 nodes (homogeneous Dirichlet);
+ * nodes numbered lexicographically, x fastest.
+ *
+ * Pressure: J has one constant-pressure null vector per slab.  Every entry
+ * point projects the pressure rows of its input to zero sum per slab and
+ * returns pressure normalised to zero mean, 1^T M_p p^k = 0.
+ *
+ * Ownership and threading: all vector memory belongs to the caller.  Device
+ * memory of a handle comes only from the caller's workspace `ws`.  A handle
+ * is not thread-safe; calls on one handle must be serialised (one stream at a
+ * time).  No C++ exception crosses this interface.
+ *
+ * Errors: every call returns an st_status; 0 is success.  st_error_string()
+ * gives a static description.
+ */
+#ifndef ST_H
+#define ST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum st_status {
+  ST_OK = 0,
+  ST_ENOTCONV = 1,      /* solver hit maxit; x holds the best iterate, info is filled */
+  ST_EINVAL = -1,       /* bad argument (null pointer, size, option) */
+  ST_EHIP = -2,         /* a HIP runtime call failed */
+  ST_ENOMEM = -3,       /* workspace smaller than st_plan_workspace_size() */
+  ST_EBREAKDOWN = -4,   /* NaN or Inf in a residual or in the Hessenberg matrix */
+  ST_EINTERNAL = -5     /* setup failed (e.g. singular coarse matrix) */
+} st_status;
+
+typedef enum st_precision { ST_FP64 = 0, ST_FP32 = 1 } st_precision;
+
+/* Inner solvers of P_T (the paper uses exact LU-based ones, Sec. "Performance
+ * of preconditioner"; here they are iterative):
+ *   ST_INNER_AMG   : one smoothed-aggregation V(1,1) cycle (Chebyshev-Jacobi
+ *                    smoothing) per spatial solve of F_u,k, C_A,k and K_p and a
+ *                    fixed Chebyshev-Jacobi polynomial for the mass matrices;
+ *   ST_INNER_EXACT : the same cycles repeated (inner_iters times) as a
+ *                    stationary iteration, so that every inner solve is
+ *                    converged to rounding level; P_T^{-1} then agrees with the
+ *                    exact-inner operator of the paper.                       */
+typedef enum st_inner_mode { ST_INNER_AMG = 0, ST_INNER_EXACT = 1 } st_inner_mode;
+
+typedef struct st_problem {
+  int n;              /* cells per side of the unit square (n >= 2)           */
+  int nt;             /* number of slabs (Nt >= 1)                            */
+  double dt;          /* time step                                            */
+  double mu;          /* viscosity (1/Re)                                     */
+  double eta;         /* resistivity (1/S)                                    */
+  double mu0;         /* magnetic permeability                                */
+  const double* ubar; /* host, [nt][2][(2n+1)^2]: Q2 nodal velocity state     */
+  const double* abar; /* host, [nt][(n+1)^2]: Q1 nodal vector-potential state */
+  const double* jbar; /* host, [nt][(n+1)^2] current state, or NULL: then the
+                         library solves M_j jbar = -(1/mu0) K abar per slab    */
+  int precond_precision; /* st_precision of everything inside P_T           */
+  int inner_mode;     /* st_inner_mode                                        */
+  int inner_iters;    /* V-cycles per spatial solve in EXACT mode (0: 40)      */
+  int mass_iters;     /* Chebyshev steps per mass-matrix solve (0: 12 AMG mode,
+                         60 EXACT mode)                                        */
+  int cheb_degree;    /* Chebyshev-Jacobi smoother degree (0: 3)              */
+  int fu_solver;      /* 0: AMG V-cycle on F_u,k; k>0: Chebyshev degree k only */
+  int ca_solver;      /* 0: AMG V-cycle on C_A,k; k>0: Chebyshev degree k only */
+  int max_restart;    /* largest FGMRES restart length the workspace holds (0: 30) */
+  int sell_sigma;     /* SELL sorting window in rows (0: whole matrix)        */
+  int adjoint;        /* 1: also build the transposed operators (J^T, P_T^{-T}) */
+  int reserved[7];
+} st_problem;
+
+typedef struct st_opts {
+  int restart;        /* m, <= max_restart (0: 30)                            */
+  int maxit;          /* total iteration cap (0: 1000)                        */
+  double rtol;        /* stop when ||b - J x||_2 <= max(rtol ||b||_2, atol)   */
+  double atol;
+  int x0_given;       /* 1: x holds the initial guess; 0: start from zero     */
+  int history_len;    /* capacity of `history` (may be 0)                     */
+  double* history;    /* host; estimated relative residual per iteration      */
+} st_opts;
+
+typedef struct st_info {
+  int iterations;     /* FGMRES iterations (preconditioner applications)      */
+  int restarts;
+  int converged;      /* 1 if the true residual met the tolerance             */
+  double true_rel_residual;  /* ||b - J x|| / ||b|| at exit (computed in FP64) */
+  double seconds;     /* wall time of the solve (host clock, after sync)      */
+  double precond_seconds;    /* time inside P_T^{-1} (event-timed)            */
+} st_info;
+
+typedef struct st_plan st_plan;       /* host-side setup result             */
+typedef struct st_handle st_handle;   /* device-resident system             */
+
+/* ---------------------------------------------------------------- setup --- */
+
+/* Host-only setup: assembles every block of J and P_T from the state, forms the
+ * wave operator blocks (eq. (CAs)), builds the AMG hierarchies and packs all
+ * device data into one image.  Makes no HIP call.  `p` and its arrays are only
+ * read during the call. */
+int st_plan_create(const st_problem* p, st_plan** out);
+
+/* Bytes of device workspace st_create() needs for this plan (256-aligned). */
+int st_plan_workspace_size(const st_plan* plan, size_t* bytes);
+
+/* Sizes of one slab: Ns and the block offsets [u_x, u_y, p, j, A, end]. */
+int st_plan_sizes(const st_plan* plan, int* ns, int offsets[6]);
+
+/* Debug/test export of one host-assembled block (CSR, float64) for slab k.
+ * block ids: 0 Fu, 1 Mu, 2 B, 3 Zj, 4 ZA, 5 Mj, 6 KjA, 7 Y, 8 FA, 9 MA, 10 KA,
+ * 11 Kp, 12 Fp, 13 C0 (diagonal band of C_A), 14 C1 (band -1, k < nt-1),
+ * 15 C2 (band -2).  Call with rowptr == NULL to get nrows, ncols, nnz first. */
+int st_plan_export_block(const st_plan* plan, int block, int k, int* nrows, int* ncols,
+                         int64_t* nnz, int* rowptr, int* colind, double* val);
+
+/* The current state used (either given or computed), host [nt][(n+1)^2]. */
+int st_plan_export_jbar(const st_plan* plan, double* jbar);
+
+int st_plan_destroy(st_plan* plan);
+
+/* Uploads the plan into the caller's device workspace `ws` (>= workspace size
+ * bytes, 256-byte aligned) on `stream` and returns a handle.  The plan may be
+ * destroyed afterwards.  `stream` is a hipStream_t (NULL = default stream). */
+int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_handle** out);
+
+/* Releases host-side state only; `ws` stays owned by the caller. */
+int st_destroy(st_handle* h);
+
+/* ---------------------------------------------------------- operators --- */
+
+/* y = J x (eq. (jacobianSTDiscrete)); x, y device, length N, must not alias.
+ * Asynchronous on `stream`. */
+int st_apply_jacobian(st_handle* h, const double* x, double* y, void* stream);
+
+/* y = J^T x (block upper-bidiagonal in time). */
+int st_apply_jacobian_t(st_handle* h, const double* x, double* y, void* stream);
+
+/* z = P_T^{-1} r (eq. (PT)); internal precision per the problem; FP64 in/out.
+ * r and z device, length N, must not alias.  Asynchronous on `stream`. */
+int st_apply_precond(st_handle* h, const double* r, double* z, void* stream);
+
+/* z = P_T^{-T} r: the transposed preconditioner (backward-in-time sweeps). */
+int st_apply_precond_t(st_handle* h, const double* r, double* z, void* stream);
+
+/* ------------------------------------------------------------- solves --- */
+
+/* Right-preconditioned FGMRES(m) on J x = b with P_T; residual, Arnoldi (CGS2)
+ * and the Hessenberg least-squares problem in FP64 on the device.  Blocks until
+ * done.  Returns ST_OK, ST_ENOTCONV (x = last iterate) or an error. */
+int st_fgmres_solve(st_handle* h, const double* b, double* x, const st_opts* o,
+                    st_info* info, void* stream);
+
+/* Adjoint solve J^T lam = g with FGMRES right-preconditioned by P_T^{-T}. */
+int st_adjoint_solve(st_handle* h, const double* g, double* lam, const st_opts* o,
+                     st_info* info, void* stream);
+
+/* Sizes of a created system: N, Ns, Nt. */
+int st_sizes(const st_handle* h, int64_t* n_total, int* ns, int* nt);
+
+const char* st_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ST_H */

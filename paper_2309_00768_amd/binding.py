@@ -1,0 +1,251 @@
+"""ctypes binding of libst (argument marshalling only; every step runs in the library).
+
+The library is ``paper_2309_00768_amd/libst.so`` (built by ``build.py``).  PyTorch
+supplies device memory (the workspace and all vectors) and streams.  Importing
+this module raises ``RuntimeError`` if the library is missing: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libst.so")
+
+ST_OK, ST_ENOTCONV = 0, 1
+ST_FP64, ST_FP32 = 0, 1
+ST_INNER_AMG, ST_INNER_EXACT = 0, 1
+
+BLOCK_IDS = {"Fu": 0, "Mu": 1, "B": 2, "Zj": 3, "ZA": 4, "Mj": 5, "KjA": 6, "Y": 7, "FA": 8,
+             "MA": 9, "KA": 10, "Kp": 11, "Fp": 12, "C0": 13, "C1": 14, "C2": 15}
+
+
+class StProblem(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int), ("nt", ctypes.c_int),
+        ("dt", ctypes.c_double), ("mu", ctypes.c_double), ("eta", ctypes.c_double), ("mu0", ctypes.c_double),
+        ("ubar", ctypes.POINTER(ctypes.c_double)), ("abar", ctypes.POINTER(ctypes.c_double)),
+        ("jbar", ctypes.POINTER(ctypes.c_double)),
+        ("precond_precision", ctypes.c_int), ("inner_mode", ctypes.c_int), ("inner_iters", ctypes.c_int),
+        ("mass_iters", ctypes.c_int), ("cheb_degree", ctypes.c_int), ("fu_solver", ctypes.c_int),
+        ("ca_solver", ctypes.c_int), ("max_restart", ctypes.c_int), ("sell_sigma", ctypes.c_int),
+        ("adjoint", ctypes.c_int), ("reserved", ctypes.c_int * 7),
+    ]
+
+
+class StOpts(ctypes.Structure):
+    _fields_ = [
+        ("restart", ctypes.c_int), ("maxit", ctypes.c_int), ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
+        ("x0_given", ctypes.c_int), ("history_len", ctypes.c_int), ("history", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class StInfo(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
+        ("true_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double), ("precond_seconds", ctypes.c_double),
+    ]
+
+
+EXPORTED = [
+    "st_plan_create", "st_plan_workspace_size", "st_plan_sizes", "st_plan_export_block", "st_plan_export_jbar",
+    "st_plan_destroy", "st_create", "st_destroy", "st_apply_jacobian", "st_apply_jacobian_t",
+    "st_apply_precond", "st_apply_precond_t", "st_fgmres_solve", "st_adjoint_solve", "st_sizes",
+    "st_error_string",
+]
+
+
+def _load(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise RuntimeError(f"libst not built: {path} is missing (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
+    ip = ctypes.POINTER(ctypes.c_int)
+    dp = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "st_plan_create": ([ctypes.POINTER(StProblem), ctypes.POINTER(vp)], ctypes.c_int),
+        "st_plan_workspace_size": ([vp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "st_plan_sizes": ([vp, ip, ip], ctypes.c_int),
+        "st_plan_export_block": ([vp, ctypes.c_int, ctypes.c_int, ip, ip, i64p, ip, ip, dp], ctypes.c_int),
+        "st_plan_export_jbar": ([vp, dp], ctypes.c_int),
+        "st_plan_destroy": ([vp], ctypes.c_int),
+        "st_create": ([vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "st_destroy": ([vp], ctypes.c_int),
+        "st_apply_jacobian": ([vp, vp, vp, vp], ctypes.c_int),
+        "st_apply_jacobian_t": ([vp, vp, vp, vp], ctypes.c_int),
+        "st_apply_precond": ([vp, vp, vp, vp], ctypes.c_int),
+        "st_apply_precond_t": ([vp, vp, vp, vp], ctypes.c_int),
+        "st_fgmres_solve": ([vp, vp, vp, ctypes.POINTER(StOpts), ctypes.POINTER(StInfo), vp], ctypes.c_int),
+        "st_adjoint_solve": ([vp, vp, vp, ctypes.POINTER(StOpts), ctypes.POINTER(StInfo), vp], ctypes.c_int),
+        "st_sizes": ([vp, i64p, ip, ip], ctypes.c_int),
+        "st_error_string": ([ctypes.c_int], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        _LIB = _load()
+    return _LIB
+
+
+class StError(RuntimeError):
+    def __init__(self, code, what):
+        msg = lib().st_error_string(code).decode()
+        super().__init__(f"{what}: {msg} (status {code})")
+        self.code = code
+
+
+def _check(code, what):
+    if code < 0:
+        raise StError(code, what)
+    return code
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Plan:
+    """Host-side setup of one space-time system (``st_plan_create``)."""
+
+    def __init__(self, n, nt, dt, mu, eta, mu0, ubar, abar, jbar=None, precision="fp64", inner="amg",
+                 inner_iters=0, mass_iters=0, cheb_degree=0, max_restart=0, sell_sigma=0, adjoint=False):
+        self._ub = np.ascontiguousarray(ubar, dtype=np.float64)
+        self._ab = np.ascontiguousarray(abar, dtype=np.float64)
+        assert self._ub.shape == (nt, 2, (2 * n + 1) ** 2) and self._ab.shape == (nt, (n + 1) ** 2)
+        self._jb = None if jbar is None else np.ascontiguousarray(jbar, dtype=np.float64)
+        p = StProblem()
+        p.n, p.nt, p.dt, p.mu, p.eta, p.mu0 = n, nt, dt, mu, eta, mu0
+        p.ubar, p.abar = _dptr(self._ub), _dptr(self._ab)
+        p.jbar = _dptr(self._jb) if self._jb is not None else ctypes.POINTER(ctypes.c_double)()
+        p.precond_precision = ST_FP32 if precision == "fp32" else ST_FP64
+        p.inner_mode = ST_INNER_EXACT if inner == "exact" else ST_INNER_AMG
+        p.inner_iters, p.mass_iters, p.cheb_degree = inner_iters, mass_iters, cheb_degree
+        p.max_restart, p.sell_sigma, p.adjoint = max_restart, sell_sigma, int(adjoint)
+        self.problem = p
+        self.n, self.nt = n, nt
+        h = ctypes.c_void_p()
+        _check(lib().st_plan_create(ctypes.byref(p), ctypes.byref(h)), "st_plan_create")
+        self.ptr = h
+        ns = ctypes.c_int()
+        offs = (ctypes.c_int * 6)()
+        _check(lib().st_plan_sizes(self.ptr, ctypes.byref(ns), offs), "st_plan_sizes")
+        self.ns = ns.value
+        self.offsets = list(offs)
+        wb = ctypes.c_size_t()
+        _check(lib().st_plan_workspace_size(self.ptr, ctypes.byref(wb)), "st_plan_workspace_size")
+        self.workspace_bytes = wb.value
+
+    def export_block(self, name, k=0):
+        """CSR (scipy) of a host-assembled block for slab k."""
+        import scipy.sparse as sp
+        bid = BLOCK_IDS[name]
+        nr, nc, nnz = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+        ip = ctypes.POINTER(ctypes.c_int)
+        _check(lib().st_plan_export_block(self.ptr, bid, k, ctypes.byref(nr), ctypes.byref(nc), ctypes.byref(nnz),
+                                          ip(), ip(), ctypes.POINTER(ctypes.c_double)()), "export")
+        rp = np.empty(nr.value + 1, dtype=np.int32)
+        ci = np.empty(nnz.value, dtype=np.int32)
+        v = np.empty(nnz.value, dtype=np.float64)
+        _check(lib().st_plan_export_block(self.ptr, bid, k, ctypes.byref(nr), ctypes.byref(nc), ctypes.byref(nnz),
+                                          rp.ctypes.data_as(ip), ci.ctypes.data_as(ip), _dptr(v)), "export")
+        return sp.csr_matrix((v, ci, rp), shape=(nr.value, nc.value))
+
+    def export_jbar(self):
+        out = np.empty((self.nt, (self.n + 1) ** 2))
+        _check(lib().st_plan_export_jbar(self.ptr, _dptr(out)), "export_jbar")
+        return out
+
+    def close(self):
+        if self.ptr:
+            lib().st_plan_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class System:
+    """A device-resident space-time system (``st_create``) with torch-owned memory."""
+
+    def __init__(self, plan: Plan, device="cuda:0", stream=None):
+        import torch
+        self.device = torch.device(device)
+        self.ws = torch.empty(plan.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        h = ctypes.c_void_p()
+        _check(lib().st_create(plan.ptr, ctypes.c_void_p(self._ws_ptr), ctypes.c_size_t(plan.workspace_bytes),
+                               _stream_ptr(stream), ctypes.byref(h)), "st_create")
+        self.ptr = h
+        self.ns, self.nt, self.n = plan.ns, plan.nt, plan.n
+        self.N = self.ns * self.nt
+        self.offsets = plan.offsets
+
+    def _vec(self, t):
+        import torch
+        assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous() and t.numel() == self.N
+        return ctypes.c_void_p(t.data_ptr())
+
+    def apply_jacobian(self, x, y=None, transpose=False, stream=None):
+        import torch
+        y = torch.empty_like(x) if y is None else y
+        fn = lib().st_apply_jacobian_t if transpose else lib().st_apply_jacobian
+        _check(fn(self.ptr, self._vec(x), self._vec(y), _stream_ptr(stream)), "st_apply_jacobian")
+        return y
+
+    def apply_precond(self, r, z=None, transpose=False, stream=None):
+        import torch
+        z = torch.empty_like(r) if z is None else z
+        fn = lib().st_apply_precond_t if transpose else lib().st_apply_precond
+        _check(fn(self.ptr, self._vec(r), self._vec(z), _stream_ptr(stream)), "st_apply_precond")
+        return z
+
+    def solve(self, b, x=None, restart=30, rtol=1e-8, atol=0.0, maxit=1000, x0=False, history=0,
+              adjoint=False, stream=None):
+        """FGMRES on J x = b (or the adjoint J^T x = b).  Returns (x, info, status, history)."""
+        import torch
+        x = torch.zeros_like(b) if x is None else x
+        o = StOpts()
+        o.restart, o.maxit, o.rtol, o.atol, o.x0_given = restart, maxit, rtol, atol, int(x0)
+        hist = np.zeros(max(history, 0))
+        o.history_len = hist.size
+        o.history = _dptr(hist) if hist.size else ctypes.POINTER(ctypes.c_double)()
+        info = StInfo()
+        fn = lib().st_adjoint_solve if adjoint else lib().st_fgmres_solve
+        rc = _check(fn(self.ptr, self._vec(b), self._vec(x), ctypes.byref(o), ctypes.byref(info),
+                       _stream_ptr(stream)), "solve")
+        return x, info, rc, hist[:min(info.iterations + 1, hist.size)]
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().st_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

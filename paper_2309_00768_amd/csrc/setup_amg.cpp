@@ -1,0 +1,302 @@
+// Host setup of the smoothed-aggregation AMG hierarchies for the spatial blocks
+// of P_T (F_u,k, the wave blocks C_A,k, and the pressure Laplacian K_p) and the
+// SELL-C-sigma packer that lays matrices out for the device.
+//
+// Aggregation is geometric: the blocks live on structured node grids, so
+// aggregates are 3 x 3 node blocks per vector component (boundary remainders
+// join the last aggregate of their row/column).  The tentative prolongator is
+// the aggregate indicator (it preserves constants per component); it is
+// smoothed once with damped Jacobi on a reference operator (value set 0,
+// inter-component couplings dropped) to give P; R = P^T and A_c = R A P per
+// value set (per slab for the state-dependent blocks).  The coarsest level is
+// inverted densely.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "st_internal.h"
+
+namespace st {
+
+namespace {
+
+constexpr int kCoarseMax = 160;
+
+Csr set_of(const Csr& a, int s) {
+  Csr c;
+  c.nr = a.nr;
+  c.nc = a.nc;
+  c.rp = a.rp;
+  c.ci = a.ci;
+  const int64_t z = a.nnz();
+  c.v.assign(a.v.begin() + size_t(s) * z, a.v.begin() + size_t(s + 1) * z);
+  return c;
+}
+
+std::vector<double> diag_of(const Csr& a, int s) {
+  std::vector<double> d(a.nr, 0.0);
+  const int64_t z = a.nnz();
+  for (int r = 0; r < a.nr; ++r) {
+    const int64_t p = a.find(r, r);
+    if (p >= 0) d[r] = a.v[size_t(s) * z + p];
+  }
+  return d;
+}
+
+// Largest |eigenvalue| of D^{-1} A (value set s) by power iteration.
+double lambda_max(const Csr& a, int s, const std::vector<double>& dinv) {
+  const int n = a.nr;
+  std::vector<double> x(n), y(n);
+  for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.37 * std::sin(1.7 * i + 0.3);   // deterministic start
+  const int64_t z = a.nnz();
+  const double* v = a.v.data() + size_t(s) * z;
+  double lam = 0.0;
+  for (int it = 0; it < 30; ++it) {
+    double nx = 0;
+    for (double t : x) nx += t * t;
+    nx = std::sqrt(nx);
+    for (auto& t : x) t /= nx;
+    double ny = 0;
+    for (int r = 0; r < n; ++r) {
+      double acc = 0;
+      for (int p = a.rp[r]; p < a.rp[r + 1]; ++p) acc += v[p] * x[a.ci[p]];
+      y[r] = acc * dinv[r];
+      ny += y[r] * y[r];
+    }
+    lam = std::sqrt(ny);
+    std::swap(x, y);
+  }
+  return lam;
+}
+
+// Dense inverse by Gauss-Jordan with partial pivoting; returns false if singular.
+bool dense_inverse(std::vector<double>& a, int n) {
+  std::vector<double> inv(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[size_t(i) * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(a[size_t(r) * n + c]) > std::fabs(a[size_t(piv) * n + c])) piv = r;
+    if (a[size_t(piv) * n + c] == 0.0) return false;
+    if (piv != c)
+      for (int j = 0; j < n; ++j) {
+        std::swap(a[size_t(c) * n + j], a[size_t(piv) * n + j]);
+        std::swap(inv[size_t(c) * n + j], inv[size_t(piv) * n + j]);
+      }
+    const double d = 1.0 / a[size_t(c) * n + c];
+    for (int j = 0; j < n; ++j) {
+      a[size_t(c) * n + j] *= d;
+      inv[size_t(c) * n + j] *= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = a[size_t(r) * n + c];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        a[size_t(r) * n + j] -= f * a[size_t(c) * n + j];
+        inv[size_t(r) * n + j] -= f * inv[size_t(c) * n + j];
+      }
+    }
+  }
+  a.swap(inv);
+  return true;
+}
+
+template <class T>
+Span put_converted(Image& img, const std::vector<double>& v, int fp32) {
+  if (fp32) {
+    std::vector<float> f(v.begin(), v.end());
+    return img.put(f);
+  }
+  return img.put(v);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- SELL ---
+SellGroup pack_sell(Image& img, const std::vector<const Csr*>& mats, int fp32, int sigma) {
+  SellGroup g;
+  g.nseg = int(mats.size());
+  g.nrows = mats[0]->nr;
+  g.ncols = mats[0]->nc;
+  g.fp32 = fp32;
+  const int nr = g.nrows;
+  g.nslices = (nr + kSlice - 1) / kSlice;
+  // Row order: descending total row length inside windows of `sigma` rows.
+  std::vector<int> total(nr, 0);
+  for (const Csr* m : mats)
+    for (int r = 0; r < nr; ++r) total[r] += m->rp[r + 1] - m->rp[r];
+  std::vector<int> order(nr);
+  std::iota(order.begin(), order.end(), 0);
+  const int win = sigma <= 0 ? nr : sigma;
+  for (int b = 0; b < nr; b += win) {
+    const int e = std::min(nr, b + win);
+    std::stable_sort(order.begin() + b, order.begin() + e, [&](int x, int y) { return total[x] > total[y]; });
+  }
+  std::vector<int> perm(size_t(g.nslices) * kSlice, -1);
+  for (int i = 0; i < nr; ++i) perm[i] = order[i];
+  g.perm = img.put(perm);
+  for (int si = 0; si < g.nseg; ++si) {
+    const Csr& m = *mats[si];
+    SellSeg& s = g.seg[si];
+    const int64_t z = m.nnz();
+    s.nsets = z ? int(m.v.size() / z) : 1;
+    if (s.nsets < 1) s.nsets = 1;
+    std::vector<int> sptr(g.nslices + 1, 0);
+    for (int sl = 0; sl < g.nslices; ++sl) {
+      int w = 0;
+      for (int l = 0; l < kSlice; ++l) {
+        const int r = perm[size_t(sl) * kSlice + l];
+        if (r >= 0) w = std::max(w, m.rp[r + 1] - m.rp[r]);
+      }
+      sptr[sl + 1] = sptr[sl] + w * kSlice;
+    }
+    s.total = sptr[g.nslices];
+    std::vector<int> col(s.total, 0);
+    std::vector<double> val(size_t(s.nsets) * s.total, 0.0);
+    for (int sl = 0; sl < g.nslices; ++sl)
+      for (int l = 0; l < kSlice; ++l) {
+        const int r = perm[size_t(sl) * kSlice + l];
+        if (r < 0) continue;
+        int j = 0;
+        for (int p = m.rp[r]; p < m.rp[r + 1]; ++p, ++j) {
+          const int64_t q = sptr[sl] + int64_t(j) * kSlice + l;
+          col[q] = m.ci[p];
+          for (int st = 0; st < s.nsets; ++st) val[size_t(st) * s.total + q] = m.v[size_t(st) * z + p];
+        }
+      }
+    s.sptr = img.put(sptr);
+    s.col = img.put(col);
+    s.val = fp32 ? put_converted<float>(img, val, 1) : img.put(val);
+  }
+  return g;
+}
+
+// ----------------------------------------------------------------- AMG ---
+int build_amg(Image& img, const Csr& a0, int nsets, Grid2 grid, int fp32, int cheb_degree,
+              int sigma, bool singular, Amg& out, std::string& err) {
+  out = Amg();
+  out.nsets = nsets;
+  out.fp32 = fp32;
+  out.cheb_degree = cheb_degree;
+  out.singular = singular ? 1 : 0;
+  Csr A = a0;   // current level, nsets value sets
+  Grid2 g = grid;
+  const int threads = host_threads();
+  for (int level = 0;; ++level) {
+    const int n = A.nr;
+    AmgLevel L;
+    L.nrows = n;
+    const int64_t z = A.nnz();
+    // Jacobi diagonals and Chebyshev intervals per value set.
+    std::vector<double> dinv(size_t(nsets) * n), cheb(size_t(nsets) * 2);
+    parallel_for(nsets, threads, [&](int s) {
+      std::vector<double> d = diag_of(A, s);
+      std::vector<double> di(n);
+      for (int i = 0; i < n; ++i) di[i] = d[i] != 0.0 ? 1.0 / d[i] : 0.0;
+      std::copy(di.begin(), di.end(), dinv.begin() + size_t(s) * n);
+      const double lm = lambda_max(A, s, di);
+      const double hi = 1.1 * lm, lo = hi / 10.0;
+      cheb[2 * s] = 0.5 * (hi + lo);
+      cheb[2 * s + 1] = 0.5 * (hi - lo);
+    });
+    L.A = pack_sell(img, {&A}, fp32, sigma);
+    L.dinv = fp32 ? put_converted<float>(img, dinv, 1) : img.put(dinv);
+    L.cheb = img.put(cheb);
+    const int ax = std::max(1, g.gx / 3), ay = std::max(1, g.gy / 3);
+    const int nagg = ax * ay * g.ncomp;
+    const bool last = n <= kCoarseMax || nagg >= n || (ax == 1 && ay == 1);
+    if (last) {
+      out.lev.push_back(L);
+      out.ncoarse = n;
+      std::vector<double> inv(size_t(nsets) * n * n);
+      bool ok = true;
+      parallel_for(nsets, threads, [&](int s) {
+        std::vector<double> dense(size_t(n) * n, 0.0);
+        for (int r = 0; r < n; ++r)
+          for (int p = A.rp[r]; p < A.rp[r + 1]; ++p) dense[size_t(r) * n + A.ci[p]] = A.v[size_t(s) * z + p];
+        if (singular) {   // constant null vector: invert A + alpha 1 1^T
+          double md = 0;
+          for (int r = 0; r < n; ++r) md += dense[size_t(r) * n + r];
+          const double alpha = md / n / n;
+          for (auto& x : dense) x += alpha;
+        }
+        if (!dense_inverse(dense, n)) ok = false;
+        // stored column-major: inv[s][j][i] = Ainv(i, j) (coalesced reads on the device)
+        for (int i = 0; i < n; ++i)
+          for (int j = 0; j < n; ++j) inv[size_t(s) * n * n + size_t(j) * n + i] = dense[size_t(i) * n + j];
+      });
+      if (!ok) {
+        err = "singular coarsest AMG matrix";
+        return ST_EINTERNAL;
+      }
+      out.coarse_inv = fp32 ? put_converted<float>(img, inv, 1) : img.put(inv);
+      break;
+    }
+    // Aggregates: 3x3 node blocks per component.
+    std::vector<int> agg(n);
+    for (int c = 0; c < g.ncomp; ++c)
+      for (int j = 0; j < g.gy; ++j)
+        for (int i = 0; i < g.gx; ++i) {
+          const int node = c * g.gx * g.gy + j * g.gx + i;
+          agg[node] = c * ax * ay + std::min(j / 3, ay - 1) * ax + std::min(i / 3, ax - 1);
+        }
+    // Reference operator: value set 0 with inter-component entries dropped.
+    const int per = g.gx * g.gy;
+    std::vector<double> dref(n, 0.0);
+    Csr Aref;
+    Aref.nr = n;
+    Aref.nc = n;
+    Aref.rp.assign(n + 1, 0);
+    for (int r = 0; r < n; ++r) {
+      for (int p = A.rp[r]; p < A.rp[r + 1]; ++p)
+        if (A.ci[p] / per == r / per) {
+          Aref.ci.push_back(A.ci[p]);
+          Aref.v.push_back(A.v[p]);
+          if (A.ci[p] == r) dref[r] = A.v[p];
+        }
+      Aref.rp[r + 1] = int(Aref.ci.size());
+    }
+    std::vector<double> drefinv(n);
+    for (int i = 0; i < n; ++i) drefinv[i] = dref[i] != 0.0 ? 1.0 / dref[i] : 0.0;
+    const double omega = 4.0 / (3.0 * lambda_max(Aref, 0, drefinv));
+    // P = (I - omega D^{-1} Aref) P_tent
+    Csr Pt;
+    Pt.nr = n;
+    Pt.nc = nagg;
+    Pt.rp.resize(n + 1);
+    Pt.ci.resize(n);
+    Pt.v.assign(n, 1.0);
+    for (int i = 0; i <= n; ++i) Pt.rp[i] = i;
+    for (int i = 0; i < n; ++i) Pt.ci[i] = agg[i];
+    Csr DA = Aref;
+    for (int r = 0; r < n; ++r)
+      for (int p = DA.rp[r]; p < DA.rp[r + 1]; ++p) DA.v[p] *= omega * drefinv[r];
+    Csr P = csr_add(Pt, 1.0, csr_matmul(DA, Pt), -1.0);
+    Csr R = csr_transpose(P);
+    L.P = pack_sell(img, {&P}, fp32, sigma);
+    L.R = pack_sell(img, {&R}, fp32, sigma);
+    out.lev.push_back(L);
+    // Galerkin coarse operators per value set on a common pattern.
+    std::vector<Csr> coarse(nsets);
+    parallel_for(nsets, threads, [&](int s) {
+      Csr As = set_of(A, s);
+      coarse[s] = csr_matmul(R, csr_matmul(As, P));
+    });
+    Csr Ac = coarse[0];
+    const int64_t zc = Ac.nnz();
+    Ac.v.resize(size_t(nsets) * zc);
+    for (int s = 1; s < nsets; ++s) {
+      if (coarse[s].rp != coarse[0].rp || coarse[s].ci != coarse[0].ci) {
+        err = "coarse pattern differs between value sets";
+        return ST_EINTERNAL;
+      }
+      std::copy(coarse[s].v.begin(), coarse[s].v.end(), Ac.v.begin() + size_t(s) * zc);
+    }
+    A = std::move(Ac);
+    g = Grid2{ax, ay, g.ncomp};
+  }
+  return ST_OK;
+}
+
+}  // namespace st

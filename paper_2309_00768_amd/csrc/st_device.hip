@@ -1,0 +1,911 @@
+// Device side of libst: st_create, the space-time operator applies, the
+// preconditioner P_T^{-1} (and its transpose) and FGMRES, all on one HIP stream.
+//
+// Paper references: J = eq. (jacobianSTDiscrete); P_T = Ubar_ujA Utilde_up,
+// eq. (PT), with Ubar_ujA from eq. (barUuja), Utilde_up from eq. (Utilde), the
+// PCD operator of eq. (Fp) and the magnetic Schur approximation
+// S_A^{-1} ~ C_A^{-1} F_A M_A^{-1} of eq. (ASchurApprox); GMRES on J with right
+// preconditioning (Sec. "Performance of preconditioner").
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <new>
+#include <vector>
+
+#include "kernels.h"
+#include "st_internal.h"
+
+struct st_plan {
+  st::Plan p;
+};
+
+namespace st {
+
+// ------------------------------------------------------ device mirrors ---
+struct DGroup {
+  const int* perm = nullptr;
+  int nrows = 0, nslices = 0, nseg = 0;
+  const int* sptr[3] = {nullptr, nullptr, nullptr};
+  const int* col[3] = {nullptr, nullptr, nullptr};
+  const void* val[3] = {nullptr, nullptr, nullptr};
+  int64_t vstride[3] = {0, 0, 0};
+};
+
+struct DLevel {
+  int n = 0;
+  DGroup A, P, R;
+  const void* dinv = nullptr;
+  const double* cheb = nullptr;
+};
+
+struct DAmg {
+  std::vector<DLevel> lev;
+  int nsets = 1, deg = 3, ncoarse = 0;
+  const void* cinv = nullptr;
+  // scratch: 6 vectors per level (x, b, r, d0, d1, e)
+  std::vector<void*> buf;
+};
+
+struct Handle {
+  Plan* plan_copy = nullptr;   // scalars only (no big host arrays kept)
+  Dims d;
+  double dt = 0;
+  int fp32 = 0, exact = 0, inner_iters = 1, mass_iters = 12, max_restart = 30, adjoint = 0;
+  char* base = nullptr;
+  WsLayout L;
+  DGroup J, JT, MA, Mj, Mp, FA, FAt, Fp, Fpt, KjA, KjAt, Bt, B, Zj, Zjt, ZAt, Mu, C1, C1t;
+  const void *dMA = nullptr, *dMj = nullptr, *dMp = nullptr;
+  const double* mp_rowsum = nullptr;
+  double msum = 1.0;              // 1^T M_p 1 (the area)
+  DAmg amgFu, amgC0, amgKp, amgFuT, amgC0T;
+  double* host_small = nullptr;   // pinned
+  double precond_ms = 0.0;
+};
+
+}  // namespace st
+
+struct st_handle {
+  st::Handle h;
+};
+
+namespace st {
+namespace {
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      std::fprintf(stderr, "libst: %s failed: %s\n", #expr, hipGetErrorString(e_));    \
+      return ST_EHIP;                                                                  \
+    }                                                                                  \
+  } while (0)
+
+template <class T>
+T* at(char* base, size_t off) {
+  return reinterpret_cast<T*>(base + off);
+}
+
+DGroup mirror(char* base, const SellGroup& g) {
+  DGroup d;
+  d.nrows = g.nrows;
+  d.nslices = g.nslices;
+  d.nseg = g.nseg;
+  if (!g.nrows) return d;
+  d.perm = at<int>(base, g.perm.off);
+  for (int s = 0; s < g.nseg; ++s) {
+    d.sptr[s] = at<int>(base, g.seg[s].sptr.off);
+    d.col[s] = at<int>(base, g.seg[s].col.off);
+    d.val[s] = base + g.seg[s].val.off;
+    d.vstride[s] = g.seg[s].nsets > 1 ? g.seg[s].total : 0;
+  }
+  return d;
+}
+
+DAmg mirror_amg(char* base, const Amg& a, const std::vector<size_t>& bufs) {
+  DAmg d;
+  d.nsets = a.nsets;
+  d.deg = a.cheb_degree;
+  d.ncoarse = a.ncoarse;
+  d.cinv = base + a.coarse_inv.off;
+  for (const AmgLevel& l : a.lev) {
+    DLevel dl;
+    dl.n = l.nrows;
+    dl.A = mirror(base, l.A);
+    dl.P = mirror(base, l.P);
+    dl.R = mirror(base, l.R);
+    dl.dinv = base + l.dinv.off;
+    dl.cheb = at<double>(base, l.cheb.off);
+    d.lev.push_back(dl);
+  }
+  for (size_t o : bufs) d.buf.push_back(base + o);
+  return d;
+}
+
+// ---------------------------------------------------------- launchers ---
+template <class T>
+Seg<T> seg(const DGroup& g, int s, int set_base, int set_step, const void* x, int64_t xstride, int xshift,
+           int vlo, int vhi, double alpha) {
+  Seg<T> r;
+  r.sptr = g.sptr[s];
+  r.col = g.col[s];
+  r.val = static_cast<const T*>(g.val[s]);
+  r.vstride = g.vstride[s];
+  r.set_base = set_base;
+  r.set_step = set_step;
+  r.x = x;
+  r.xstride = xstride;
+  r.xshift = xshift;
+  r.vlo = vlo;
+  r.vhi = vhi;
+  r.alpha = alpha;
+  return r;
+}
+
+template <class T, class TX>
+void spmv(hipStream_t s, const DGroup& g, int nvec, int nseg, const Seg<T>* segs, const TX* b, int64_t bstride,
+          double beta, TX* y, int64_t ystride) {
+  SpmvArgs<T, TX> a;
+  a.perm = g.perm;
+  a.nslices = g.nslices;
+  a.nseg = nseg;
+  for (int i = 0; i < nseg; ++i) a.seg[i] = segs[i];
+  a.b = b;
+  a.bstride = bstride;
+  a.beta = beta;
+  a.y = y;
+  a.ystride = ystride;
+  dim3 grid((g.nslices + 3) / 4, nvec);
+  using TA = T;
+  hipLaunchKernelGGL((k_spmv<T, TX, TA>), grid, dim3(kBlock), 0, s, a);
+}
+
+// y = alpha A x + beta b for a one-segment group, nvec vectors of length n.
+template <class T>
+void spmv1(hipStream_t s, const DGroup& g, int nvec, int set_base, int set_step, const T* x, int64_t xstride,
+           double alpha, const T* b, double beta, T* y, int64_t ystride) {
+  Seg<T> sg = seg<T>(g, 0, set_base, set_step, x, xstride, 0, 0, nvec, alpha);
+  spmv<T, T>(s, g, nvec, 1, &sg, b, ystride, beta, y, ystride);
+}
+
+template <class T>
+void cheb_launch(hipStream_t s, const DGroup& A, int nvec, int set_base, int set_step, const T* dinv,
+                 int64_t dstride, const double* cheb, double theta, double delta, const T* b, T* r, T* x,
+                 const T* dold, T* dnew, int64_t vec, int mode, int step, int x_add) {
+  ChebArgs<T> a;
+  a.perm = A.perm;
+  a.nslices = A.nslices;
+  a.sptr = A.sptr[0];
+  a.col = A.col[0];
+  a.val = static_cast<const T*>(A.val[0]);
+  a.vstride = A.vstride[0];
+  a.set_base = set_base;
+  a.set_step = set_step;
+  a.dinv = dinv;
+  a.dstride = dstride;
+  a.cheb = cheb;
+  a.theta = theta;
+  a.delta = delta;
+  a.b = b;
+  a.r = r;
+  a.x = x;
+  a.dold = dold;
+  a.dnew = dnew;
+  a.vec = vec;
+  a.mode = mode;
+  a.step = step;
+  a.x_add = x_add;
+  dim3 grid((A.nslices + 3) / 4, nvec);
+  hipLaunchKernelGGL((k_cheb<T>), grid, dim3(kBlock), 0, s, a);
+}
+
+// Chebyshev-Jacobi polynomial solve of A x = b with `steps` steps from x = 0
+// (or x += correction when x_add), using caller scratch r, d0, d1.
+template <class T>
+void cheb_solve(hipStream_t s, const DGroup& A, int nvec, int set_base, int set_step, const T* dinv,
+                int64_t dstride, const double* cheb, double theta, double delta, const T* b, T* x, T* r, T* d0,
+                T* d1, int64_t vec, int steps, int x_add, bool final_residual) {
+  cheb_launch<T>(s, A, nvec, set_base, set_step, dinv, dstride, cheb, theta, delta, b, r, x, nullptr, d0, vec, 0, 0,
+                 x_add);
+  T* d[2] = {d0, d1};
+  for (int i = 1; i < steps; ++i)
+    cheb_launch<T>(s, A, nvec, set_base, set_step, dinv, dstride, cheb, theta, delta, nullptr, r, x, d[(i - 1) % 2],
+                   d[i % 2], vec, 1, i, 1);
+  if (final_residual)
+    cheb_launch<T>(s, A, nvec, set_base, set_step, dinv, dstride, cheb, theta, delta, nullptr, r, x,
+                   d[(steps - 1) % 2], d[steps % 2], vec, 2, 0, 1);
+}
+
+// ---------------------------------------------------------------- AMG ---
+// One V(1,1) cycle on level l for nvec vectors (value set set_base + v*set_step).
+// Level-0 vectors may be supplied by the caller (x0, b0); x_add: x holds a guess.
+template <class T>
+void vcycle(hipStream_t s, DAmg& a, int l, int nvec, int set_base, int set_step, T* x0, const T* b0, int x_add,
+            bool need_residual) {
+  DLevel& L = a.lev[l];
+  const int64_t vec = L.n;   // vectors of one level are stored back to back
+  T* x = (l == 0 && x0) ? x0 : static_cast<T*>(a.buf[6 * l + 0]);
+  const T* b = (l == 0 && b0) ? b0 : static_cast<const T*>(a.buf[6 * l + 1]);
+  T* r = static_cast<T*>(a.buf[6 * l + 2]);
+  T* d0 = static_cast<T*>(a.buf[6 * l + 3]);
+  T* d1 = static_cast<T*>(a.buf[6 * l + 4]);
+  const T* dinv = static_cast<const T*>(L.dinv);
+  const int64_t dstride = a.nsets > 1 ? L.n : 0;
+  const bool coarsest = (l + 1 == int(a.lev.size()));
+  if (coarsest) {
+    const T* rhs = b;
+    if (x_add) {   // x += Ainv (b - A x)
+      spmv1<T>(s, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec);
+      rhs = r;
+    }
+    const int64_t istride = a.nsets > 1 ? int64_t(a.ncoarse) * a.ncoarse : 0;
+    hipLaunchKernelGGL((k_coarse<T>), dim3(nvec), dim3(kBlock), 0, s, a.ncoarse, static_cast<const T*>(a.cinv),
+                       istride, set_base, set_step, rhs, x, vec, x_add);
+    if (need_residual) spmv1<T>(s, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec);
+    return;
+  }
+  const int deg = a.deg;
+  // pre-smoothing (leaves r = b - A x)
+  if (x_add) {
+    spmv1<T>(s, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec);
+    cheb_solve<T>(s, L.A, nvec, set_base, set_step, dinv, dstride, L.cheb, 0, 0, nullptr, x, r, d0, d1, vec, deg, 1,
+                  true);
+  } else {
+    cheb_solve<T>(s, L.A, nvec, set_base, set_step, dinv, dstride, L.cheb, 0, 0, b, x, r, d0, d1, vec, deg, 0, true);
+  }
+  // coarse-grid correction
+  DLevel& C = a.lev[l + 1];
+  const int64_t cvec = C.n;
+  T* cb = static_cast<T*>(a.buf[6 * (l + 1) + 1]);
+  T* cx = static_cast<T*>(a.buf[6 * (l + 1) + 0]);
+  spmv1<T>(s, L.R, nvec, 0, 0, r, vec, 1.0, nullptr, 0.0, cb, cvec);
+  vcycle<T>(s, a, l + 1, nvec, set_base, set_step, nullptr, nullptr, 0, false);
+  spmv1<T>(s, L.P, nvec, 0, 0, cx, cvec, 1.0, x, 1.0, x, vec);   // x += P x_c
+  // post-smoothing
+  spmv1<T>(s, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec);
+  cheb_solve<T>(s, L.A, nvec, set_base, set_step, dinv, dstride, L.cheb, 0, 0, nullptr, x, r, d0, d1, vec, deg, 1,
+                need_residual);
+}
+
+// Spatial solve A x = b with `iters` V-cycles (x starts from zero).
+template <class T>
+void amg_solve(hipStream_t s, DAmg& a, int nvec, int set_base, int set_step, T* x, const T* b, int iters) {
+  for (int it = 0; it < iters; ++it) vcycle<T>(s, a, 0, nvec, set_base, set_step, x, b, it > 0 ? 1 : 0, false);
+}
+
+// ------------------------------------------------- vector kernels (P_T) ---
+// Per-slab sums of src[k*ld + off + i], i < len (weights w[i] if w): out[k].
+__global__ __launch_bounds__(kBlock) void k_slab_sums_d(const double* src, int64_t ld, int off, int len,
+                                                        const double* w, double* out) {
+  const int k = blockIdx.x;
+  const double* p = src + int64_t(k) * ld + off;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < len; i += blockDim.x) acc += (w ? w[i] : 1.0) * p[i];
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) out[k] = acc;
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_slab_sums_t(const T* src, int64_t ld, int len, const double* w,
+                                                        double* out) {
+  const int k = blockIdx.x;
+  const T* p = src + int64_t(k) * ld;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < len; i += blockDim.x) acc += (w ? w[i] : 1.0) * double(p[i]);
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) out[k] = acc;
+}
+
+// Split an FP64 slab-major vector into per-block arrays (precision T); the
+// pressure rows lose their per-slab mean psum[k] / np.
+template <class T>
+__global__ void k_split(const double* r, int ns, int nt, int o2, int o3, int o4, const double* psum, T* ru,
+                        T* rp, T* rj, T* ra) {
+  const int64_t N = int64_t(ns) * nt;
+  const int np = o3 - o2, nj = o4 - o3, na = ns - o4;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+    const int k = int(i / ns), c = int(i % ns);
+    const double v = r[i];
+    if (c < o2) ru[int64_t(k) * o2 + c] = T(v);
+    else if (c < o3) rp[int64_t(k) * np + (c - o2)] = T(v - psum[k] / np);
+    else if (c < o4) rj[int64_t(k) * nj + (c - o3)] = T(v);
+    else ra[int64_t(k) * na + (c - o4)] = T(v);
+  }
+}
+
+// Join per-block arrays into an FP64 slab-major vector; pressure is
+// sign * xp shifted so that 1^T M_p p^k = 0 (wsum[k] = m . xp^k, msum = sum m).
+template <class T>
+__global__ void k_join(double* z, int ns, int nt, int o2, int o3, int o4, const T* xu, const T* xp, double psign,
+                       const double* wsum, double msum, const T* yj, const T* ya) {
+  const int64_t N = int64_t(ns) * nt;
+  const int np = o3 - o2, nj = o4 - o3, na = ns - o4;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+    const int k = int(i / ns), c = int(i % ns);
+    double v;
+    if (c < o2) v = double(xu[int64_t(k) * o2 + c]);
+    else if (c < o3) v = psign * (double(xp[int64_t(k) * np + (c - o2)]) - wsum[k] / msum);
+    else if (c < o4) v = double(yj[int64_t(k) * nj + (c - o3)]);
+    else v = double(ya[int64_t(k) * na + (c - o4)]);
+    z[i] = v;
+  }
+}
+
+// x[k*ld + i] -= sums[k] * scale (i < len)
+template <class T>
+__global__ void k_slab_shift(T* x, int64_t ld, int len, int nt, const double* sums, double scale) {
+  const int64_t N = int64_t(len) * nt;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+    const int k = int(i / len), c = int(i % len);
+    x[int64_t(k) * ld + c] = T(double(x[int64_t(k) * ld + c]) - sums[k] * scale);
+  }
+}
+
+// FP64 slab-major: p rows (offset o2..o3) minus psum[k]/np, written to dst.
+__global__ void k_project_p(const double* src, double* dst, int ns, int nt, int o2, int o3, const double* psum) {
+  const int64_t N = int64_t(ns) * nt;
+  const int np = o3 - o2;
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+    const int k = int(i / ns), c = int(i % ns);
+    double v = src[i];
+    if (c >= o2 && c < o3) v -= psum[k] / np;
+    dst[i] = v;
+  }
+}
+
+// ------------------------------------------------------ FGMRES kernels ---
+// partial[i * nb + blk] = sum over the block's rows of V_i . w   (i = blockIdx.y)
+__global__ __launch_bounds__(kBlock) void k_mdot_partial(const double* V, int64_t N, const double* w,
+                                                         double* partial) {
+  const int i = blockIdx.y;
+  const double* v = V + int64_t(i) * N;
+  double acc = 0.0;
+  for (int64_t r = blockIdx.x * int64_t(kBlock) + threadIdx.x; r < N; r += int64_t(gridDim.x) * kBlock)
+    acc += v[r] * w[r];
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partial[int64_t(i) * gridDim.x + blockIdx.x] = acc;
+}
+
+// out[i] (+)= sum_b partial[i * nb + b]; mode 1: out[0] = sqrt(sum), mode 2: add.
+__global__ __launch_bounds__(kBlock) void k_reduce(const double* partial, int nb, double* out, int mode,
+                                                   double* copy_to) {
+  const int i = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) acc += partial[int64_t(i) * nb + b];
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) {
+    if (mode == 1) acc = std::sqrt(acc);
+    if (mode == 2) out[i] += acc;
+    else out[i] = acc;
+    if (copy_to) copy_to[i] = out[i];
+  }
+}
+
+// w -= sum_{i < nv} h[i] V_i
+__global__ __launch_bounds__(kBlock) void k_mgs_update(double* w, const double* V, int64_t N, const double* h,
+                                                       int nv) {
+  for (int64_t r = blockIdx.x * int64_t(kBlock) + threadIdx.x; r < N; r += int64_t(gridDim.x) * kBlock) {
+    double acc = w[r];
+    for (int i = 0; i < nv; ++i) acc -= h[i] * V[int64_t(i) * N + r];
+    w[r] = acc;
+  }
+}
+
+// x += sum_i y[i] Z_i
+__global__ __launch_bounds__(kBlock) void k_update_x(double* x, const double* Z, int64_t N, const double* y, int nv) {
+  for (int64_t r = blockIdx.x * int64_t(kBlock) + threadIdx.x; r < N; r += int64_t(gridDim.x) * kBlock) {
+    double acc = x[r];
+    for (int i = 0; i < nv; ++i) acc += y[i] * Z[int64_t(i) * N + r];
+    x[r] = acc;
+  }
+}
+
+// dst = src / *nrm (zero if the norm is zero)
+__global__ __launch_bounds__(kBlock) void k_scale(double* dst, const double* src, int64_t N, const double* nrm) {
+  const double s = *nrm;
+  const double f = s != 0.0 ? 1.0 / s : 0.0;
+  for (int64_t r = blockIdx.x * int64_t(kBlock) + threadIdx.x; r < N; r += int64_t(gridDim.x) * kBlock)
+    dst[r] = src[r] * f;
+}
+
+// Givens update of Hessenberg column j; g, cs, sn in `sm`; est = |g[j+1]|.
+// Layout of sm: g[0..m], cs[m+1..], sn[...]
+__global__ void k_givens(double* Hcol, int j, int ldh, double* g, double* cs, double* sn, double* est) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double* h = Hcol + int64_t(j) * ldh;
+  for (int i = 0; i < j; ++i) {
+    const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+    h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+    h[i] = t;
+  }
+  const double a = h[j], b = h[j + 1];
+  const double d = std::hypot(a, b);
+  const double c = d != 0.0 ? a / d : 1.0, s = d != 0.0 ? b / d : 0.0;
+  cs[j] = c;
+  sn[j] = s;
+  h[j] = d;
+  h[j + 1] = 0.0;
+  g[j + 1] = -s * g[j];
+  g[j] = c * g[j];
+  est[0] = std::fabs(g[j + 1]);
+}
+
+// Back substitution of the rotated upper-triangular m x m system H y = g.
+__global__ void k_trisolve(const double* Hcol, int m, int ldh, const double* g, double* y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = m - 1; i >= 0; --i) {
+    double acc = g[i];
+    for (int l = i + 1; l < m; ++l) acc -= Hcol[int64_t(l) * ldh + i] * y[l];
+    y[i] = acc / Hcol[int64_t(i) * ldh + i];
+  }
+}
+
+__global__ void k_init_g(double* g, int m1, const double* beta) {
+  for (int i = threadIdx.x; i < m1; i += blockDim.x) g[i] = i == 0 ? *beta : 0.0;
+}
+
+inline int grid_for(int64_t n) {
+  int64_t b = (n + kBlock - 1) / kBlock;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return int(b);
+}
+
+// ================================================= P_T^{-1} (forward) ===
+template <class T>
+int precond_forward(Handle& H, const double* r, double* z, hipStream_t s) {
+  const Dims& d = H.d;
+  const int nt = d.nt;
+  char* B = H.base;
+  const WsLayout& L = H.L;
+  T* ru = at<T>(B, L.ru); T* yu = at<T>(B, L.yu); T* xu = at<T>(B, L.xu);
+  T* rp = at<T>(B, L.rp); T* q = at<T>(B, L.q); T* t = at<T>(B, L.t); T* xp = at<T>(B, L.xp);
+  T* rj = at<T>(B, L.rj); T* yj = at<T>(B, L.yj);
+  T* ra = at<T>(B, L.ra); T* w = at<T>(B, L.wA); T* sA = at<T>(B, L.sA); T* yA = at<T>(B, L.yA);
+  T* mr = at<T>(B, L.mr); T* md0 = at<T>(B, L.md0); T* md1 = at<T>(B, L.md1);
+  double* psum = at<double>(B, L.psum);
+  const int o2 = d.off[2], o3 = d.off[3], o4 = d.off[4], ns = d.ns;
+  const int nu = d.nu, np = d.np, nj = d.nj, na = d.na;
+  const double dt = H.dt;
+  const int vc = H.exact ? H.inner_iters : 1;       // V-cycles per spatial solve
+  const int mit = H.mass_iters;
+  // Q1 mass: eigenvalues of D^{-1} M lie in [1/4, 9/4] on squares; widened slightly.
+  const double mlo = 0.24, mhi = 2.3, mth = 0.5 * (mhi + mlo), mde = 0.5 * (mhi - mlo);
+
+  // 0. split r, projecting the pressure rows to zero sum per slab
+  hipLaunchKernelGGL(k_slab_sums_d, dim3(nt), dim3(kBlock), 0, s, r, int64_t(ns), o2, np, nullptr, psum);
+  hipLaunchKernelGGL((k_split<T>), dim3(grid_for(int64_t(ns) * nt)), dim3(kBlock), 0, s, r, ns, nt, o2, o3, o4,
+                     psum, ru, rp, rj, ra);
+  // 1. magnetic Schur complement: w = M_A^{-1} r_A; s = F_A w; y_A = C_A^{-1} s (forward sweep)
+  cheb_solve<T>(s, H.MA, nt, 0, 0, static_cast<const T*>(H.dMA), 0, nullptr, mth, mde, ra, w, mr, md0, md1, na, mit,
+                0, false);
+  {
+    Seg<T> sg[2] = {seg<T>(H.FA, 0, 0, 1, w, na, 0, 0, nt, 1.0), seg<T>(H.FA, 1, 0, 0, w, na, -1, 1, nt, 1.0)};
+    spmv<T, T>(s, H.FA, nt, 2, sg, nullptr, na, 0.0, sA, na);
+  }
+  for (int k = 0; k < nt; ++k) {
+    T* rhs = static_cast<T*>(H.amgC0.buf[1]);   // level-0 b of the C_A hierarchy
+    Seg<T> sg[2];
+    int nsg = 0;
+    if (k >= 1) sg[nsg++] = seg<T>(H.C1, 0, k - 1, 0, yA + int64_t(k - 1) * na, 0, 0, 0, 1, 1.0 / dt);
+    if (k >= 2) sg[nsg++] = seg<T>(H.C1, 1, 0, 0, yA + int64_t(k - 2) * na, 0, 0, 0, 1, -1.0 / (dt * dt));
+    spmv<T, T>(s, H.C1, 1, nsg, sg, sA + int64_t(k) * na, 0, 1.0, rhs, 0);
+    amg_solve<T>(s, H.amgC0, 1, k, 0, yA + int64_t(k) * na, rhs, vc);
+  }
+  // 2. y_j = M_j^{-1} (r_j - K_jA y_A)
+  spmv1<T>(s, H.KjA, nt, 0, 0, yA, na, -1.0, rj, 1.0, rj, nj);
+  cheb_solve<T>(s, H.Mj, nt, 0, 0, static_cast<const T*>(H.dMj), 0, nullptr, mth, mde, rj, yj, mr, md0, md1, nj, mit,
+                0, false);
+  // 3. y_u = r_u - Z_j y_j - Z_A y_A
+  {
+    Seg<T> sg[2] = {seg<T>(H.Zj, 0, 0, 1, yj, nj, 0, 0, nt, -1.0), seg<T>(H.Zj, 1, 0, 1, yA, na, 0, 0, nt, -1.0)};
+    spmv<T, T>(s, H.Zj, nt, 2, sg, ru, nu, 1.0, yu, nu);
+  }
+  // 4. pressure: q = K_p^{-1} r_p; t = F_p q; x_p = -M_p^{-1} t (sign applied at the join)
+  amg_solve<T>(s, H.amgKp, nt, 0, 0, q, rp, vc);
+  {
+    Seg<T> sg[2] = {seg<T>(H.Fp, 0, 0, 1, q, np, 0, 0, nt, 1.0), seg<T>(H.Fp, 1, 0, 0, q, np, -1, 1, nt, 1.0)};
+    spmv<T, T>(s, H.Fp, nt, 2, sg, nullptr, np, 0.0, t, np);
+  }
+  cheb_solve<T>(s, H.Mp, nt, 0, 0, static_cast<const T*>(H.dMp), 0, nullptr, mth, mde, t, xp, mr, md0, md1, np, mit,
+                0, false);
+  // 5. x_u = F_u^{-1} (y_u - B^T x_p), x_p carrying the minus sign: y_u + B^T xp
+  spmv1<T>(s, H.Bt, nt, 0, 0, xp, np, 1.0, yu, 1.0, yu, nu);
+  for (int k = 0; k < nt; ++k) {
+    T* rhs = static_cast<T*>(H.amgFu.buf[1]);
+    Seg<T> sg = seg<T>(H.Mu, 0, 0, 0, xu + int64_t(k - 1) * nu, 0, 0, 0, 1, 1.0 / dt);
+    spmv<T, T>(s, H.Mu, 1, k >= 1 ? 1 : 0, &sg, yu + int64_t(k) * nu, 0, 1.0, rhs, 0);
+    amg_solve<T>(s, H.amgFu, 1, k, 0, xu + int64_t(k) * nu, rhs, vc);
+  }
+  // 6. join with the pressure normalisation 1^T M_p p = 0
+  hipLaunchKernelGGL((k_slab_sums_t<T>), dim3(nt), dim3(kBlock), 0, s, xp, int64_t(np), np, H.mp_rowsum,
+                     psum + nt);
+  hipLaunchKernelGGL((k_join<T>), dim3(grid_for(int64_t(ns) * nt)), dim3(kBlock), 0, s, z, ns, nt, o2, o3, o4, xu,
+                     xp, -1.0, psum + nt, H.msum, yj, yA);
+  return ST_OK;
+}
+
+// ================================================ P_T^{-T} (adjoint) ====
+template <class T>
+int precond_transpose(Handle& H, const double* r, double* z, hipStream_t s) {
+  if (!H.adjoint) return ST_EINVAL;
+  const Dims& d = H.d;
+  const int nt = d.nt;
+  char* B = H.base;
+  const WsLayout& L = H.L;
+  T* ru = at<T>(B, L.ru); T* xu = at<T>(B, L.xu);
+  T* rp = at<T>(B, L.rp); T* q = at<T>(B, L.q); T* t = at<T>(B, L.t); T* xp = at<T>(B, L.xp);
+  T* rj = at<T>(B, L.rj); T* yj = at<T>(B, L.yj);
+  T* ra = at<T>(B, L.ra); T* c = at<T>(B, L.wA); T* f = at<T>(B, L.sA); T* yA = at<T>(B, L.yA);
+  T* mr = at<T>(B, L.mr); T* md0 = at<T>(B, L.md0); T* md1 = at<T>(B, L.md1);
+  double* psum = at<double>(B, L.psum);
+  const int o2 = d.off[2], o3 = d.off[3], o4 = d.off[4], ns = d.ns;
+  const int nu = d.nu, np = d.np, nj = d.nj, na = d.na;
+  const double dt = H.dt;
+  const int vc = H.exact ? H.inner_iters : 1;
+  const int mit = H.mass_iters;
+  const double mlo = 0.24, mhi = 2.3, mth = 0.5 * (mhi + mlo), mde = 0.5 * (mhi - mlo);
+
+  hipLaunchKernelGGL(k_slab_sums_d, dim3(nt), dim3(kBlock), 0, s, r, int64_t(ns), o2, np, nullptr, psum);
+  hipLaunchKernelGGL((k_split<T>), dim3(grid_for(int64_t(ns) * nt)), dim3(kBlock), 0, s, r, ns, nt, o2, o3, o4,
+                     psum, ru, rp, rj, ra);
+  // x_u = F_u^{-T} r_u, backward in time: F_uk^T x^k = r^k + (1/dt) M_u x^{k+1}
+  for (int k = nt - 1; k >= 0; --k) {
+    T* rhs = static_cast<T*>(H.amgFuT.buf[1]);
+    Seg<T> sg = seg<T>(H.Mu, 0, 0, 0, xu + int64_t(k + 1) * nu, 0, 0, 0, 1, 1.0 / dt);
+    spmv<T, T>(s, H.Mu, 1, k + 1 < nt ? 1 : 0, &sg, ru + int64_t(k) * nu, 0, 1.0, rhs, 0);
+    amg_solve<T>(s, H.amgFuT, 1, k, 0, xu + int64_t(k) * nu, rhs, vc);
+  }
+  // x_p = S_p^{-T}(r_p - B x_u),  S_p^{-T} = -K_p^{-1} F_p^T M_p^{-1}
+  spmv1<T>(s, H.B, nt, 0, 0, xu, nu, -1.0, rp, 1.0, rp, np);
+  hipLaunchKernelGGL((k_slab_sums_t<T>), dim3(nt), dim3(kBlock), 0, s, rp, int64_t(np), np, nullptr, psum);
+  hipLaunchKernelGGL((k_slab_shift<T>), dim3(grid_for(int64_t(np) * nt)), dim3(kBlock), 0, s, rp, int64_t(np), np,
+                     nt, psum, 1.0 / np);
+  cheb_solve<T>(s, H.Mp, nt, 0, 0, static_cast<const T*>(H.dMp), 0, nullptr, mth, mde, rp, q, mr, md0, md1, np, mit,
+                0, false);
+  {
+    Seg<T> sg[2] = {seg<T>(H.Fpt, 0, 0, 1, q, np, 0, 0, nt, 1.0), seg<T>(H.Fpt, 1, 0, 0, q, np, 1, 0, nt - 1, 1.0)};
+    spmv<T, T>(s, H.Fpt, nt, 2, sg, nullptr, np, 0.0, t, np);
+  }
+  hipLaunchKernelGGL((k_slab_sums_t<T>), dim3(nt), dim3(kBlock), 0, s, t, int64_t(np), np, nullptr, psum);
+  hipLaunchKernelGGL((k_slab_shift<T>), dim3(grid_for(int64_t(np) * nt)), dim3(kBlock), 0, s, t, int64_t(np), np,
+                     nt, psum, 1.0 / np);
+  amg_solve<T>(s, H.amgKp, nt, 0, 0, xp, t, vc);
+  // y_j = M_j^{-1}(r_j - Z_j^T x_u)
+  spmv1<T>(s, H.Zjt, nt, 0, 1, xu, nu, -1.0, rj, 1.0, rj, nj);
+  cheb_solve<T>(s, H.Mj, nt, 0, 0, static_cast<const T*>(H.dMj), 0, nullptr, mth, mde, rj, yj, mr, md0, md1, nj, mit,
+                0, false);
+  // h = r_A - Z_A^T x_u - K_jA^T y_j  (in ra)
+  spmv1<T>(s, H.ZAt, nt, 0, 1, xu, nu, -1.0, ra, 1.0, ra, na);
+  spmv1<T>(s, H.KjAt, nt, 0, 0, yj, nj, -1.0, ra, 1.0, ra, na);
+  // c = C_A^{-T} h backward: C0_k^T c^k = h^k + (1/dt) C1_k^T c^{k+1} - (1/dt^2) C2^T c^{k+2}
+  for (int k = nt - 1; k >= 0; --k) {
+    T* rhs = static_cast<T*>(H.amgC0T.buf[1]);
+    Seg<T> sg[2];
+    int nsg = 0;
+    if (k + 1 < nt) sg[nsg++] = seg<T>(H.C1t, 0, k, 0, c + int64_t(k + 1) * na, 0, 0, 0, 1, 1.0 / dt);
+    if (k + 2 < nt) sg[nsg++] = seg<T>(H.C1t, 1, 0, 0, c + int64_t(k + 2) * na, 0, 0, 0, 1, -1.0 / (dt * dt));
+    spmv<T, T>(s, H.C1t, 1, nsg, sg, ra + int64_t(k) * na, 0, 1.0, rhs, 0);
+    amg_solve<T>(s, H.amgC0T, 1, k, 0, c + int64_t(k) * na, rhs, vc);
+  }
+  // f = F_A^T c; y_A = M_A^{-1} f
+  {
+    Seg<T> sg[2] = {seg<T>(H.FAt, 0, 0, 1, c, na, 0, 0, nt, 1.0), seg<T>(H.FAt, 1, 0, 0, c, na, 1, 0, nt - 1, 1.0)};
+    spmv<T, T>(s, H.FAt, nt, 2, sg, nullptr, na, 0.0, f, na);
+  }
+  cheb_solve<T>(s, H.MA, nt, 0, 0, static_cast<const T*>(H.dMA), 0, nullptr, mth, mde, f, yA, mr, md0, md1, na, mit,
+                0, false);
+  hipLaunchKernelGGL((k_slab_sums_t<T>), dim3(nt), dim3(kBlock), 0, s, xp, int64_t(np), np, H.mp_rowsum,
+                     psum + nt);
+  hipLaunchKernelGGL((k_join<T>), dim3(grid_for(int64_t(ns) * nt)), dim3(kBlock), 0, s, z, ns, nt, o2, o3, o4, xu,
+                     xp, -1.0, psum + nt, H.msum, yj, yA);
+  return ST_OK;
+}
+
+int apply_precond(Handle& H, const double* r, double* z, hipStream_t s, bool transpose) {
+  int rc;
+  if (H.fp32)
+    rc = transpose ? precond_transpose<float>(H, r, z, s) : precond_forward<float>(H, r, z, s);
+  else
+    rc = transpose ? precond_transpose<double>(H, r, z, s) : precond_forward<double>(H, r, z, s);
+  return rc;
+}
+
+// y = alpha J x + beta b  (J or J^T), FP64
+void apply_J(Handle& H, const double* x, double* y, hipStream_t s, bool transpose, double alpha, const double* b) {
+  const DGroup& g = transpose ? H.JT : H.J;
+  const int nt = H.d.nt, ns = H.d.ns;
+  Seg<double> sg[3] = {
+      seg<double>(g, 0, 0, 1, x, ns, 0, 0, nt, alpha),
+      seg<double>(g, 1, 0, 0, x, ns, 0, 0, nt, alpha),
+      transpose ? seg<double>(g, 2, 0, 0, x, ns, 1, 0, nt - 1, alpha) : seg<double>(g, 2, 0, 0, x, ns, -1, 1, nt, alpha)};
+  spmv<double, double>(s, g, nt, 3, sg, b, ns, b ? 1.0 : 0.0, y, ns);
+}
+
+// ============================================================ FGMRES ===
+struct Reducer {
+  Handle& H;
+  hipStream_t s;
+  double* partial;
+  int64_t N;
+  // out[i] = V_i . w for i < nv (mode 0 set, 2 add); mode 1: out[0] = ||w||
+  void dots(const double* V, int nv, const double* w, double* out, int mode, double* copy_to = nullptr) {
+    hipLaunchKernelGGL(k_mdot_partial, dim3(kPartialBlocks, nv), dim3(kBlock), 0, s, V, N, w, partial);
+    hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(kBlock), 0, s, partial, kPartialBlocks, out, mode, copy_to);
+  }
+};
+
+int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* info, hipStream_t s, bool adjoint) {
+  auto t0 = std::chrono::steady_clock::now();
+  const Dims& d = H.d;
+  const int64_t N = int64_t(d.nt) * d.ns;
+  const int m = o->restart > 0 ? o->restart : 30;
+  if (m > H.max_restart) return ST_EINVAL;
+  if (adjoint && !H.adjoint) return ST_EINVAL;
+  const int maxit = o->maxit > 0 ? o->maxit : 1000;
+  char* B = H.base;
+  const WsLayout& L = H.L;
+  double* V = at<double>(B, L.V);
+  double* Z = at<double>(B, L.Z);
+  double* w = at<double>(B, L.w);
+  double* bp = at<double>(B, L.r);
+  double* Hc = at<double>(B, L.hess);     // column j at Hc + j*(m+1)
+  double* sm = at<double>(B, L.small);
+  double* g = sm + 64;
+  double* cs = g + (m + 2);
+  double* sn = cs + (m + 2);
+  double* y = sn + (m + 2);
+  double* psum = at<double>(B, L.psum);
+  const int ldh = m + 1;
+  Reducer red{H, s, at<double>(B, L.partial), N};
+  double* hs = H.host_small;
+  const int gr = grid_for(N);
+  std::vector<hipEvent_t> evs;
+  auto precond = [&](const double* r, double* z) {
+    hipEvent_t a, bev;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&bev);
+    (void)hipEventRecord(a, s);
+    apply_precond(H, r, z, s, adjoint);
+    (void)hipEventRecord(bev, s);
+    evs.push_back(a);
+    evs.push_back(bev);
+  };
+  auto fetch = [&](const double* dev, int count) -> int {
+    if (hipMemcpyAsync(hs, dev, sizeof(double) * count, hipMemcpyDeviceToHost, s) != hipSuccess) return ST_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return ST_EHIP;
+    return ST_OK;
+  };
+  // project b's pressure rows: bp = P b
+  hipLaunchKernelGGL(k_slab_sums_d, dim3(d.nt), dim3(kBlock), 0, s, b_in, int64_t(d.ns), d.off[2], d.np, nullptr,
+                     psum);
+  hipLaunchKernelGGL(k_project_p, dim3(gr), dim3(kBlock), 0, s, b_in, bp, d.ns, d.nt, d.off[2], d.off[3], psum);
+  red.dots(bp, 1, bp, sm + 0, 1);
+  int rc = fetch(sm, 1);
+  if (rc) return rc;
+  const double bnorm = hs[0];
+  if (!std::isfinite(bnorm)) return ST_EBREAKDOWN;
+  const double tol = std::max(o->rtol * bnorm, o->atol);
+  if (!o->x0_given) HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * N, s));
+  info->iterations = 0;
+  info->restarts = 0;
+  info->converged = 0;
+  int its = 0, status = ST_ENOTCONV;
+  double true_res = 0.0;
+  if (bnorm == 0.0) {
+    HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * N, s));
+    info->converged = 1;
+    info->true_rel_residual = 0.0;
+    return ST_OK;
+  }
+  for (;;) {
+    // r = bp - J x  -> V_0 (unnormalised), beta
+    apply_J(H, x, V, s, adjoint, -1.0, bp);
+    red.dots(V, 1, V, sm + 0, 1);
+    rc = fetch(sm, 1);
+    if (rc) return rc;
+    const double beta = hs[0];
+    true_res = beta;
+    if (!std::isfinite(beta)) return ST_EBREAKDOWN;
+    if (beta <= tol) {
+      status = ST_OK;
+      break;
+    }
+    if (its >= maxit) break;
+    if (o->history && its < o->history_len && its == 0) o->history[0] = beta / bnorm;
+    hipLaunchKernelGGL(k_scale, dim3(gr), dim3(kBlock), 0, s, V, V, N, sm + 0);
+    hipLaunchKernelGGL(k_init_g, dim3(1), dim3(64), 0, s, g, m + 1, sm + 0);
+    int j = 0, mused = 0;
+    for (; j < m; ++j) {
+      double* vj = V + int64_t(j) * N;
+      double* zj = Z + int64_t(j) * N;
+      precond(vj, zj);
+      apply_J(H, zj, w, s, adjoint, 1.0, nullptr);
+      double* hcol = Hc + int64_t(j) * ldh;
+      // CGS2: two classical Gram-Schmidt passes
+      red.dots(V, j + 1, w, hcol, 0);
+      hipLaunchKernelGGL(k_mgs_update, dim3(gr), dim3(kBlock), 0, s, w, V, N, hcol, j + 1);
+      red.dots(V, j + 1, w, y, 0);
+      hipLaunchKernelGGL(k_mgs_update, dim3(gr), dim3(kBlock), 0, s, w, V, N, y, j + 1);
+      // H[:, j] += second-pass coefficients
+      {
+        // hcol[i] += y[i]: reuse k_reduce in add mode with a one-element partial per entry
+        hipLaunchKernelGGL(k_reduce, dim3(j + 1), dim3(kBlock), 0, s, y, 1, hcol, 2, nullptr);
+      }
+      red.dots(w, 1, w, hcol + (j + 1), 1, sm + 1);   // h_{j+1,j} = ||w||, copy to sm[1]
+      hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, s, Hc, j, ldh, g, cs, sn, sm + 2);
+      if (j + 1 < m) hipLaunchKernelGGL(k_scale, dim3(gr), dim3(kBlock), 0, s, V + int64_t(j + 1) * N, w, N, sm + 1);
+      rc = fetch(sm, 3);
+      if (rc) return rc;
+      ++its;
+      mused = j + 1;
+      const double est = hs[2];
+      if (o->history && its < o->history_len) o->history[its] = est / bnorm;
+      if (!std::isfinite(est) || !std::isfinite(hs[1])) return ST_EBREAKDOWN;
+      if (est <= tol || its >= maxit) break;
+    }
+    hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(1), 0, s, Hc, mused, ldh, g, y);
+    hipLaunchKernelGGL(k_update_x, dim3(gr), dim3(kBlock), 0, s, x, Z, N, y, mused);
+    info->restarts++;
+  }
+  // normalise the pressure of x: 1^T M_p p^k = 0
+  hipLaunchKernelGGL(k_slab_sums_d, dim3(d.nt), dim3(kBlock), 0, s, x, int64_t(d.ns), d.off[2], d.np, H.mp_rowsum,
+                     psum);
+  hipLaunchKernelGGL((k_slab_shift<double>), dim3(grid_for(int64_t(d.np) * d.nt)), dim3(kBlock), 0, s,
+                     x + d.off[2], int64_t(d.ns), d.np, d.nt, psum, 1.0 / H.msum);
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipGetLastError());
+  double pms = 0.0;
+  for (size_t i = 0; i + 1 < evs.size(); i += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, evs[i], evs[i + 1]) == hipSuccess) pms += ms;
+    (void)hipEventDestroy(evs[i]);
+    (void)hipEventDestroy(evs[i + 1]);
+  }
+  info->iterations = its;
+  info->converged = status == ST_OK ? 1 : 0;
+  info->true_rel_residual = true_res / bnorm;
+  info->precond_seconds = pms * 1e-3;
+  info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return status;
+}
+
+}  // namespace
+}  // namespace st
+
+// ============================================================ C ABI ===
+extern "C" {
+
+int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_handle** out) {
+  using namespace st;
+  if (!plan || !ws || !out) return ST_EINVAL;
+  *out = nullptr;
+  const Plan& P = plan->p;
+  if (ws_bytes < P.ws_bytes) return ST_ENOMEM;
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return ST_EINVAL;
+  if (P.amgFu.ncoarse > 512 || P.amgC0.ncoarse > 512 || P.amgKp.ncoarse > 512) return ST_EINTERNAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  st_handle* hh = nullptr;
+  try {
+    hh = new st_handle;
+  } catch (...) {
+    return ST_ENOMEM;
+  }
+  Handle& H = hh->h;
+  H.d = P.blk.d;
+  H.dt = P.blk.dt;
+  H.fp32 = P.fp32;
+  H.exact = P.exact;
+  H.inner_iters = P.inner_iters;
+  H.mass_iters = P.mass_iters;
+  H.max_restart = P.max_restart;
+  H.adjoint = P.prob.adjoint;
+  H.base = static_cast<char*>(ws);
+  H.L = workspace_layout(P);
+  char* base = H.base;
+  if (hipMemcpyAsync(base, P.img.bytes.data(), P.img.bytes.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    delete hh;
+    return ST_EHIP;
+  }
+  H.J = mirror(base, P.J);
+  if (H.adjoint) H.JT = mirror(base, P.JT);
+  H.MA = mirror(base, P.MA);
+  H.Mj = mirror(base, P.Mj);
+  H.Mp = mirror(base, P.Mp);
+  H.dMA = base + P.dMA.off;
+  H.dMj = base + P.dMj.off;
+  H.dMp = base + P.dMp.off;
+  H.FA = mirror(base, P.FA);
+  H.Fp = mirror(base, P.Fp);
+  H.KjA = mirror(base, P.KjA);
+  H.Bt = mirror(base, P.Bt);
+  H.Zj = mirror(base, P.Zj);
+  H.Mu = mirror(base, P.Mu);
+  H.C1 = mirror(base, P.C1);
+  if (H.adjoint) {
+    H.FAt = mirror(base, P.FAt);
+    H.Fpt = mirror(base, P.Fpt);
+    H.KjAt = mirror(base, P.KjAt);
+    H.B = mirror(base, P.B);
+    H.Zjt = mirror(base, P.Zjt);
+    H.ZAt = mirror(base, P.ZAt);
+    H.C1t = mirror(base, P.C1t);
+  }
+  H.mp_rowsum = at<double>(base, P.mp_rowsum.off);
+  {
+    const double* m = reinterpret_cast<const double*>(P.img.bytes.data() + P.mp_rowsum.off);
+    double acc = 0.0;
+    for (size_t i = 0; i < P.mp_rowsum.count; ++i) acc += m[i];
+    H.msum = acc;
+  }
+  H.amgFu = mirror_amg(base, P.amgFu, H.L.fu_lev);
+  H.amgC0 = mirror_amg(base, P.amgC0, H.L.ca_lev);
+  H.amgKp = mirror_amg(base, P.amgKp, H.L.kp_lev);
+  if (H.adjoint) {
+    H.amgFuT = mirror_amg(base, P.amgFuT, H.L.fu_lev);
+    H.amgC0T = mirror_amg(base, P.amgC0T, H.L.ca_lev);
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&H.host_small), 64 * sizeof(double), hipHostMallocDefault) !=
+      hipSuccess) {
+    delete hh;
+    return ST_EHIP;
+  }
+  *out = hh;
+  return ST_OK;
+}
+
+int st_destroy(st_handle* h) {
+  if (!h) return ST_OK;
+  if (h->h.host_small) (void)hipHostFree(h->h.host_small);
+  delete h;
+  return ST_OK;
+}
+
+int st_sizes(const st_handle* h, int64_t* n_total, int* ns, int* nt) {
+  if (!h) return ST_EINVAL;
+  if (n_total) *n_total = int64_t(h->h.d.ns) * h->h.d.nt;
+  if (ns) *ns = h->h.d.ns;
+  if (nt) *nt = h->h.d.nt;
+  return ST_OK;
+}
+
+int st_apply_jacobian(st_handle* h, const double* x, double* y, void* stream) {
+  if (!h || !x || !y || x == y) return ST_EINVAL;
+  st::apply_J(h->h, x, y, static_cast<hipStream_t>(stream), false, 1.0, nullptr);
+  return hipGetLastError() == hipSuccess ? ST_OK : ST_EHIP;
+}
+
+int st_apply_jacobian_t(st_handle* h, const double* x, double* y, void* stream) {
+  if (!h || !x || !y || x == y || !h->h.adjoint) return ST_EINVAL;
+  st::apply_J(h->h, x, y, static_cast<hipStream_t>(stream), true, 1.0, nullptr);
+  return hipGetLastError() == hipSuccess ? ST_OK : ST_EHIP;
+}
+
+int st_apply_precond(st_handle* h, const double* r, double* z, void* stream) {
+  if (!h || !r || !z || r == z) return ST_EINVAL;
+  int rc = st::apply_precond(h->h, r, z, static_cast<hipStream_t>(stream), false);
+  if (rc) return rc;
+  return hipGetLastError() == hipSuccess ? ST_OK : ST_EHIP;
+}
+
+int st_apply_precond_t(st_handle* h, const double* r, double* z, void* stream) {
+  if (!h || !r || !z || r == z || !h->h.adjoint) return ST_EINVAL;
+  int rc = st::apply_precond(h->h, r, z, static_cast<hipStream_t>(stream), true);
+  if (rc) return rc;
+  return hipGetLastError() == hipSuccess ? ST_OK : ST_EHIP;
+}
+
+int st_fgmres_solve(st_handle* h, const double* b, double* x, const st_opts* o, st_info* info, void* stream) {
+  if (!h || !b || !x || !o || !info || b == x) return ST_EINVAL;
+  return st::fgmres(h->h, b, x, o, info, static_cast<hipStream_t>(stream), false);
+}
+
+int st_adjoint_solve(st_handle* h, const double* g, double* lam, const st_opts* o, st_info* info, void* stream) {
+  if (!h || !g || !lam || !o || !info || g == lam) return ST_EINVAL;
+  return st::fgmres(h->h, g, lam, o, info, static_cast<hipStream_t>(stream), true);
+}
+
+}  // extern "C"

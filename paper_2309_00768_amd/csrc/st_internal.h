@@ -1,0 +1,189 @@
+// Internal host-side data structures of libst (setup, packing, device image).
+#pragma once
+
+#include <cstdint>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "../../include/st.h"
+
+namespace st {
+
+// ------------------------------------------------------------ host CSR ---
+struct Csr {
+  int nr = 0, nc = 0;
+  std::vector<int> rp;      // nr+1
+  std::vector<int> ci;      // nnz, sorted within each row
+  std::vector<double> v;    // nnz (or nsets * nnz for per-slab values)
+  int64_t nnz() const { return rp.empty() ? 0 : rp[nr]; }
+  // Position of (r, c) in the pattern, or -1.
+  int64_t find(int r, int c) const;
+};
+
+// Pattern from (row, col) pairs; duplicates merged, rows sorted.
+class PatternBuilder {
+ public:
+  PatternBuilder(int nr, int nc) : nr_(nr), nc_(nc), rows_(nr) {}
+  void add(int r, int c) { rows_[r].push_back(c); }
+  Csr finish();
+ private:
+  int nr_, nc_;
+  std::vector<std::vector<int>> rows_;
+};
+
+// Sparse products on a common pattern type (host, float64).
+Csr csr_transpose(const Csr& a);
+Csr csr_matmul(const Csr& a, const Csr& b);          // pattern + values
+Csr csr_add(const Csr& a, double sa, const Csr& b, double sb);  // sa*a + sb*b
+Csr csr_scale_cols(const Csr& a, const std::vector<double>& s);  // a * diag(s)
+void csr_spmv(const Csr& a, const double* x, double* y);         // y = a x (set 0)
+
+// Run f(i) for i in [0, n) on up to `threads` host threads.
+void parallel_for(int n, int threads, const std::function<void(int)>& f);
+int host_threads();
+
+// ------------------------------------------------------------- problem ---
+struct Dims {
+  int n = 0, nt = 0;
+  int nq2 = 0, nq1 = 0;     // all Q2 / Q1 nodes
+  int nf2 = 0, nf1 = 0;     // interior Q2 / Q1 nodes
+  int nu = 0, np = 0, nj = 0, na = 0, ns = 0;
+  int off[6] = {0, 0, 0, 0, 0, 0};   // u_x, u_y, p, j, A, end
+};
+
+Dims make_dims(int n, int nt);
+
+// Every host-assembled block.  State-dependent blocks hold one value array per
+// slab (v has nt * nnz entries, slab-major); constant blocks one value array.
+struct Blocks {
+  Dims d;
+  double dt, mu, eta, mu0;
+  Csr Fu, Mu, Ku, B, Bt, Zj, ZA, Mj, KjA, KjAt, Y, FA, MA, KA, Mp, Kp, Fp;
+  Csr C0, C1, C2;           // wave operator bands; C1 has nt-1 value sets (nt>=2)
+  std::vector<double> jbar; // [nt][nq1]
+  std::vector<double> bbar2;  // |Bbar_k|^2 per slab
+};
+
+// Assembles all blocks from the state (host, multithreaded over slabs).
+int assemble_blocks(const st_problem& p, Blocks& out, std::string& err);
+void form_wave_operator(Blocks& b);
+
+// ---------------------------------------------------------- device image ---
+struct Span {
+  size_t off = 0;   // byte offset in the image
+  size_t count = 0; // elements
+};
+
+class Image {
+ public:
+  template <class T>
+  Span put(const T* data, size_t count) {
+    Span s = reserve(count * sizeof(T));
+    s.count = count;
+    if (count) std::memcpy(bytes.data() + s.off, data, count * sizeof(T));
+    return s;
+  }
+  template <class T>
+  Span put(const std::vector<T>& v) { return put(v.data(), v.size()); }
+  Span reserve(size_t nbytes) {
+    size_t off = (bytes.size() + 255) & ~size_t(255);
+    bytes.resize(off + nbytes);
+    Span s;
+    s.off = off;
+    s.count = nbytes;
+    return s;
+  }
+  std::vector<char> bytes;
+};
+
+// Sliced ELLPACK with C = 64 rows per slice (one wavefront lane per row).
+// Several segments can share the row permutation (the fused J rows).
+constexpr int kSlice = 64;
+
+struct SellSeg {
+  Span sptr;        // int32 [nslices + 1], element offsets (multiples of 64)
+  Span col;         // int32 [total]
+  Span val;         // T [nsets][total]
+  int nsets = 1;
+  int64_t total = 0;
+};
+
+struct SellGroup {
+  int nrows = 0, ncols = 0, nslices = 0;
+  int fp32 = 0;     // value type: 0 double, 1 float
+  Span perm;        // int32 [nslices * 64]; -1 marks padding lanes
+  SellSeg seg[3];
+  int nseg = 0;
+};
+
+// Packs CSR matrices with the same row count into one SELL group.  Each
+// matrix may carry several value sets (csr.v.size() = nsets * nnz).  Rows are
+// sorted by total length in windows of `sigma` rows (0 = whole matrix).
+SellGroup pack_sell(Image& img, const std::vector<const Csr*>& mats, int fp32, int sigma);
+
+// --------------------------------------------------------------- AMG ---
+struct AmgLevel {
+  int nrows = 0;
+  SellGroup A;            // per-set values
+  Span dinv;              // T [nsets][nrows]
+  Span cheb;              // double [nsets][2] = (theta, delta) of the interval
+  SellGroup P;            // prolongation to this level from the next (shared)
+  SellGroup R;            // restriction from this level to the next (shared)
+};
+
+struct Amg {
+  int nsets = 1;
+  int fp32 = 0;
+  int cheb_degree = 3;
+  std::vector<AmgLevel> lev;   // lev.back() is the coarsest
+  int ncoarse = 0;
+  Span coarse_inv;        // T [nsets][ncoarse][ncoarse] dense inverse
+  int singular = 0;
+};
+
+struct Grid2 { int gx, gy, ncomp; };   // structured node grid of a block (per component)
+
+// Builds a smoothed-aggregation hierarchy for the value sets of `a` (a.v holds
+// nsets * nnz values).  `grid` gives the structured node layout used for
+// aggregation (3x3 node blocks per component).
+int build_amg(Image& img, const Csr& a, int nsets, Grid2 grid, int fp32, int cheb_degree,
+              int sigma, bool singular, Amg& out, std::string& err);
+
+// ---------------------------------------------------------------- plan ---
+struct Plan {
+  st_problem prob{};
+  Blocks blk;
+  Image img;
+  size_t ws_bytes = 0;
+  int fp32 = 0;
+  int inner_iters = 40, mass_iters = 12, max_restart = 30, exact = 0;
+  // J and J^T (FP64): segment 0 per-slab values, 1 shared, 2 previous/next slab coupling.
+  SellGroup J, JT;
+  // P_T pieces (precision per fp32).
+  SellGroup MA, Mj, Mp;           // masses (Chebyshev-Jacobi solves)
+  Span dMA, dMj, dMp;             // inverse diagonals
+  SellGroup FA, FAt, Fp, Fpt;     // per-slab bidiagonal applies (diag blocks)
+  SellGroup KjA, KjAt, Bt, B;     // shared couplings
+  SellGroup Zj, ZA, Zjt, ZAt;     // per-slab couplings
+  SellGroup Mu;                   // sweep coupling of F_u
+  SellGroup C1, C2, C1t, C2t;     // sweep couplings of C_A
+  Amg amgFu, amgC0, amgKp;        // spatial solvers (per-slab for Fu, C0; shared Kp)
+  Amg amgFuT, amgC0T;             // transposed hierarchies for the adjoint
+  Span mp_rowsum;                 // double [np]: 1^T M_p (pressure normalisation)
+  size_t image_bytes = 0;
+};
+
+// Scratch vectors of a handle, carved from the workspace after the image.
+struct WsLayout {
+  size_t V = 0, Z = 0, w = 0, r = 0, hess = 0, small = 0, partial = 0, psum = 0;
+  size_t ru = 0, yu = 0, xu = 0, rp = 0, q = 0, t = 0, xp = 0, rj = 0, yj = 0;
+  size_t ra = 0, wA = 0, sA = 0, yA = 0, mr = 0, md0 = 0, md1 = 0;
+  std::vector<size_t> kp_lev, fu_lev, ca_lev;   // 6 vectors per level each
+  size_t end = 0;
+};
+constexpr int kPartialBlocks = 1024;   // blocks of the two-stage reductions
+WsLayout workspace_layout(const Plan& p);
+
+}  // namespace st

@@ -1,0 +1,96 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the header
+declares, and its host setup (assembly, wave operator) matches the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_00768_amd import binding, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "st.h")).read()
+    return re.findall(r"^(?:int|const char\*)\s+(st_\w+)\(", text, re.M)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    names = header_symbols()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(binding.EXPORTED) == set(names)
+
+
+def test_error_strings():
+    assert binding.lib().st_error_string(0) == b"success"
+    assert b"invalid" in binding.lib().st_error_string(-1)
+
+
+def test_plan_rejects_invalid_problem():
+    p = binding.StProblem()
+    p.n, p.nt, p.dt, p.mu0 = 1, 1, 0.1, 1.0
+    h = ctypes.c_void_p()
+    assert binding.lib().st_plan_create(ctypes.byref(p), ctypes.byref(h)) == -1
+
+
+def _compare(plan, ref, tol=1e-13):
+    worst = 0.0
+    for k in sorted({0, ref.nt // 2, ref.nt - 1}):
+        s = ref.slabs[k]
+        for nm in ("Fu", "Zj", "ZA", "Y", "FA", "Fp"):
+            A, R = plan.export_block(nm, k), getattr(s, nm)
+            worst = max(worst, abs(A - R).max() / max(abs(R).max(), 1e-300))
+        C0, C1, C2 = ref.wave_blocks()
+        worst = max(worst, abs(plan.export_block("C0", k) - C0[k]).max() / abs(C0[k]).max())
+        if k < ref.nt - 1:
+            worst = max(worst, abs(plan.export_block("C1", k) - C1[k]).max() / abs(C1[k]).max())
+    cb = ref.cb
+    for nm, R in (("Mu", cb.Mu), ("B", cb.B), ("Mj", cb.Mj), ("KjA", cb.KjA), ("MA", cb.MA), ("KA", cb.KA),
+                  ("Kp", cb.Kp)):
+        worst = max(worst, abs(plan.export_block(nm, 0) - R).max() / abs(R).max())
+    assert worst <= tol, worst
+
+
+@pytest.mark.parametrize("name", ["cfg1"])
+def test_host_assembly_matches_oracle(name):
+    cfg = inputs.CONFIGS[name]
+    ub, ab = inputs.state(cfg)
+    plan = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab)
+    ref = oracle.system_from_config(cfg, ub, ab)
+    np.testing.assert_allclose(plan.export_jbar(), ref.jbar, rtol=0, atol=1e-12 * np.abs(ref.jbar).max())
+    assert plan.ns == ref.ns and plan.offsets == [0, ref.offs[0] + ref.nu // 2, *ref.offs[1:]]
+    _compare(plan, ref)
+
+
+def test_host_assembly_matches_oracle_shear_layer_small():
+    cfg = inputs.Config("shear6", 6, 3, 0.05, 100.0, 100.0, state="shear")
+    ub, ab = inputs.state(cfg)
+    plan = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab)
+    ref = oracle.system_from_config(cfg, ub, ab)
+    _compare(plan, ref)
+
+
+def test_given_current_state_is_used():
+    cfg = inputs.Config("j", 3, 2, 0.1, 10.0, 10.0)
+    ub, ab = inputs.state(cfg)
+    jb = np.random.default_rng(0).standard_normal((2, 16))
+    plan = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, jbar=jb)
+    ref = oracle.SpaceTimeSystem(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, jbar=jb)
+    assert np.array_equal(plan.export_jbar(), jb)
+    _compare(plan, ref)
+
+
+@pytest.mark.parametrize("n,nt", [(2, 1), (3, 2), (5, 4)])
+def test_plan_sizes_and_workspace(n, nt):
+    cfg = inputs.Config("s", n, nt, 0.1, 10.0, 10.0)
+    ub, ab = inputs.state(cfg)
+    plan = binding.Plan(n, nt, 0.1, 0.1, 0.1, 1.0, ub, ab, adjoint=True, precision="fp32")
+    lay = inputs.slab_sizes(n)
+    assert plan.ns == lay["slab"]
+    assert plan.workspace_bytes > 8 * plan.ns * nt * 60
