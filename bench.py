@@ -1,0 +1,159 @@
+"""Benchmark: space-time FGMRES time-to-1e-8 and DOF-iterations/s on one MI355X.
+
+A step is one FGMRES(30) solve to a true relative residual of 1e-8 of the whole
+linearised space-time MHD system (every slab at once) with the block
+preconditioner P_T applied in FP32 (Krylov, residual and least squares in
+FP64).  Workload (default): 64 x 64 mesh, Q2-Q1 velocity/pressure and Q1
+current/potential, Nt = 128 backward-Euler slabs, dt = 0.01, Re = S = 100,
+seeded smooth synthetic state and N(0,1) right-hand side.  The same solve with
+an FP64 preconditioner is timed beside it (speed-up of FP32 over FP64).
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ST-FGMRES time-to-1e-8 residual + DOF-iters/s; FP32-precond vs FP64, % HBM"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def jacobian_bytes(plan, nt, N):
+    """Algorithmic bytes of one J apply: every per-slab value once (8 B), every shared value
+    once (8 B), every index once (4 B, shared by all slabs), x read and y written (16 B/DOF)."""
+    state = sum(plan.block_nnz(b) for b in ("Fu", "Zj", "ZA", "Y", "FA"))
+    const = 2 * plan.block_nnz("B") + plan.block_nnz("Mj") + plan.block_nnz("KjA") + plan.block_nnz("Mu") \
+        + plan.block_nnz("MA")
+    return 8 * nt * state + 8 * const + 4 * (state + const) + 16 * N, state, const
+
+
+def cpu_baseline(cfg, nt_sample, rtol):
+    """The oracle (exact inner solves, GMRES(30)) on the first slabs of the same workload."""
+    import oracle
+    from paper_2309_00768_amd import inputs
+    ub, ab = inputs.state(cfg)
+    sysm = oracle.SpaceTimeSystem(cfg.n, nt_sample, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub[:nt_sample], ab[:nt_sample])
+    b = inputs.rhs(inputs.Config("s", cfg.n, nt_sample, cfg.dt, cfg.re, cfg.s), cfg.rhs_seeds[0])
+    sysm.apply_PT_inv(b)            # factorisations (setup) outside the timed region
+    t0 = time.perf_counter()
+    x, its, _ = oracle.solve_fgmres(sysm, b, rtol=rtol)
+    dt = time.perf_counter() - t0
+    return {"value": sysm.N * its / dt, "unit": "DOF-iter/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle GMRES(30)+P_T with sparse-LU inner solves to {rtol:g} on the first {nt_sample} of "
+                      f"{cfg.nt} slabs of the same workload (N={sysm.N}, {its} iterations, {dt:.1f} s; "
+                      f"single-threaded SuperLU/SciPy, host has {os.cpu_count()} logical CPUs)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="cfg3")
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-slabs", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (one system is not sharded "
+              f"across GPUs in this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2309_00768_amd import binding, inputs
+
+    cfg = inputs.CONFIGS[args.config]
+    ub, ab = inputs.state(cfg)
+    b = inputs.rhs(cfg, cfg.rhs_seeds[0])
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    plan32 = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp32")
+    N = plan32.ns * cfg.nt
+    jbytes, nnz_state, nnz_const = jacobian_bytes(plan32, cfg.nt, N)
+    sys32 = binding.System(plan32, dev)
+    plan32.close()
+    log(f"setup fp32 {time.perf_counter() - t0:.1f} s, N={N}")
+    sys64 = None
+    if not args.no_fp64:
+        t0 = time.perf_counter()
+        plan64 = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp64")
+        sys64 = binding.System(plan64, dev)
+        plan64.close()
+        log(f"setup fp64 {time.perf_counter() - t0:.1f} s")
+    bt = torch.from_numpy(b).to(dev)
+    x = torch.zeros_like(bt)
+
+    def solve(sysg):
+        _, info, rc, _ = sysg.solve(bt, x, rtol=args.rtol, restart=30)
+        if rc != 0:
+            raise RuntimeError(f"solve did not converge: status {rc}, residual {info.true_rel_residual:.2e}")
+        return info
+
+    for i in range(args.warmup):
+        info = solve(sys32)
+        log(f"warmup {i}: {info.iterations} its, {info.seconds:.3f} s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [solve(sys32) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    its = sum(i.iterations for i in infos)
+    value = N * its / elapsed
+    jac_s = sum(i.jacobian_seconds for i in infos)
+    jac_n = sum(i.jacobian_calls for i in infos)
+    jac_avg = jac_s / max(jac_n, 1)
+    res = max(i.true_rel_residual for i in infos)
+    log(f"fp32 precond: {its / args.steps:.1f} its/solve, {elapsed / args.steps:.3f} s/solve, residual {res:.2e}")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "DOF-iter/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32-precond/f64-krylov", "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {cfg.n}x{cfg.n} Q2-Q1/Q1/Q1, Nt={cfg.nt}, dt={cfg.dt}, "
+                               f"Re=S={cfg.re:g}; FGMRES(30) to {args.rtol:g}, P_T in FP32 with SA-AMG V(1,1) "
+                               f"Chebyshev-3 inner solves",
+                   "N": N, "nt": cfg.nt, "n": cfg.n},
+        "time_to_1e8_s": elapsed / args.steps,
+        "fgmres_iters": its / args.steps,
+        "true_rel_residual": res,
+        "precond_share": sum(i.precond_seconds for i in infos) / elapsed,
+    }
+    if sys64 is not None:
+        info64 = solve(sys64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info64 = solve(sys64)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        out["fp64_time_to_1e8_s"] = t64
+        out["fp64_fgmres_iters"] = info64.iterations
+        out["fp32_vs_fp64_speedup"] = t64 / (elapsed / args.steps)
+        log(f"fp64 precond: {info64.iterations} its, {t64:.3f} s")
+    achieved = jbytes / jac_avg / 1e9
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                       "kernel": "k_spmv<double,double,double,0> (space-time Jacobian apply)",
+                       "bytes_per_launch": jbytes, "avg_launch_ms": jac_avg * 1e3, "launches": jac_n,
+                       "nnz_state_per_slab": nnz_state, "nnz_shared": nnz_const}
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_slabs, args.rtol)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -108,6 +108,9 @@ typedef struct st_info {
   double true_rel_residual;  /* ||b - J x|| / ||b|| at exit (computed in FP64) */
   double seconds;     /* wall time of the solve (host clock, after sync)      */
   double precond_seconds;    /* time inside P_T^{-1} (event-timed)            */
+  double jacobian_seconds;   /* time inside the J applies (event-timed)       */
+  int jacobian_calls;        /* number of J applies in the solve              */
+  int precond_calls;         /* number of P_T^{-1} applies in the solve       */
 } st_info;
 
 typedef struct st_plan st_plan;       /* host-side setup result             */

@@ -47,6 +47,7 @@ class StInfo(ctypes.Structure):
     _fields_ = [
         ("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
         ("true_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double), ("precond_seconds", ctypes.c_double),
+        ("jacobian_seconds", ctypes.c_double), ("jacobian_calls", ctypes.c_int), ("precond_calls", ctypes.c_int),
     ]
 
 
@@ -162,6 +163,13 @@ class Plan:
         _check(lib().st_plan_export_block(self.ptr, bid, k, ctypes.byref(nr), ctypes.byref(nc), ctypes.byref(nnz),
                                           rp.ctypes.data_as(ip), ci.ctypes.data_as(ip), _dptr(v)), "export")
         return sp.csr_matrix((v, ci, rp), shape=(nr.value, nc.value))
+
+    def block_nnz(self, name, k=0):
+        nr, nc, nnz = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+        ip = ctypes.POINTER(ctypes.c_int)
+        _check(lib().st_plan_export_block(self.ptr, BLOCK_IDS[name], k, ctypes.byref(nr), ctypes.byref(nc),
+                                          ctypes.byref(nnz), ip(), ip(), ctypes.POINTER(ctypes.c_double)()), "nnz")
+        return nnz.value
 
     def export_jbar(self):
         out = np.empty((self.nt, (self.n + 1) ** 2))

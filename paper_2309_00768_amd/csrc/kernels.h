@@ -41,8 +41,16 @@ struct SpmvArgs {
   int64_t ystride;
 };
 
+// Kernel roles get distinct symbols so that profiles separate them.
+enum Role : int {
+  kRoleJ = 0,        // space-time Jacobian (or its transpose)
+  kRoleSlab = 1,     // slab-parallel products inside P_T
+  kRoleSweep = 2,    // sweep right-hand sides (coupling to earlier slabs)
+  kRoleAmg = 3,      // AMG residuals, restriction, prolongation
+};
+
 // y[v][row] = sum_seg alpha_seg (A_seg x_seg)[row] + beta b[v][row]
-template <class T, class TX, class TA>
+template <class T, class TX, class TA, int Role>
 __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs<T, TX> a) {
   const int v = blockIdx.y;
   const int slice = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
@@ -96,7 +104,8 @@ struct ChebArgs {
   int mode, step, x_add;
 };
 
-template <class T>
+// Role: 0 mass-matrix solves, 1 finest AMG level, 2 coarser AMG levels.
+template <class T, int Role>
 __global__ __launch_bounds__(kBlock) void k_cheb(ChebArgs<T> a) {
   const int v = blockIdx.y;
   const int slice = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);

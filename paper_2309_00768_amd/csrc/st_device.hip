@@ -146,7 +146,7 @@ Seg<T> seg(const DGroup& g, int s, int set_base, int set_step, const void* x, in
 
 template <class T, class TX>
 void spmv(hipStream_t s, const DGroup& g, int nvec, int nseg, const Seg<T>* segs, const TX* b, int64_t bstride,
-          double beta, TX* y, int64_t ystride) {
+          double beta, TX* y, int64_t ystride, int role = kRoleSlab) {
   SpmvArgs<T, TX> a;
   a.perm = g.perm;
   a.nslices = g.nslices;
@@ -159,21 +159,26 @@ void spmv(hipStream_t s, const DGroup& g, int nvec, int nseg, const Seg<T>* segs
   a.ystride = ystride;
   dim3 grid((g.nslices + 3) / 4, nvec);
   using TA = T;
-  hipLaunchKernelGGL((k_spmv<T, TX, TA>), grid, dim3(kBlock), 0, s, a);
+  switch (role) {
+    case kRoleJ: hipLaunchKernelGGL((k_spmv<T, TX, TA, kRoleJ>), grid, dim3(kBlock), 0, s, a); break;
+    case kRoleSweep: hipLaunchKernelGGL((k_spmv<T, TX, TA, kRoleSweep>), grid, dim3(kBlock), 0, s, a); break;
+    case kRoleAmg: hipLaunchKernelGGL((k_spmv<T, TX, TA, kRoleAmg>), grid, dim3(kBlock), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_spmv<T, TX, TA, kRoleSlab>), grid, dim3(kBlock), 0, s, a); break;
+  }
 }
 
 // y = alpha A x + beta b for a one-segment group, nvec vectors of length n.
 template <class T>
 void spmv1(hipStream_t s, const DGroup& g, int nvec, int set_base, int set_step, const T* x, int64_t xstride,
-           double alpha, const T* b, double beta, T* y, int64_t ystride) {
+           double alpha, const T* b, double beta, T* y, int64_t ystride, int role = kRoleSlab) {
   Seg<T> sg = seg<T>(g, 0, set_base, set_step, x, xstride, 0, 0, nvec, alpha);
-  spmv<T, T>(s, g, nvec, 1, &sg, b, ystride, beta, y, ystride);
+  spmv<T, T>(s, g, nvec, 1, &sg, b, ystride, beta, y, ystride, role);
 }
 
 template <class T>
 void cheb_launch(hipStream_t s, const DGroup& A, int nvec, int set_base, int set_step, const T* dinv,
                  int64_t dstride, const double* cheb, double theta, double delta, const T* b, T* r, T* x,
-                 const T* dold, T* dnew, int64_t vec, int mode, int step, int x_add) {
+                 const T* dold, T* dnew, int64_t vec, int mode, int step, int x_add, int role) {
   ChebArgs<T> a;
   a.perm = A.perm;
   a.nslices = A.nslices;
@@ -198,7 +203,9 @@ void cheb_launch(hipStream_t s, const DGroup& A, int nvec, int set_base, int set
   a.step = step;
   a.x_add = x_add;
   dim3 grid((A.nslices + 3) / 4, nvec);
-  hipLaunchKernelGGL((k_cheb<T>), grid, dim3(kBlock), 0, s, a);
+  if (role == 1) hipLaunchKernelGGL((k_cheb<T, 1>), grid, dim3(kBlock), 0, s, a);
+  else if (role == 2) hipLaunchKernelGGL((k_cheb<T, 2>), grid, dim3(kBlock), 0, s, a);
+  else hipLaunchKernelGGL((k_cheb<T, 0>), grid, dim3(kBlock), 0, s, a);
 }
 
 // Chebyshev-Jacobi polynomial solve of A x = b with `steps` steps from x = 0
@@ -206,16 +213,16 @@ void cheb_launch(hipStream_t s, const DGroup& A, int nvec, int set_base, int set
 template <class T>
 void cheb_solve(hipStream_t s, const DGroup& A, int nvec, int set_base, int set_step, const T* dinv,
                 int64_t dstride, const double* cheb, double theta, double delta, const T* b, T* x, T* r, T* d0,
-                T* d1, int64_t vec, int steps, int x_add, bool final_residual) {
+                T* d1, int64_t vec, int steps, int x_add, bool final_residual, int role = 0) {
   cheb_launch<T>(s, A, nvec, set_base, set_step, dinv, dstride, cheb, theta, delta, b, r, x, nullptr, d0, vec, 0, 0,
-                 x_add);
+                 x_add, role);
   T* d[2] = {d0, d1};
   for (int i = 1; i < steps; ++i)
     cheb_launch<T>(s, A, nvec, set_base, set_step, dinv, dstride, cheb, theta, delta, nullptr, r, x, d[(i - 1) % 2],
-                   d[i % 2], vec, 1, i, 1);
+                   d[i % 2], vec, 1, i, 1, role);
   if (final_residual)
     cheb_launch<T>(s, A, nvec, set_base, set_step, dinv, dstride, cheb, theta, delta, nullptr, r, x,
-                   d[(steps - 1) % 2], d[steps % 2], vec, 2, 0, 1);
+                   d[(steps - 1) % 2], d[steps % 2], vec, 2, 0, 1, role);
 }
 
 // ---------------------------------------------------------------- AMG ---
@@ -237,36 +244,38 @@ void vcycle(hipStream_t s, DAmg& a, int l, int nvec, int set_base, int set_step,
   if (coarsest) {
     const T* rhs = b;
     if (x_add) {   // x += Ainv (b - A x)
-      spmv1<T>(s, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec);
+      spmv1<T>(s, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec, kRoleAmg);
       rhs = r;
     }
     const int64_t istride = a.nsets > 1 ? int64_t(a.ncoarse) * a.ncoarse : 0;
     hipLaunchKernelGGL((k_coarse<T>), dim3(nvec), dim3(kBlock), 0, s, a.ncoarse, static_cast<const T*>(a.cinv),
                        istride, set_base, set_step, rhs, x, vec, x_add);
-    if (need_residual) spmv1<T>(s, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec);
+    if (need_residual) spmv1<T>(s, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec, kRoleAmg);
     return;
   }
   const int deg = a.deg;
+  const int crole = l == 0 ? 1 : 2;
   // pre-smoothing (leaves r = b - A x)
   if (x_add) {
-    spmv1<T>(s, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec);
+    spmv1<T>(s, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec, kRoleAmg);
     cheb_solve<T>(s, L.A, nvec, set_base, set_step, dinv, dstride, L.cheb, 0, 0, nullptr, x, r, d0, d1, vec, deg, 1,
-                  true);
+                  true, crole);
   } else {
-    cheb_solve<T>(s, L.A, nvec, set_base, set_step, dinv, dstride, L.cheb, 0, 0, b, x, r, d0, d1, vec, deg, 0, true);
+    cheb_solve<T>(s, L.A, nvec, set_base, set_step, dinv, dstride, L.cheb, 0, 0, b, x, r, d0, d1, vec, deg, 0, true,
+                  crole);
   }
   // coarse-grid correction
   DLevel& C = a.lev[l + 1];
   const int64_t cvec = C.n;
   T* cb = static_cast<T*>(a.buf[6 * (l + 1) + 1]);
   T* cx = static_cast<T*>(a.buf[6 * (l + 1) + 0]);
-  spmv1<T>(s, L.R, nvec, 0, 0, r, vec, 1.0, nullptr, 0.0, cb, cvec);
+  spmv1<T>(s, L.R, nvec, 0, 0, r, vec, 1.0, nullptr, 0.0, cb, cvec, kRoleAmg);
   vcycle<T>(s, a, l + 1, nvec, set_base, set_step, nullptr, nullptr, 0, false);
-  spmv1<T>(s, L.P, nvec, 0, 0, cx, cvec, 1.0, x, 1.0, x, vec);   // x += P x_c
+  spmv1<T>(s, L.P, nvec, 0, 0, cx, cvec, 1.0, x, 1.0, x, vec, kRoleAmg);   // x += P x_c
   // post-smoothing
-  spmv1<T>(s, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec);
+  spmv1<T>(s, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec, kRoleAmg);
   cheb_solve<T>(s, L.A, nvec, set_base, set_step, dinv, dstride, L.cheb, 0, 0, nullptr, x, r, d0, d1, vec, deg, 1,
-                need_residual);
+                need_residual, crole);
 }
 
 // Spatial solve A x = b with `iters` V-cycles (x starts from zero).
@@ -491,7 +500,7 @@ int precond_forward(Handle& H, const double* r, double* z, hipStream_t s) {
     int nsg = 0;
     if (k >= 1) sg[nsg++] = seg<T>(H.C1, 0, k - 1, 0, yA + int64_t(k - 1) * na, 0, 0, 0, 1, 1.0 / dt);
     if (k >= 2) sg[nsg++] = seg<T>(H.C1, 1, 0, 0, yA + int64_t(k - 2) * na, 0, 0, 0, 1, -1.0 / (dt * dt));
-    spmv<T, T>(s, H.C1, 1, nsg, sg, sA + int64_t(k) * na, 0, 1.0, rhs, 0);
+    spmv<T, T>(s, H.C1, 1, nsg, sg, sA + int64_t(k) * na, 0, 1.0, rhs, 0, kRoleSweep);
     amg_solve<T>(s, H.amgC0, 1, k, 0, yA + int64_t(k) * na, rhs, vc);
   }
   // 2. y_j = M_j^{-1} (r_j - K_jA y_A)
@@ -516,7 +525,7 @@ int precond_forward(Handle& H, const double* r, double* z, hipStream_t s) {
   for (int k = 0; k < nt; ++k) {
     T* rhs = static_cast<T*>(H.amgFu.buf[1]);
     Seg<T> sg = seg<T>(H.Mu, 0, 0, 0, xu + int64_t(k - 1) * nu, 0, 0, 0, 1, 1.0 / dt);
-    spmv<T, T>(s, H.Mu, 1, k >= 1 ? 1 : 0, &sg, yu + int64_t(k) * nu, 0, 1.0, rhs, 0);
+    spmv<T, T>(s, H.Mu, 1, k >= 1 ? 1 : 0, &sg, yu + int64_t(k) * nu, 0, 1.0, rhs, 0, kRoleSweep);
     amg_solve<T>(s, H.amgFu, 1, k, 0, xu + int64_t(k) * nu, rhs, vc);
   }
   // 6. join with the pressure normalisation 1^T M_p p = 0
@@ -555,7 +564,7 @@ int precond_transpose(Handle& H, const double* r, double* z, hipStream_t s) {
   for (int k = nt - 1; k >= 0; --k) {
     T* rhs = static_cast<T*>(H.amgFuT.buf[1]);
     Seg<T> sg = seg<T>(H.Mu, 0, 0, 0, xu + int64_t(k + 1) * nu, 0, 0, 0, 1, 1.0 / dt);
-    spmv<T, T>(s, H.Mu, 1, k + 1 < nt ? 1 : 0, &sg, ru + int64_t(k) * nu, 0, 1.0, rhs, 0);
+    spmv<T, T>(s, H.Mu, 1, k + 1 < nt ? 1 : 0, &sg, ru + int64_t(k) * nu, 0, 1.0, rhs, 0, kRoleSweep);
     amg_solve<T>(s, H.amgFuT, 1, k, 0, xu + int64_t(k) * nu, rhs, vc);
   }
   // x_p = S_p^{-T}(r_p - B x_u),  S_p^{-T} = -K_p^{-1} F_p^T M_p^{-1}
@@ -587,7 +596,7 @@ int precond_transpose(Handle& H, const double* r, double* z, hipStream_t s) {
     int nsg = 0;
     if (k + 1 < nt) sg[nsg++] = seg<T>(H.C1t, 0, k, 0, c + int64_t(k + 1) * na, 0, 0, 0, 1, 1.0 / dt);
     if (k + 2 < nt) sg[nsg++] = seg<T>(H.C1t, 1, 0, 0, c + int64_t(k + 2) * na, 0, 0, 0, 1, -1.0 / (dt * dt));
-    spmv<T, T>(s, H.C1t, 1, nsg, sg, ra + int64_t(k) * na, 0, 1.0, rhs, 0);
+    spmv<T, T>(s, H.C1t, 1, nsg, sg, ra + int64_t(k) * na, 0, 1.0, rhs, 0, kRoleSweep);
     amg_solve<T>(s, H.amgC0T, 1, k, 0, c + int64_t(k) * na, rhs, vc);
   }
   // f = F_A^T c; y_A = M_A^{-1} f
@@ -621,7 +630,7 @@ void apply_J(Handle& H, const double* x, double* y, hipStream_t s, bool transpos
       seg<double>(g, 0, 0, 1, x, ns, 0, 0, nt, alpha),
       seg<double>(g, 1, 0, 0, x, ns, 0, 0, nt, alpha),
       transpose ? seg<double>(g, 2, 0, 0, x, ns, 1, 0, nt - 1, alpha) : seg<double>(g, 2, 0, 0, x, ns, -1, 1, nt, alpha)};
-  spmv<double, double>(s, g, nt, 3, sg, b, ns, b ? 1.0 : 0.0, y, ns);
+  spmv<double, double>(s, g, nt, 3, sg, b, ns, b ? 1.0 : 0.0, y, ns, kRoleJ);
 }
 
 // ============================================================ FGMRES ===
@@ -662,7 +671,17 @@ int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* 
   Reducer red{H, s, at<double>(B, L.partial), N};
   double* hs = H.host_small;
   const int gr = grid_for(N);
-  std::vector<hipEvent_t> evs;
+  std::vector<hipEvent_t> evs, jevs;
+  auto jac = [&](const double* xin, double* yout, double alpha, const double* bb) {
+    hipEvent_t a, bev;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&bev);
+    (void)hipEventRecord(a, s);
+    apply_J(H, xin, yout, s, adjoint, alpha, bb);
+    (void)hipEventRecord(bev, s);
+    jevs.push_back(a);
+    jevs.push_back(bev);
+  };
   auto precond = [&](const double* r, double* z) {
     hipEvent_t a, bev;
     (void)hipEventCreate(&a);
@@ -702,7 +721,7 @@ int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* 
   }
   for (;;) {
     // r = bp - J x  -> V_0 (unnormalised), beta
-    apply_J(H, x, V, s, adjoint, -1.0, bp);
+    jac(x, V, -1.0, bp);
     red.dots(V, 1, V, sm + 0, 1);
     rc = fetch(sm, 1);
     if (rc) return rc;
@@ -722,7 +741,7 @@ int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* 
       double* vj = V + int64_t(j) * N;
       double* zj = Z + int64_t(j) * N;
       precond(vj, zj);
-      apply_J(H, zj, w, s, adjoint, 1.0, nullptr);
+      jac(zj, w, 1.0, nullptr);
       double* hcol = Hc + int64_t(j) * ldh;
       // CGS2: two classical Gram-Schmidt passes
       red.dots(V, j + 1, w, hcol, 0);
@@ -757,13 +776,20 @@ int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* 
                      x + d.off[2], int64_t(d.ns), d.np, d.nt, psum, 1.0 / H.msum);
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipGetLastError());
-  double pms = 0.0;
-  for (size_t i = 0; i + 1 < evs.size(); i += 2) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, evs[i], evs[i + 1]) == hipSuccess) pms += ms;
-    (void)hipEventDestroy(evs[i]);
-    (void)hipEventDestroy(evs[i + 1]);
-  }
+  auto elapsed = [](std::vector<hipEvent_t>& v) {
+    double acc = 0.0;
+    for (size_t i = 0; i + 1 < v.size(); i += 2) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, v[i], v[i + 1]) == hipSuccess) acc += ms;
+      (void)hipEventDestroy(v[i]);
+      (void)hipEventDestroy(v[i + 1]);
+    }
+    return acc;
+  };
+  const double pms = elapsed(evs), jms = elapsed(jevs);
+  info->precond_calls = int(evs.size() / 2);
+  info->jacobian_calls = int(jevs.size() / 2);
+  info->jacobian_seconds = jms * 1e-3;
   info->iterations = its;
   info->converged = status == ST_OK ? 1 : 0;
   info->true_rel_residual = true_res / bnorm;
