@@ -83,12 +83,20 @@ typedef struct st_problem {
   int mass_iters;     /* Chebyshev steps per mass-matrix solve (0: 12 AMG mode,
                          60 EXACT mode)                                        */
   int cheb_degree;    /* Chebyshev-Jacobi smoother degree (0: 3)              */
-  int fu_solver;      /* 0: AMG V-cycle on F_u,k; k>0: Chebyshev degree k only */
-  int ca_solver;      /* 0: AMG V-cycle on C_A,k; k>0: Chebyshev degree k only */
+  int fu_solver;      /* inner solver of F_u,k in AMG mode: 0 auto (from the
+                         estimated condition number of D^{-1} F_u), -1 one SA-AMG
+                         V(1,1) cycle, k > 0 Chebyshev-Jacobi of degree k alone */
+  int ca_solver;      /* the same for the wave blocks C_A,k                   */
   int max_restart;    /* largest FGMRES restart length the workspace holds (0: 30) */
   int sell_sigma;     /* SELL sorting window in rows (0: whole matrix)        */
   int adjoint;        /* 1: also build the transposed operators (J^T, P_T^{-T}) */
-  int reserved[7];
+  int j_lanes;        /* wavefront lanes per row of the J apply (0: auto)     */
+  int reserved[6];
+  double inner_reduction; /* auto inner solver of F_u,k: target error reduction
+                             per spatial solve (0: 0.1)                        */
+  double ca_reduction;    /* auto inner solver of C_A,k: target reduction (0:
+                             min(0.05, 0.25/Nt); the C_A sweep is a second-order
+                             recursion in time that accumulates inner errors)  */
 } st_problem;
 
 typedef struct st_opts {
@@ -136,6 +144,11 @@ int st_plan_sizes(const st_plan* plan, int* ns, int offsets[6]);
  * 15 C2 (band -2).  Call with rowptr == NULL to get nrows, ncols, nnz first. */
 int st_plan_export_block(const st_plan* plan, int block, int k, int* nrows, int* ncols,
                          int64_t* nnz, int* rowptr, int* colind, double* val);
+
+/* Inner solvers chosen by the setup: Chebyshev degree used alone on F_u,k and
+ * C_A,k (0 = SA-AMG V-cycle) and the estimated condition numbers of D^{-1} A. */
+int st_plan_solver_info(const st_plan* plan, int* fu_degree, int* ca_degree, double* fu_kappa,
+                        double* ca_kappa);
 
 /* The current state used (either given or computed), host [nt][(n+1)^2]. */
 int st_plan_export_jbar(const st_plan* plan, double* jbar);

@@ -32,7 +32,8 @@ class StProblem(ctypes.Structure):
         ("precond_precision", ctypes.c_int), ("inner_mode", ctypes.c_int), ("inner_iters", ctypes.c_int),
         ("mass_iters", ctypes.c_int), ("cheb_degree", ctypes.c_int), ("fu_solver", ctypes.c_int),
         ("ca_solver", ctypes.c_int), ("max_restart", ctypes.c_int), ("sell_sigma", ctypes.c_int),
-        ("adjoint", ctypes.c_int), ("reserved", ctypes.c_int * 7),
+        ("adjoint", ctypes.c_int), ("j_lanes", ctypes.c_int), ("reserved", ctypes.c_int * 6),
+        ("inner_reduction", ctypes.c_double), ("ca_reduction", ctypes.c_double),
     ]
 
 
@@ -53,6 +54,7 @@ class StInfo(ctypes.Structure):
 
 EXPORTED = [
     "st_plan_create", "st_plan_workspace_size", "st_plan_sizes", "st_plan_export_block", "st_plan_export_jbar",
+    "st_plan_solver_info",
     "st_plan_destroy", "st_create", "st_destroy", "st_apply_jacobian", "st_apply_jacobian_t",
     "st_apply_precond", "st_apply_precond_t", "st_fgmres_solve", "st_adjoint_solve", "st_sizes",
     "st_error_string",
@@ -72,6 +74,7 @@ def _load(path=LIB_PATH):
         "st_plan_sizes": ([vp, ip, ip], ctypes.c_int),
         "st_plan_export_block": ([vp, ctypes.c_int, ctypes.c_int, ip, ip, i64p, ip, ip, dp], ctypes.c_int),
         "st_plan_export_jbar": ([vp, dp], ctypes.c_int),
+        "st_plan_solver_info": ([vp, ip, ip, dp, dp], ctypes.c_int),
         "st_plan_destroy": ([vp], ctypes.c_int),
         "st_create": ([vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)], ctypes.c_int),
         "st_destroy": ([vp], ctypes.c_int),
@@ -122,7 +125,8 @@ class Plan:
     """Host-side setup of one space-time system (``st_plan_create``)."""
 
     def __init__(self, n, nt, dt, mu, eta, mu0, ubar, abar, jbar=None, precision="fp64", inner="amg",
-                 inner_iters=0, mass_iters=0, cheb_degree=0, max_restart=0, sell_sigma=0, adjoint=False):
+                 inner_iters=0, mass_iters=0, cheb_degree=0, max_restart=0, sell_sigma=0, adjoint=False,
+                 fu_solver=0, ca_solver=0, inner_reduction=0.0, j_lanes=0, ca_reduction=0.0):
         self._ub = np.ascontiguousarray(ubar, dtype=np.float64)
         self._ab = np.ascontiguousarray(abar, dtype=np.float64)
         assert self._ub.shape == (nt, 2, (2 * n + 1) ** 2) and self._ab.shape == (nt, (n + 1) ** 2)
@@ -135,6 +139,8 @@ class Plan:
         p.inner_mode = ST_INNER_EXACT if inner == "exact" else ST_INNER_AMG
         p.inner_iters, p.mass_iters, p.cheb_degree = inner_iters, mass_iters, cheb_degree
         p.max_restart, p.sell_sigma, p.adjoint = max_restart, sell_sigma, int(adjoint)
+        p.fu_solver, p.ca_solver, p.inner_reduction, p.j_lanes = fu_solver, ca_solver, inner_reduction, j_lanes
+        p.ca_reduction = ca_reduction
         self.problem = p
         self.n, self.nt = n, nt
         h = ctypes.c_void_p()
@@ -170,6 +176,14 @@ class Plan:
         _check(lib().st_plan_export_block(self.ptr, BLOCK_IDS[name], k, ctypes.byref(nr), ctypes.byref(nc),
                                           ctypes.byref(nnz), ip(), ip(), ctypes.POINTER(ctypes.c_double)()), "nnz")
         return nnz.value
+
+    def solver_info(self):
+        """(fu_degree, ca_degree, fu_kappa, ca_kappa) chosen by the setup (degree 0 = AMG)."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        c, d = ctypes.c_double(), ctypes.c_double()
+        _check(lib().st_plan_solver_info(self.ptr, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                         ctypes.byref(d)), "solver_info")
+        return a.value, b.value, c.value, d.value
 
     def export_jbar(self):
         out = np.empty((self.nt, (self.n + 1) ** 2))

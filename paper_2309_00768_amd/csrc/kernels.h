@@ -32,6 +32,7 @@ template <class T, class TX>
 struct SpmvArgs {
   const int* perm;
   int nslices;
+  int lanes;            // lanes per row (1, 2, 4, 8, 16)
   int nseg;
   Seg<T> seg[3];
   const TX* b;          // optional: y = sum + beta * b
@@ -39,6 +40,14 @@ struct SpmvArgs {
   double beta;
   TX* y;
   int64_t ystride;
+  // Epilogue 1 (first Chebyshev step of a sweep solve, one vector): with
+  // q = sum + beta b, write r = q, d = dinv q / theta, x = d.
+  int epi;
+  const T* dinv;
+  double theta;
+  TX* r;
+  TX* d;
+  TX* x;
 };
 
 // Kernel roles get distinct symbols so that profiles separate them.
@@ -49,15 +58,22 @@ enum Role : int {
   kRoleAmg = 3,      // AMG residuals, restriction, prolongation
 };
 
+template <class TA>
+__device__ inline TA group_sum(TA v, int lanes) {
+  for (int off = lanes / 2; off > 0; off /= 2) v += __shfl_down(v, off, lanes);
+  return v;
+}
+
 // y[v][row] = sum_seg alpha_seg (A_seg x_seg)[row] + beta b[v][row]
 template <class T, class TX, class TA, int Role>
 __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs<T, TX> a) {
   const int v = blockIdx.y;
   const int slice = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
-  if (slice >= a.nslices) return;
+  if (slice >= a.nslices) return;          // uniform per wavefront
   const int lane = threadIdx.x % kWave;
-  const int row = a.perm[slice * kWave + lane];
-  if (row < 0) return;
+  const int L = a.lanes;
+  const int q = lane / L, sub = lane % L;
+  const int row = a.perm[slice * (kWave / L) + q];
   TA acc = TA(0);
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
@@ -66,15 +82,23 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs<T, TX> a) {
     if (v < g.vlo || v >= g.vhi) continue;
     const int beg = g.sptr[slice];
     const int w = (g.sptr[slice + 1] - beg) / kWave;
-    const T* val = g.val + (g.vstride ? int64_t(g.set_base + v * g.set_step) * g.vstride : 0);
+    const T* val = g.val + (g.vstride ? int64_t(g.set_base + v * g.set_step) * g.vstride : 0) + beg + lane;
     const TX* x = static_cast<const TX*>(g.x) + int64_t(v + g.xshift) * g.xstride;
     const int* col = g.col + beg + lane;
-    val += beg + lane;
     TA sum = TA(0);
     for (int j = 0; j < w; ++j) sum += TA(val[j * kWave]) * TA(x[col[j * kWave]]);
     acc += TA(g.alpha) * sum;
   }
+  acc = group_sum(acc, L);
+  if (sub != 0 || row < 0) return;
   if (a.b) acc += TA(a.beta) * TA(a.b[int64_t(v) * a.bstride + row]);
+  if (a.epi == 1) {
+    const TX dd = TX(TA(a.dinv[row]) * acc / TA(a.theta));
+    a.r[row] = TX(acc);
+    a.d[row] = dd;
+    a.x[row] = dd;
+    return;
+  }
   a.y[int64_t(v) * a.ystride + row] = TX(acc);
 }
 
@@ -86,6 +110,7 @@ template <class T>
 struct ChebArgs {
   const int* perm;
   int nslices;
+  int lanes;
   const int* sptr;
   const int* col;
   const T* val;
@@ -104,15 +129,16 @@ struct ChebArgs {
   int mode, step, x_add;
 };
 
-// Role: 0 mass-matrix solves, 1 finest AMG level, 2 coarser AMG levels.
+// Role: 0 mass-matrix solves, 1 finest AMG level / single-level solves, 2 coarser AMG levels.
 template <class T, int Role>
 __global__ __launch_bounds__(kBlock) void k_cheb(ChebArgs<T> a) {
   const int v = blockIdx.y;
   const int slice = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
-  if (slice >= a.nslices) return;
+  if (slice >= a.nslices) return;          // uniform per wavefront
   const int lane = threadIdx.x % kWave;
-  const int row = a.perm[slice * kWave + lane];
-  if (row < 0) return;
+  const int L = a.lanes;
+  const int q = lane / L, sub = lane % L;
+  const int row = a.perm[slice * (kWave / L) + q];
   const int set = a.set_base + v * a.set_step;
   double theta = a.theta, delta = a.delta;
   if (a.cheb) {
@@ -120,8 +146,9 @@ __global__ __launch_bounds__(kBlock) void k_cheb(ChebArgs<T> a) {
     delta = a.cheb[2 * set + 1];
   }
   const int64_t o = int64_t(v) * a.vec;
-  const T dg = a.dinv[(a.dstride ? int64_t(set) * a.dstride : 0) + row];
   if (a.mode == 0) {
+    if (sub != 0 || row < 0) return;
+    const T dg = a.dinv[(a.dstride ? int64_t(set) * a.dstride : 0) + row];
     const T rr = a.b ? a.b[o + row] : a.r[o + row];
     if (a.b) a.r[o + row] = rr;
     const T d = T(dg * rr / T(theta));
@@ -136,9 +163,12 @@ __global__ __launch_bounds__(kBlock) void k_cheb(ChebArgs<T> a) {
   const T* d0 = a.dold + o;
   T sum = T(0);
   for (int j = 0; j < w; ++j) sum += val[j * kWave] * d0[col[j * kWave]];
+  sum = group_sum(sum, L);
+  if (sub != 0 || row < 0) return;
   const T rn = a.r[o + row] - sum;
   a.r[o + row] = rn;
   if (a.mode == 2) return;
+  const T dg = a.dinv[(a.dstride ? int64_t(set) * a.dstride : 0) + row];
   // Chebyshev recurrence coefficients for step `step` (rho_0 = delta/theta).
   const double sigma = theta / delta;
   double rho_prev = 1.0 / sigma, rho = rho_prev;

@@ -3,6 +3,7 @@
 // the pieces of P_T (eq. (PT)) and the AMG hierarchies, and packs everything
 // into a device image that st_create() uploads in one copy.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <new>
 
@@ -158,7 +159,7 @@ static int build_plan(Plan& P, std::string& err) {
     Csr C = fuse(ns, ns, 1, {{&b.Bt, 0, o2, 1.0}, {&b.B, o2, 0, 1.0}, {&b.Mj, o3, o3, 1.0},
                              {&b.KjA, o3, o4, 1.0}});
     Csr Pv = fuse(ns, ns, 1, {{&b.Mu, 0, 0, -1.0 / b.dt}, {&b.MA, o4, o4, -1.0 / b.dt}});
-    P.J = pack_sell(img, {&S, &C, &Pv}, 0, sigma);
+    P.J = pack_sell(img, {&S, &C, &Pv}, 0, sigma, pr.j_lanes);
   }
   if (pr.adjoint) {
     Csr FuT = csr_transpose(b.Fu), YT = csr_transpose(b.Y), ZjT = csr_transpose(b.Zj),
@@ -168,7 +169,7 @@ static int build_plan(Plan& P, std::string& err) {
     Csr C = fuse(ns, ns, 1, {{&b.Bt, 0, o2, 1.0}, {&b.B, o2, 0, 1.0}, {&b.Mj, o3, o3, 1.0},
                              {&b.KjAt, o4, o3, 1.0}});
     Csr Pv = fuse(ns, ns, 1, {{&b.Mu, 0, 0, -1.0 / b.dt}, {&b.MA, o4, o4, -1.0 / b.dt}});
-    P.JT = pack_sell(img, {&S, &C, &Pv}, 0, sigma);
+    P.JT = pack_sell(img, {&S, &C, &Pv}, 0, sigma, pr.j_lanes);
   }
 
   // ------------------------------------------------------- P_T pieces
@@ -223,6 +224,26 @@ static int build_plan(Plan& P, std::string& err) {
     if (rc) return rc;
     rc = build_amg(img, C0T, nt, Grid2{n - 1, n - 1, 1}, fp, cheb, sigma, false, P.amgC0T, err);
     if (rc) return rc;
+  }
+  // Spatial solver of the two sweeps: Chebyshev-Jacobi alone when D^{-1} A is
+  // well conditioned (it then needs a few kernels per slab instead of a whole
+  // V-cycle), otherwise one SA-AMG V(1,1) cycle.  D^{-1} A^T has the spectrum
+  // of D^{-1} A, so the transposed sweeps reuse the interval.
+  estimate_interval(img, b.Fu, nt, P.amgFu);
+  estimate_interval(img, b.C0, nt, P.amgC0);
+  {
+    const double red_fu = pr.inner_reduction > 0 ? pr.inner_reduction : 0.1;
+    const double red_ca = pr.ca_reduction > 0 ? pr.ca_reduction : std::min(0.05, 0.25 / nt);
+    auto pick = [&](int opt, const Amg& a, double red) -> int {
+      if (P.exact || opt < 0) return 0;
+      if (opt > 0) return opt;
+      if (a.kappa > 60.0) return 0;
+      const double sk = std::sqrt(a.kappa), r = (sk - 1.0) / (sk + 1.0);
+      int deg = int(std::ceil(std::log(red / 2.0) / std::log(r)));
+      return std::max(2, std::min(16, deg));
+    };
+    P.fu_deg = pick(pr.fu_solver, P.amgFu, red_fu);
+    P.ca_deg = pick(pr.ca_solver, P.amgC0, red_ca);
   }
 
   // pressure normalisation weights m = 1^T M_p (FP64)
@@ -312,6 +333,15 @@ int st_plan_export_block(const st_plan* plan, int block, int k, int* nrows, int*
   std::copy(m->ci.begin(), m->ci.end(), colind);
   const size_t s = nsets > 1 ? size_t(k) : 0;
   std::copy(m->v.begin() + s * z, m->v.begin() + (s + 1) * z, val);
+  return ST_OK;
+}
+
+int st_plan_solver_info(const st_plan* plan, int* fu_degree, int* ca_degree, double* fu_kappa, double* ca_kappa) {
+  if (!plan) return ST_EINVAL;
+  if (fu_degree) *fu_degree = plan->p.fu_deg;
+  if (ca_degree) *ca_degree = plan->p.ca_deg;
+  if (fu_kappa) *fu_kappa = plan->p.amgFu.kappa;
+  if (ca_kappa) *ca_kappa = plan->p.amgC0.kappa;
   return ST_OK;
 }
 

@@ -114,18 +114,33 @@ Span put_converted(Image& img, const std::vector<double>& v, int fp32) {
 }  // namespace
 
 // ---------------------------------------------------------------- SELL ---
-SellGroup pack_sell(Image& img, const std::vector<const Csr*>& mats, int fp32, int sigma) {
+int auto_lanes(double mean) {
+  // Keep each lane's loop near 6-12 entries: long per-lane loops are latency-bound
+  // on small matrices, where few waves are in flight.
+  int l = 1;
+  while (l < 16 && mean / (2 * l) >= 6.0) l *= 2;
+  return l;
+}
+
+SellGroup pack_sell(Image& img, const std::vector<const Csr*>& mats, int fp32, int sigma, int lanes) {
   SellGroup g;
   g.nseg = int(mats.size());
   g.nrows = mats[0]->nr;
   g.ncols = mats[0]->nc;
   g.fp32 = fp32;
   const int nr = g.nrows;
-  g.nslices = (nr + kSlice - 1) / kSlice;
   // Row order: descending total row length inside windows of `sigma` rows.
   std::vector<int> total(nr, 0);
+  int64_t sum = 0;
   for (const Csr* m : mats)
-    for (int r = 0; r < nr; ++r) total[r] += m->rp[r + 1] - m->rp[r];
+    for (int r = 0; r < nr; ++r) {
+      total[r] += m->rp[r + 1] - m->rp[r];
+      sum += m->rp[r + 1] - m->rp[r];
+    }
+  if (lanes <= 0) lanes = auto_lanes(nr ? double(sum) / nr : 0.0);
+  g.lanes = lanes;
+  const int rps = kSlice / lanes;   // rows per slice
+  g.nslices = (nr + rps - 1) / rps;
   std::vector<int> order(nr);
   std::iota(order.begin(), order.end(), 0);
   const int win = sigma <= 0 ? nr : sigma;
@@ -133,7 +148,7 @@ SellGroup pack_sell(Image& img, const std::vector<const Csr*>& mats, int fp32, i
     const int e = std::min(nr, b + win);
     std::stable_sort(order.begin() + b, order.begin() + e, [&](int x, int y) { return total[x] > total[y]; });
   }
-  std::vector<int> perm(size_t(g.nslices) * kSlice, -1);
+  std::vector<int> perm(size_t(g.nslices) * rps, -1);
   for (int i = 0; i < nr; ++i) perm[i] = order[i];
   g.perm = img.put(perm);
   for (int si = 0; si < g.nseg; ++si) {
@@ -145,9 +160,9 @@ SellGroup pack_sell(Image& img, const std::vector<const Csr*>& mats, int fp32, i
     std::vector<int> sptr(g.nslices + 1, 0);
     for (int sl = 0; sl < g.nslices; ++sl) {
       int w = 0;
-      for (int l = 0; l < kSlice; ++l) {
-        const int r = perm[size_t(sl) * kSlice + l];
-        if (r >= 0) w = std::max(w, m.rp[r + 1] - m.rp[r]);
+      for (int q = 0; q < rps; ++q) {
+        const int r = perm[size_t(sl) * rps + q];
+        if (r >= 0) w = std::max(w, (m.rp[r + 1] - m.rp[r] + lanes - 1) / lanes);
       }
       sptr[sl + 1] = sptr[sl] + w * kSlice;
     }
@@ -155,14 +170,14 @@ SellGroup pack_sell(Image& img, const std::vector<const Csr*>& mats, int fp32, i
     std::vector<int> col(s.total, 0);
     std::vector<double> val(size_t(s.nsets) * s.total, 0.0);
     for (int sl = 0; sl < g.nslices; ++sl)
-      for (int l = 0; l < kSlice; ++l) {
-        const int r = perm[size_t(sl) * kSlice + l];
+      for (int q = 0; q < rps; ++q) {
+        const int r = perm[size_t(sl) * rps + q];
         if (r < 0) continue;
         int j = 0;
         for (int p = m.rp[r]; p < m.rp[r + 1]; ++p, ++j) {
-          const int64_t q = sptr[sl] + int64_t(j) * kSlice + l;
-          col[q] = m.ci[p];
-          for (int st = 0; st < s.nsets; ++st) val[size_t(st) * s.total + q] = m.v[size_t(st) * z + p];
+          const int64_t at = sptr[sl] + int64_t(j / lanes) * kSlice + q * lanes + (j % lanes);
+          col[at] = m.ci[p];
+          for (int st = 0; st < s.nsets; ++st) val[size_t(st) * s.total + at] = m.v[size_t(st) * z + p];
         }
       }
     s.sptr = img.put(sptr);
@@ -170,6 +185,48 @@ SellGroup pack_sell(Image& img, const std::vector<const Csr*>& mats, int fp32, i
     s.val = fp32 ? put_converted<float>(img, val, 1) : img.put(val);
   }
   return g;
+}
+
+// --------------------------------------------------- spectral interval ---
+void estimate_interval(Image& img, const Csr& a, int nsets, Amg& out) {
+  const int n = a.nr;
+  out.cheb_alone.assign(size_t(nsets) * 2, 0.0);
+  std::vector<double> kap(nsets, 0.0);
+  const int64_t z = a.nnz();
+  parallel_for(nsets, host_threads(), [&](int s) {
+    std::vector<double> di = diag_of(a, s);
+    for (auto& x : di) x = x != 0.0 ? 1.0 / x : 0.0;
+    const double lmax = lambda_max(a, s, di);
+    // Shifted power iteration on sigma I - D^{-1} A for the low end.
+    const double sig = 1.05 * lmax;
+    const double* v = a.v.data() + size_t(s) * z;
+    std::vector<double> x(n), y(n);
+    for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.29 * std::cos(0.9 * i + 0.7);
+    double mu = 0.0;
+    for (int it = 0; it < 80; ++it) {
+      double nx = 0;
+      for (double t : x) nx += t * t;
+      nx = std::sqrt(nx);
+      for (auto& t : x) t /= nx;
+      double ny = 0;
+      for (int r = 0; r < n; ++r) {
+        double acc = 0;
+        for (int p = a.rp[r]; p < a.rp[r + 1]; ++p) acc += v[p] * x[a.ci[p]];
+        y[r] = sig * x[r] - acc * di[r];
+        ny += y[r] * y[r];
+      }
+      mu = std::sqrt(ny);
+      std::swap(x, y);
+    }
+    double lmin = sig - mu;
+    // Widen: the power estimates approach the extreme eigenvalues from inside.
+    const double lo = std::max(0.7 * lmin, 1e-3 * lmax), hi = 1.1 * lmax;
+    out.cheb_alone[2 * s] = 0.5 * (hi + lo);
+    out.cheb_alone[2 * s + 1] = 0.5 * (hi - lo);
+    kap[s] = hi / lo;
+  });
+  out.kappa = *std::max_element(kap.begin(), kap.end());
+  out.cheb_alone_span = img.put(out.cheb_alone);
 }
 
 // ----------------------------------------------------------------- AMG ---

@@ -27,7 +27,7 @@ namespace st {
 // ------------------------------------------------------ device mirrors ---
 struct DGroup {
   const int* perm = nullptr;
-  int nrows = 0, nslices = 0, nseg = 0;
+  int nrows = 0, nslices = 0, nseg = 0, lanes = 1;
   const int* sptr[3] = {nullptr, nullptr, nullptr};
   const int* col[3] = {nullptr, nullptr, nullptr};
   const void* val[3] = {nullptr, nullptr, nullptr};
@@ -45,6 +45,8 @@ struct DAmg {
   std::vector<DLevel> lev;
   int nsets = 1, deg = 3, ncoarse = 0;
   const void* cinv = nullptr;
+  std::vector<double> alone;            // host copy of the Chebyshev-alone intervals
+  const double* alone_dev = nullptr;
   // scratch: 6 vectors per level (x, b, r, d0, d1, e)
   std::vector<void*> buf;
 };
@@ -54,6 +56,7 @@ struct Handle {
   Dims d;
   double dt = 0;
   int fp32 = 0, exact = 0, inner_iters = 1, mass_iters = 12, max_restart = 30, adjoint = 0;
+  int fu_deg = 0, ca_deg = 0;
   char* base = nullptr;
   WsLayout L;
   DGroup J, JT, MA, Mj, Mp, FA, FAt, Fp, Fpt, KjA, KjAt, Bt, B, Zj, Zjt, ZAt, Mu, C1, C1t;
@@ -93,6 +96,7 @@ DGroup mirror(char* base, const SellGroup& g) {
   d.nrows = g.nrows;
   d.nslices = g.nslices;
   d.nseg = g.nseg;
+  d.lanes = g.lanes;
   if (!g.nrows) return d;
   d.perm = at<int>(base, g.perm.off);
   for (int s = 0; s < g.nseg; ++s) {
@@ -121,6 +125,8 @@ DAmg mirror_amg(char* base, const Amg& a, const std::vector<size_t>& bufs) {
     d.lev.push_back(dl);
   }
   for (size_t o : bufs) d.buf.push_back(base + o);
+  d.alone = a.cheb_alone;
+  if (!a.cheb_alone.empty()) d.alone_dev = at<double>(base, a.cheb_alone_span.off);
   return d;
 }
 
@@ -144,19 +150,39 @@ Seg<T> seg(const DGroup& g, int s, int set_base, int set_step, const void* x, in
   return r;
 }
 
+struct Epilogue {
+  int kind = 0;
+  const void* dinv = nullptr;
+  double theta = 1.0;
+  void *r = nullptr, *d = nullptr, *x = nullptr;
+};
+
 template <class T, class TX>
 void spmv(hipStream_t s, const DGroup& g, int nvec, int nseg, const Seg<T>* segs, const TX* b, int64_t bstride,
-          double beta, TX* y, int64_t ystride, int role = kRoleSlab) {
+          double beta, TX* y, int64_t ystride, int role = kRoleSlab, const Epilogue* ep = nullptr) {
   SpmvArgs<T, TX> a;
   a.perm = g.perm;
   a.nslices = g.nslices;
+  a.lanes = g.lanes;
   a.nseg = nseg;
+  a.epi = 0;
+  a.dinv = nullptr;
+  a.theta = 1.0;
+  a.r = a.d = a.x = nullptr;
   for (int i = 0; i < nseg; ++i) a.seg[i] = segs[i];
   a.b = b;
   a.bstride = bstride;
   a.beta = beta;
   a.y = y;
   a.ystride = ystride;
+  if (ep && ep->kind == 1) {
+    a.epi = 1;
+    a.dinv = static_cast<const T*>(ep->dinv);
+    a.theta = ep->theta;
+    a.r = static_cast<TX*>(ep->r);
+    a.d = static_cast<TX*>(ep->d);
+    a.x = static_cast<TX*>(ep->x);
+  }
   dim3 grid((g.nslices + 3) / 4, nvec);
   using TA = T;
   switch (role) {
@@ -182,6 +208,7 @@ void cheb_launch(hipStream_t s, const DGroup& A, int nvec, int set_base, int set
   ChebArgs<T> a;
   a.perm = A.perm;
   a.nslices = A.nslices;
+  a.lanes = A.lanes;
   a.sptr = A.sptr[0];
   a.col = A.col[0];
   a.val = static_cast<const T*>(A.val[0]);
@@ -462,6 +489,40 @@ inline int grid_for(int64_t n) {
   return int(b);
 }
 
+// One sweep step: x = A_k^{-1} (q + coupling), the coupling given as segments
+// of `cg` acting on earlier (or later) slabs.  With deg > 0 the solve is
+// Chebyshev-Jacobi alone of that degree, its first step fused into the
+// coupling product; otherwise the right-hand side is formed and `vc`
+// V-cycles of the hierarchy are applied.
+template <class T>
+void sweep_step(hipStream_t s, DAmg& a, const DGroup& cg, int nseg, const Seg<T>* segs, const T* q, T* x, int k,
+                int deg, int vc) {
+  T* rhs = static_cast<T*>(a.buf[1]);
+  if (deg <= 0) {
+    spmv<T, T>(s, cg, 1, nseg, segs, q, 0, 1.0, rhs, 0, kRoleSweep);
+    amg_solve<T>(s, a, 1, k, 0, x, rhs, vc);
+    return;
+  }
+  DLevel& L = a.lev[0];
+  T* r = static_cast<T*>(a.buf[2]);
+  T* d0 = static_cast<T*>(a.buf[3]);
+  T* d1 = static_cast<T*>(a.buf[4]);
+  const int64_t dstride = a.nsets > 1 ? L.n : 0;
+  const T* dinv = static_cast<const T*>(L.dinv) + (a.nsets > 1 ? int64_t(k) * L.n : 0);
+  Epilogue ep;
+  ep.kind = 1;
+  ep.dinv = dinv;
+  ep.theta = a.alone[2 * (a.nsets > 1 ? k : 0)];
+  ep.r = r;
+  ep.d = d0;
+  ep.x = x;
+  spmv<T, T>(s, cg, 1, nseg, segs, q, 0, 1.0, rhs, 0, kRoleSweep, &ep);
+  T* d[2] = {d0, d1};
+  for (int i = 1; i < deg; ++i)
+    cheb_launch<T>(s, L.A, 1, a.nsets > 1 ? k : 0, 0, static_cast<const T*>(L.dinv), dstride, a.alone_dev, 0, 0,
+                   nullptr, r, x, d[(i - 1) % 2], d[i % 2], L.n, 1, i, 1, 1);
+}
+
 // ================================================= P_T^{-1} (forward) ===
 template <class T>
 int precond_forward(Handle& H, const double* r, double* z, hipStream_t s) {
@@ -495,13 +556,11 @@ int precond_forward(Handle& H, const double* r, double* z, hipStream_t s) {
     spmv<T, T>(s, H.FA, nt, 2, sg, nullptr, na, 0.0, sA, na);
   }
   for (int k = 0; k < nt; ++k) {
-    T* rhs = static_cast<T*>(H.amgC0.buf[1]);   // level-0 b of the C_A hierarchy
     Seg<T> sg[2];
     int nsg = 0;
     if (k >= 1) sg[nsg++] = seg<T>(H.C1, 0, k - 1, 0, yA + int64_t(k - 1) * na, 0, 0, 0, 1, 1.0 / dt);
     if (k >= 2) sg[nsg++] = seg<T>(H.C1, 1, 0, 0, yA + int64_t(k - 2) * na, 0, 0, 0, 1, -1.0 / (dt * dt));
-    spmv<T, T>(s, H.C1, 1, nsg, sg, sA + int64_t(k) * na, 0, 1.0, rhs, 0, kRoleSweep);
-    amg_solve<T>(s, H.amgC0, 1, k, 0, yA + int64_t(k) * na, rhs, vc);
+    sweep_step<T>(s, H.amgC0, H.C1, nsg, sg, sA + int64_t(k) * na, yA + int64_t(k) * na, k, H.ca_deg, vc);
   }
   // 2. y_j = M_j^{-1} (r_j - K_jA y_A)
   spmv1<T>(s, H.KjA, nt, 0, 0, yA, na, -1.0, rj, 1.0, rj, nj);
@@ -523,10 +582,8 @@ int precond_forward(Handle& H, const double* r, double* z, hipStream_t s) {
   // 5. x_u = F_u^{-1} (y_u - B^T x_p), x_p carrying the minus sign: y_u + B^T xp
   spmv1<T>(s, H.Bt, nt, 0, 0, xp, np, 1.0, yu, 1.0, yu, nu);
   for (int k = 0; k < nt; ++k) {
-    T* rhs = static_cast<T*>(H.amgFu.buf[1]);
     Seg<T> sg = seg<T>(H.Mu, 0, 0, 0, xu + int64_t(k - 1) * nu, 0, 0, 0, 1, 1.0 / dt);
-    spmv<T, T>(s, H.Mu, 1, k >= 1 ? 1 : 0, &sg, yu + int64_t(k) * nu, 0, 1.0, rhs, 0, kRoleSweep);
-    amg_solve<T>(s, H.amgFu, 1, k, 0, xu + int64_t(k) * nu, rhs, vc);
+    sweep_step<T>(s, H.amgFu, H.Mu, k >= 1 ? 1 : 0, &sg, yu + int64_t(k) * nu, xu + int64_t(k) * nu, k, H.fu_deg, vc);
   }
   // 6. join with the pressure normalisation 1^T M_p p = 0
   hipLaunchKernelGGL((k_slab_sums_t<T>), dim3(nt), dim3(kBlock), 0, s, xp, int64_t(np), np, H.mp_rowsum,
@@ -562,10 +619,9 @@ int precond_transpose(Handle& H, const double* r, double* z, hipStream_t s) {
                      psum, ru, rp, rj, ra);
   // x_u = F_u^{-T} r_u, backward in time: F_uk^T x^k = r^k + (1/dt) M_u x^{k+1}
   for (int k = nt - 1; k >= 0; --k) {
-    T* rhs = static_cast<T*>(H.amgFuT.buf[1]);
     Seg<T> sg = seg<T>(H.Mu, 0, 0, 0, xu + int64_t(k + 1) * nu, 0, 0, 0, 1, 1.0 / dt);
-    spmv<T, T>(s, H.Mu, 1, k + 1 < nt ? 1 : 0, &sg, ru + int64_t(k) * nu, 0, 1.0, rhs, 0, kRoleSweep);
-    amg_solve<T>(s, H.amgFuT, 1, k, 0, xu + int64_t(k) * nu, rhs, vc);
+    sweep_step<T>(s, H.amgFuT, H.Mu, k + 1 < nt ? 1 : 0, &sg, ru + int64_t(k) * nu, xu + int64_t(k) * nu, k,
+                  H.fu_deg, vc);
   }
   // x_p = S_p^{-T}(r_p - B x_u),  S_p^{-T} = -K_p^{-1} F_p^T M_p^{-1}
   spmv1<T>(s, H.B, nt, 0, 0, xu, nu, -1.0, rp, 1.0, rp, np);
@@ -591,13 +647,11 @@ int precond_transpose(Handle& H, const double* r, double* z, hipStream_t s) {
   spmv1<T>(s, H.KjAt, nt, 0, 0, yj, nj, -1.0, ra, 1.0, ra, na);
   // c = C_A^{-T} h backward: C0_k^T c^k = h^k + (1/dt) C1_k^T c^{k+1} - (1/dt^2) C2^T c^{k+2}
   for (int k = nt - 1; k >= 0; --k) {
-    T* rhs = static_cast<T*>(H.amgC0T.buf[1]);
     Seg<T> sg[2];
     int nsg = 0;
     if (k + 1 < nt) sg[nsg++] = seg<T>(H.C1t, 0, k, 0, c + int64_t(k + 1) * na, 0, 0, 0, 1, 1.0 / dt);
     if (k + 2 < nt) sg[nsg++] = seg<T>(H.C1t, 1, 0, 0, c + int64_t(k + 2) * na, 0, 0, 0, 1, -1.0 / (dt * dt));
-    spmv<T, T>(s, H.C1t, 1, nsg, sg, ra + int64_t(k) * na, 0, 1.0, rhs, 0, kRoleSweep);
-    amg_solve<T>(s, H.amgC0T, 1, k, 0, c + int64_t(k) * na, rhs, vc);
+    sweep_step<T>(s, H.amgC0T, H.C1t, nsg, sg, ra + int64_t(k) * na, c + int64_t(k) * na, k, H.ca_deg, vc);
   }
   // f = F_A^T c; y_A = M_A^{-1} f
   {
@@ -828,6 +882,8 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
   H.mass_iters = P.mass_iters;
   H.max_restart = P.max_restart;
   H.adjoint = P.prob.adjoint;
+  H.fu_deg = P.fu_deg;
+  H.ca_deg = P.ca_deg;
   H.base = static_cast<char*>(ws);
   H.L = workspace_layout(P);
   char* base = H.base;
@@ -873,6 +929,11 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
   if (H.adjoint) {
     H.amgFuT = mirror_amg(base, P.amgFuT, H.L.fu_lev);
     H.amgC0T = mirror_amg(base, P.amgC0T, H.L.ca_lev);
+    // the transposed blocks share the spectrum (and the interval) of the forward ones
+    H.amgFuT.alone = H.amgFu.alone;
+    H.amgFuT.alone_dev = H.amgFu.alone_dev;
+    H.amgC0T.alone = H.amgC0.alone;
+    H.amgC0T.alone_dev = H.amgC0.alone_dev;
   }
   if (hipHostMalloc(reinterpret_cast<void**>(&H.host_small), 64 * sizeof(double), hipHostMallocDefault) !=
       hipSuccess) {

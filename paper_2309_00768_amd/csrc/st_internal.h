@@ -98,7 +98,9 @@ class Image {
   std::vector<char> bytes;
 };
 
-// Sliced ELLPACK with C = 64 rows per slice (one wavefront lane per row).
+// Sliced ELLPACK for wave64: a slice is one wavefront.  Each row is owned by
+// `lanes` consecutive lanes (1, 2, 4, 8 or 16), so a slice holds 64/lanes rows;
+// entry j of the row sits at step j/lanes, lane (row_in_slice*lanes + j%lanes).
 // Several segments can share the row permutation (the fused J rows).
 constexpr int kSlice = 64;
 
@@ -112,8 +114,9 @@ struct SellSeg {
 
 struct SellGroup {
   int nrows = 0, ncols = 0, nslices = 0;
+  int lanes = 1;    // lanes per row; rows per slice = 64 / lanes
   int fp32 = 0;     // value type: 0 double, 1 float
-  Span perm;        // int32 [nslices * 64]; -1 marks padding lanes
+  Span perm;        // int32 [nslices * 64 / lanes]; -1 marks padding rows
   SellSeg seg[3];
   int nseg = 0;
 };
@@ -121,7 +124,9 @@ struct SellGroup {
 // Packs CSR matrices with the same row count into one SELL group.  Each
 // matrix may carry several value sets (csr.v.size() = nsets * nnz).  Rows are
 // sorted by total length in windows of `sigma` rows (0 = whole matrix).
-SellGroup pack_sell(Image& img, const std::vector<const Csr*>& mats, int fp32, int sigma);
+// lanes = 0 picks the lanes per row from the mean row length.
+SellGroup pack_sell(Image& img, const std::vector<const Csr*>& mats, int fp32, int sigma, int lanes = 0);
+int auto_lanes(double mean_row_len);
 
 // --------------------------------------------------------------- AMG ---
 struct AmgLevel {
@@ -137,6 +142,11 @@ struct Amg {
   int nsets = 1;
   int fp32 = 0;
   int cheb_degree = 3;
+  // Spectral interval of D^{-1} A on the finest level, per value set, for
+  // Chebyshev-Jacobi used alone as the spatial solver: (theta, delta).
+  std::vector<double> cheb_alone;
+  Span cheb_alone_span;
+  double kappa = 0.0;          // largest estimated condition number over the sets
   std::vector<AmgLevel> lev;   // lev.back() is the coarsest
   int ncoarse = 0;
   Span coarse_inv;        // T [nsets][ncoarse][ncoarse] dense inverse
@@ -150,6 +160,9 @@ struct Grid2 { int gx, gy, ncomp; };   // structured node grid of a block (per c
 // aggregation (3x3 node blocks per component).
 int build_amg(Image& img, const Csr& a, int nsets, Grid2 grid, int fp32, int cheb_degree,
               int sigma, bool singular, Amg& out, std::string& err);
+// Estimates [lambda_min, lambda_max] of D^{-1} A per value set (finest level)
+// and stores the widened Chebyshev interval in out.cheb_alone.
+void estimate_interval(Image& img, const Csr& a, int nsets, Amg& out);
 
 // ---------------------------------------------------------------- plan ---
 struct Plan {
@@ -159,6 +172,7 @@ struct Plan {
   size_t ws_bytes = 0;
   int fp32 = 0;
   int inner_iters = 40, mass_iters = 12, max_restart = 30, exact = 0;
+  int fu_deg = 0, ca_deg = 0;     // > 0: Chebyshev alone of this degree; 0: AMG V-cycle
   // J and J^T (FP64): segment 0 per-slab values, 1 shared, 2 previous/next slab coupling.
   SellGroup J, JT;
   // P_T pieces (precision per fp32).
