@@ -179,6 +179,13 @@ int st_apply_precond(st_handle* h, const double* r, double* z, void* stream);
 /* z = P_T^{-T} r: the transposed preconditioner (backward-in-time sweeps). */
 int st_apply_precond_t(st_handle* h, const double* r, double* z, void* stream);
 
+/* y = (M_A / dt) a0: how an initial vector potential A^0 (interior Q1 nodes,
+ * length (n-1)^2, device, FP64) enters the right-hand side of the first slab
+ * (the A^{k-1} term of the induction row of the paper's recurrence, eq.
+ * (recurrence), moved to the right for k = 1).  M_A is symmetric, so the same
+ * call maps an adjoint lambda_A^1 to the gradient with respect to A^0. */
+int st_apply_initial_coupling(st_handle* h, const double* a0, double* y, void* stream);
+
 /* ------------------------------------------------------------- solves --- */
 
 /* Right-preconditioned FGMRES(m) on J x = b with P_T; residual, Arnoldi (CGS2)

@@ -56,7 +56,8 @@ EXPORTED = [
     "st_plan_create", "st_plan_workspace_size", "st_plan_sizes", "st_plan_export_block", "st_plan_export_jbar",
     "st_plan_solver_info",
     "st_plan_destroy", "st_create", "st_destroy", "st_apply_jacobian", "st_apply_jacobian_t",
-    "st_apply_precond", "st_apply_precond_t", "st_fgmres_solve", "st_adjoint_solve", "st_sizes",
+    "st_apply_precond", "st_apply_precond_t", "st_apply_initial_coupling", "st_fgmres_solve", "st_adjoint_solve",
+    "st_sizes",
     "st_error_string",
 ]
 
@@ -82,6 +83,7 @@ def _load(path=LIB_PATH):
         "st_apply_jacobian_t": ([vp, vp, vp, vp], ctypes.c_int),
         "st_apply_precond": ([vp, vp, vp, vp], ctypes.c_int),
         "st_apply_precond_t": ([vp, vp, vp, vp], ctypes.c_int),
+        "st_apply_initial_coupling": ([vp, vp, vp, vp], ctypes.c_int),
         "st_fgmres_solve": ([vp, vp, vp, ctypes.POINTER(StOpts), ctypes.POINTER(StInfo), vp], ctypes.c_int),
         "st_adjoint_solve": ([vp, vp, vp, ctypes.POINTER(StOpts), ctypes.POINTER(StInfo), vp], ctypes.c_int),
         "st_sizes": ([vp, i64p, ip, ip], ctypes.c_int),
@@ -244,6 +246,16 @@ class System:
         fn = lib().st_apply_precond_t if transpose else lib().st_apply_precond
         _check(fn(self.ptr, self._vec(r), self._vec(z), _stream_ptr(stream)), "st_apply_precond")
         return z
+
+    def initial_coupling(self, a0, y=None, stream=None):
+        """y = (M_A / dt) a0 on the interior potential nodes (FP64, device)."""
+        import torch
+        na = self.offsets[5] - self.offsets[4]
+        assert a0.dtype == torch.float64 and a0.is_cuda and a0.is_contiguous() and a0.numel() == na
+        y = torch.empty_like(a0) if y is None else y
+        _check(lib().st_apply_initial_coupling(self.ptr, ctypes.c_void_p(a0.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                               _stream_ptr(stream)), "st_apply_initial_coupling")
+        return y
 
     def solve(self, b, x=None, restart=30, rtol=1e-8, atol=0.0, maxit=1000, x0=False, history=0,
               adjoint=False, stream=None):

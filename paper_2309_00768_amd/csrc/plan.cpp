@@ -172,6 +172,11 @@ static int build_plan(Plan& P, std::string& err) {
     P.JT = pack_sell(img, {&S, &C, &Pv}, 0, sigma, pr.j_lanes);
   }
 
+  {
+    Csr MAd = b.MA;
+    for (auto& v : MAd.v) v /= b.dt;
+    P.MA64 = pack_sell(img, {&MAd}, 0, sigma);
+  }
   // ------------------------------------------------------- P_T pieces
   P.MA = pack_sell(img, {&b.MA}, fp, sigma);
   P.dMA = put_diag_inv<double>(img, b.MA, fp);

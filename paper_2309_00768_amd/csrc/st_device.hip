@@ -59,7 +59,7 @@ struct Handle {
   int fu_deg = 0, ca_deg = 0;
   char* base = nullptr;
   WsLayout L;
-  DGroup J, JT, MA, Mj, Mp, FA, FAt, Fp, Fpt, KjA, KjAt, Bt, B, Zj, Zjt, ZAt, Mu, C1, C1t;
+  DGroup J, JT, MA, Mj, Mp, FA, FAt, Fp, Fpt, KjA, KjAt, Bt, B, Zj, Zjt, ZAt, Mu, C1, C1t, MA64;
   const void *dMA = nullptr, *dMj = nullptr, *dMp = nullptr;
   const double* mp_rowsum = nullptr;
   double msum = 1.0;              // 1^T M_p 1 (the area)
@@ -893,6 +893,7 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
     return ST_EHIP;
   }
   H.J = mirror(base, P.J);
+  H.MA64 = mirror(base, P.MA64);
   if (H.adjoint) H.JT = mirror(base, P.JT);
   H.MA = mirror(base, P.MA);
   H.Mj = mirror(base, P.Mj);
@@ -982,6 +983,13 @@ int st_apply_precond_t(st_handle* h, const double* r, double* z, void* stream) {
   if (!h || !r || !z || r == z || !h->h.adjoint) return ST_EINVAL;
   int rc = st::apply_precond(h->h, r, z, static_cast<hipStream_t>(stream), true);
   if (rc) return rc;
+  return hipGetLastError() == hipSuccess ? ST_OK : ST_EHIP;
+}
+
+int st_apply_initial_coupling(st_handle* h, const double* a0, double* y, void* stream) {
+  if (!h || !a0 || !y || a0 == y) return ST_EINVAL;
+  st::spmv1<double>(static_cast<hipStream_t>(stream), h->h.MA64, 1, 0, 0, a0, 0, 1.0, nullptr, 0.0, y, 0,
+                    st::kRoleSlab);
   return hipGetLastError() == hipSuccess ? ST_OK : ST_EHIP;
 }
 

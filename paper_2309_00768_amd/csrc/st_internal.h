@@ -183,6 +183,7 @@ struct Plan {
   SellGroup Zj, ZA, Zjt, ZAt;     // per-slab couplings
   SellGroup Mu;                   // sweep coupling of F_u
   SellGroup C1, C2, C1t, C2t;     // sweep couplings of C_A
+  SellGroup MA64;                 // M_A / dt in FP64 (initial-condition coupling)
   Amg amgFu, amgC0, amgKp;        // spatial solvers (per-slab for Fu, C0; shared Kp)
   Amg amgFuT, amgC0T;             // transposed hierarchies for the adjoint
   Span mp_rowsum;                 // double [np]: 1^T M_p (pressure normalisation)
