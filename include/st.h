@@ -91,7 +91,11 @@ typedef struct st_problem {
   int sell_sigma;     /* SELL sorting window in rows (0: whole matrix)        */
   int adjoint;        /* 1: also build the transposed operators (J^T, P_T^{-T}) */
   int j_lanes;        /* wavefront lanes per row of the J apply (0: auto)     */
-  int reserved[6];
+  int sweep_format;   /* Chebyshev-alone sweeps: 0 structured 5x5 stencils,
+                         1 SELL (same arithmetic, for comparison)            */
+  int single_stream;  /* 1: run the whole of P_T^{-1} on the caller's stream
+                         (no overlap of the C_A and F_u sweeps)               */
+  int reserved[4];
   double inner_reduction; /* auto inner solver of F_u,k: target error reduction
                              per spatial solve (0: 0.1)                        */
   double ca_reduction;    /* auto inner solver of C_A,k: target reduction (0:

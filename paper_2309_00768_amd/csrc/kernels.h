@@ -11,6 +11,11 @@ namespace st {
 constexpr int kWave = 64;        // CDNA wavefront = one SELL slice
 constexpr int kBlock = 256;      // 4 slices per workgroup
 
+// The sparse kernels here are latency bound: letting the compiler use up to
+// 128 VGPRs (4 waves per SIMD) keeps a row's loads in flight together instead
+// of serialising them to reach maximum occupancy.
+#define ST_LATENCY_KERNEL __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
+
 // One segment of a multi-segment SELL SpMV.  For vector v (blockIdx.y) it adds
 //   alpha * A_seg(values of set `set_base + v*set_step`) * x[(v + xshift) * xstride + :]
 // when vlo <= v < vhi.
@@ -58,6 +63,46 @@ enum Role : int {
   kRoleAmg = 3,      // AMG residuals, restriction, prolongation
 };
 
+// sum_j val[j*64] * x[col[j*64]] for j < w, loads issued in batches of 8 so
+// that each batch costs two memory round trips (indices and values, then the
+// gathered x) instead of two per entry.
+template <class T, class TX, class TA>
+__device__ inline TA sell_row(const T* __restrict__ val, const int* __restrict__ col, const TX* __restrict__ x,
+                              int w) {
+  TA sum = TA(0);
+  int j = 0;
+  for (; j + 8 <= w; j += 8) {
+    int c[8];
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      c[u] = col[(j + u) * 64];
+      v[u] = val[(j + u) * 64];
+    }
+    TX xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xv[u] = x[c[u]];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sum += TA(v[u]) * TA(xv[u]);
+  }
+  if (j < w) {
+    const int rem = w - j;   // 1..7, padded to 8 with guarded loads
+    int c[8];
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      c[u] = u < rem ? col[(j + u) * 64] : 0;
+      v[u] = u < rem ? val[(j + u) * 64] : T(0);
+    }
+    TX xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xv[u] = u < rem ? x[c[u]] : TX(0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sum += TA(v[u]) * TA(xv[u]);
+  }
+  return sum;
+}
+
 template <class TA>
 __device__ inline TA group_sum(TA v, int lanes) {
   for (int off = lanes / 2; off > 0; off /= 2) v += __shfl_down(v, off, lanes);
@@ -66,7 +111,7 @@ __device__ inline TA group_sum(TA v, int lanes) {
 
 // y[v][row] = sum_seg alpha_seg (A_seg x_seg)[row] + beta b[v][row]
 template <class T, class TX, class TA, int Role>
-__global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs<T, TX> a) {
+__global__ ST_LATENCY_KERNEL void k_spmv(SpmvArgs<T, TX> a) {
   const int v = blockIdx.y;
   const int slice = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
   if (slice >= a.nslices) return;          // uniform per wavefront
@@ -85,8 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs<T, TX> a) {
     const T* val = g.val + (g.vstride ? int64_t(g.set_base + v * g.set_step) * g.vstride : 0) + beg + lane;
     const TX* x = static_cast<const TX*>(g.x) + int64_t(v + g.xshift) * g.xstride;
     const int* col = g.col + beg + lane;
-    TA sum = TA(0);
-    for (int j = 0; j < w; ++j) sum += TA(val[j * kWave]) * TA(x[col[j * kWave]]);
+    const TA sum = sell_row<T, TX, TA>(val, col, x, w);
     acc += TA(g.alpha) * sum;
   }
   acc = group_sum(acc, L);
@@ -131,7 +175,7 @@ struct ChebArgs {
 
 // Role: 0 mass-matrix solves, 1 finest AMG level / single-level solves, 2 coarser AMG levels.
 template <class T, int Role>
-__global__ __launch_bounds__(kBlock) void k_cheb(ChebArgs<T> a) {
+__global__ ST_LATENCY_KERNEL void k_cheb(ChebArgs<T> a) {
   const int v = blockIdx.y;
   const int slice = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
   if (slice >= a.nslices) return;          // uniform per wavefront
@@ -161,8 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_cheb(ChebArgs<T> a) {
   const T* val = a.val + (a.vstride ? int64_t(set) * a.vstride : 0) + beg + lane;
   const int* col = a.col + beg + lane;
   const T* d0 = a.dold + o;
-  T sum = T(0);
-  for (int j = 0; j < w; ++j) sum += val[j * kWave] * d0[col[j * kWave]];
+  T sum = sell_row<T, T, T>(val, col, d0, w);
   sum = group_sum(sum, L);
   if (sub != 0 || row < 0) return;
   const T rn = a.r[o + row] - sum;
@@ -180,6 +223,213 @@ __global__ __launch_bounds__(kBlock) void k_cheb(ChebArgs<T> a) {
   const T d = c1 * d0[row] + c2 * dg * rn;
   a.dnew[o + row] = d;
   a.x[o + row] += d;
+}
+
+// ------------------------------------------------------------ stencils ---
+// Operator on a structured node grid, 5x5 neighbourhood per component pair.
+template <class T>
+struct StOp {
+  const T* coef;        // [set][slot][row]
+  int64_t set_stride;   // nslot * rows (0 = shared)
+  int gx, gy, ncomp, diag_comp, nslot;
+  int cgx, cgy, shift;  // column grid (node (ii, jj) at row-grid position (ii + shift, jj + shift))
+  int64_t rows;
+};
+
+// (A x)[row] for a stencil operator of radius RAD; every coefficient and
+// neighbour load is independent of the others (one memory round trip).
+// Neighbours outside the column grid have zero coefficients; their (clamped)
+// addresses stay inside x.
+template <int RAD, class T, class TA>
+__device__ inline TA stencil_row(const StOp<T>& A, int set, int64_t row, const T* __restrict__ x) {
+  constexpr int W = 2 * RAD + 1, NS = W * W;
+  const int64_t per = int64_t(A.gx) * A.gy, cper = int64_t(A.cgx) * A.cgy;
+  const int c = int(row / per);
+  const int rem = int(row - int64_t(c) * per);
+  const int i = rem % A.gx - A.shift, j = rem / A.gx - A.shift;
+  const T* __restrict__ cf = A.coef + (A.set_stride ? int64_t(set) * A.set_stride : 0) + row;
+  int off[NS];
+#pragma unroll
+  for (int dy = -RAD; dy <= RAD; ++dy) {
+    const int jj = min(max(j + dy, 0), A.cgy - 1);
+#pragma unroll
+    for (int dx = -RAD; dx <= RAD; ++dx) off[(dy + RAD) * W + dx + RAD] = jj * A.cgx + min(max(i + dx, 0), A.cgx - 1);
+  }
+  TA acc = TA(0);
+  const int ncc = A.diag_comp ? 1 : A.ncomp;
+  for (int q = 0; q < ncc; ++q) {
+    const T* __restrict__ xc = x + int64_t(A.diag_comp ? c : q) * cper;
+    const T* __restrict__ cq = cf + int64_t(q) * NS * A.rows;
+    T cv[NS], xv[NS];
+#pragma unroll
+    for (int o = 0; o < NS; ++o) {
+      cv[o] = cq[int64_t(o) * A.rows];
+      xv[o] = xc[off[o]];
+    }
+#pragma unroll
+    for (int o = 0; o < NS; ++o) acc += TA(cv[o]) * TA(xv[o]);
+  }
+  return acc;
+}
+
+// First step of a sweep solve with Chebyshev-Jacobi alone, fused with the
+// sweep right-hand side: q' = q + a1 S1 y1 + a2 S2 y2, r = q', d = Dinv q'/theta, x = d.
+template <class T>
+struct StInitArgs {
+  StOp<T> S1, S2;
+  int set1, set2, n1, n2;   // n1/n2: whether the couplings are active
+  double a1, a2;
+  const T* y1;
+  const T* y2;
+  const T* q;
+  const T* dinv;
+  double theta;
+  T* r;
+  T* d;
+  T* x;
+  int64_t rows;
+};
+
+template <class T, int Role>
+__global__ ST_LATENCY_KERNEL void k_st_init(StInitArgs<T> a) {
+  const int64_t row = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (row >= a.rows) return;
+  T acc = a.q[row];
+  if (a.n1) acc += T(a.a1) * stencil_row<2, T, T>(a.S1, a.set1, row, a.y1);
+  if (a.n2) acc += T(a.a2) * stencil_row<2, T, T>(a.S2, a.set2, row, a.y2);
+  const T d = a.dinv[row] * acc / T(a.theta);
+  a.r[row] = acc;
+  a.d[row] = d;
+  a.x[row] = d;
+}
+
+// Chebyshev step i >= 1 on a stencil operator: r -= A d_old; d_new = c1 d_old + c2 Dinv r; x += d_new.
+template <class T>
+struct StChebArgs {
+  StOp<T> A;
+  int set;
+  const T* dinv;
+  double c1, c2;
+  const T* dold;
+  T* dnew;
+  T* r;
+  T* x;
+  int64_t rows;
+};
+
+template <class T, int Role>
+__global__ ST_LATENCY_KERNEL void k_st_cheb(StChebArgs<T> a) {
+  const int64_t row = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (row >= a.rows) return;
+  const T od = a.dold[row];
+  const T dg = a.dinv[row];
+  const T rr = a.r[row];
+  const T t = stencil_row<2, T, T>(a.A, a.set, row, a.dold);
+  const T rn = rr - t;
+  const T d = T(a.c1) * od + T(a.c2) * dg * rn;
+  a.r[row] = rn;
+  a.dnew[row] = d;
+  a.x[row] += d;
+}
+
+// The C_A sweep for slabs [k0, k1) in one workgroup, each slab followed by
+// its current solve y_j = M_j^{-1}(r_j - K_jA y_A): Chebyshev-Jacobi of degree
+// `deg` on C_A,k (first step fused with the sweep right-hand side
+// s^k + (1/dt) C1_{k-1} y^{k-1} - (1/dt^2) C2 y^{k-2}) and of degree `mit` on
+// M_j.  Only workgroup barriers: no inter-workgroup synchronisation.
+template <class T>
+struct ChainArgs {
+  StOp<T> C0, C1, C2, Mj, KjA;
+  int k0, k1, deg, mit, na, nj;
+  double dt;
+  const double* alone;  // (theta, delta) per slab for C_A
+  const T* dinvC;       // [nt][na] (or shared when dinv_stride = 0)
+  int64_t dinv_stride;
+  const T* dinvM;       // [nj]
+  double mth, mde;      // M_j interval
+  const T* sA;
+  T* yA;
+  const T* rj;
+  T* yj;
+  T* r;
+  T* d0;
+  T* d1;
+};
+
+constexpr int kChainBlock = 1024;
+
+template <class T>
+__global__ __launch_bounds__(kChainBlock) void k_ca_chain(ChainArgs<T> a) {
+  const int tid = threadIdx.x;
+  const int na = a.na, nj = a.nj;
+  for (int k = a.k0; k < a.k1; ++k) {
+    const double theta = a.alone[2 * k], delta = a.alone[2 * k + 1];
+    const T* dinv = a.dinvC + int64_t(k) * a.dinv_stride;
+    T* yk = a.yA + int64_t(k) * na;
+    const T* sk = a.sA + int64_t(k) * na;
+    const T inv_dt = T(1.0 / a.dt), inv_dt2 = T(1.0 / (a.dt * a.dt));
+    for (int row = tid; row < na; row += kChainBlock) {
+      T acc = sk[row];
+      if (k >= 1) acc += inv_dt * stencil_row<2, T, T>(a.C1, k - 1, row, a.yA + int64_t(k - 1) * na);
+      if (k >= 2) acc -= inv_dt2 * stencil_row<2, T, T>(a.C2, 0, row, a.yA + int64_t(k - 2) * na);
+      const T dd = dinv[row] * acc / T(theta);
+      a.r[row] = acc;
+      a.d0[row] = dd;
+      yk[row] = dd;
+    }
+    __syncthreads();
+    {
+      const double sigma = theta / delta;
+      double rho_prev = 1.0 / sigma, rho = rho_prev;
+      for (int i = 1; i < a.deg; ++i) {
+        rho_prev = rho;
+        rho = 1.0 / (2.0 * sigma - rho_prev);
+        const T c1 = T(rho * rho_prev), c2 = T(2.0 * rho / delta);
+        const T* dold = (i - 1) % 2 ? a.d1 : a.d0;
+        T* dnew = i % 2 ? a.d1 : a.d0;
+        for (int row = tid; row < na; row += kChainBlock) {
+          const T od = dold[row], dg = dinv[row], rr = a.r[row];
+          const T rn = rr - stencil_row<2, T, T>(a.C0, k, row, dold);
+          const T dn = c1 * od + c2 * dg * rn;
+          a.r[row] = rn;
+          dnew[row] = dn;
+          yk[row] += dn;
+        }
+        __syncthreads();
+      }
+    }
+    // current: y_j = M_j^{-1} (r_j - K_jA y_A^k)
+    T* jk = a.yj + int64_t(k) * nj;
+    const T* rjk = a.rj + int64_t(k) * nj;
+    for (int row = tid; row < nj; row += kChainBlock) {
+      const T acc = rjk[row] - stencil_row<1, T, T>(a.KjA, 0, row, yk);
+      const T dd = a.dinvM[row] * acc / T(a.mth);
+      a.r[row] = acc;
+      a.d0[row] = dd;
+      jk[row] = dd;
+    }
+    __syncthreads();
+    {
+      const double sigma = a.mth / a.mde;
+      double rho_prev = 1.0 / sigma, rho = rho_prev;
+      for (int i = 1; i < a.mit; ++i) {
+        rho_prev = rho;
+        rho = 1.0 / (2.0 * sigma - rho_prev);
+        const T c1 = T(rho * rho_prev), c2 = T(2.0 * rho / a.mde);
+        const T* dold = (i - 1) % 2 ? a.d1 : a.d0;
+        T* dnew = i % 2 ? a.d1 : a.d0;
+        for (int row = tid; row < nj; row += kChainBlock) {
+          const T od = dold[row], dg = a.dinvM[row], rr = a.r[row];
+          const T rn = rr - stencil_row<1, T, T>(a.Mj, 0, row, dold);
+          const T dn = c1 * od + c2 * dg * rn;
+          a.r[row] = rn;
+          dnew[row] = dn;
+          jk[row] += dn;
+        }
+        __syncthreads();
+      }
+    }
+  }
 }
 
 // Coarsest AMG level: x[v] (+)= Ainv(set) * b[v]; Ainv stored column-major.

@@ -121,6 +121,9 @@ WsLayout workspace_layout(const Plan& P) {
   L.mr = take(ts * nt * mm);
   L.md0 = take(ts * nt * mm);
   L.md1 = take(ts * nt * mm);
+  L.chr = take(ts * mm);
+  L.chd0 = take(ts * mm);
+  L.chd1 = take(ts * mm);
   for (const AmgLevel& lv : P.amgKp.lev)
     for (int i = 0; i < 6; ++i) L.kp_lev.push_back(take(ts * nt * lv.nrows));
   for (const AmgLevel& lv : P.amgFu.lev)
@@ -159,7 +162,8 @@ static int build_plan(Plan& P, std::string& err) {
     Csr C = fuse(ns, ns, 1, {{&b.Bt, 0, o2, 1.0}, {&b.B, o2, 0, 1.0}, {&b.Mj, o3, o3, 1.0},
                              {&b.KjA, o3, o4, 1.0}});
     Csr Pv = fuse(ns, ns, 1, {{&b.Mu, 0, 0, -1.0 / b.dt}, {&b.MA, o4, o4, -1.0 / b.dt}});
-    P.J = pack_sell(img, {&S, &C, &Pv}, 0, sigma, pr.j_lanes);
+    // J is bandwidth bound and large: one lane per row unless asked otherwise.
+    P.J = pack_sell(img, {&S, &C, &Pv}, 0, sigma, pr.j_lanes > 0 ? pr.j_lanes : 1);
   }
   if (pr.adjoint) {
     Csr FuT = csr_transpose(b.Fu), YT = csr_transpose(b.Y), ZjT = csr_transpose(b.Zj),
@@ -169,7 +173,7 @@ static int build_plan(Plan& P, std::string& err) {
     Csr C = fuse(ns, ns, 1, {{&b.Bt, 0, o2, 1.0}, {&b.B, o2, 0, 1.0}, {&b.Mj, o3, o3, 1.0},
                              {&b.KjAt, o4, o3, 1.0}});
     Csr Pv = fuse(ns, ns, 1, {{&b.Mu, 0, 0, -1.0 / b.dt}, {&b.MA, o4, o4, -1.0 / b.dt}});
-    P.JT = pack_sell(img, {&S, &C, &Pv}, 0, sigma, pr.j_lanes);
+    P.JT = pack_sell(img, {&S, &C, &Pv}, 0, sigma, pr.j_lanes > 0 ? pr.j_lanes : 1);
   }
 
   {
@@ -199,7 +203,8 @@ static int build_plan(Plan& P, std::string& err) {
   }
   P.KjA = pack_sell(img, {&b.KjA}, fp, sigma);
   P.Bt = pack_sell(img, {&b.Bt}, fp, sigma);
-  P.Zj = pack_sell(img, {&b.Zj, &b.ZA}, fp, sigma);   // y_u = r_u - Zj y_j - ZA y_A (two segments)
+  // y_u = r_u - Zj y_j - ZA y_A + B^T (-x_p): three segments over the velocity rows
+  P.Zj = pack_sell(img, {&b.Zj, &b.ZA, &b.Bt}, fp, sigma);
   P.Mu = pack_sell(img, {&b.Mu}, fp, sigma);
   {
     // C_A sweep couplings: rhs = s^k + (1/dt) C1_{k-1} y^{k-1} - (1/dt^2) C2 y^{k-2}
@@ -249,6 +254,31 @@ static int build_plan(Plan& P, std::string& err) {
     };
     P.fu_deg = pick(pr.fu_solver, P.amgFu, red_fu);
     P.ca_deg = pick(pr.ca_solver, P.amgC0, red_ca);
+  }
+  // Stencil forms of the sweep operators (structured grids, 5x5 neighbourhoods).
+  P.use_stencil = (P.fu_deg > 0 || P.ca_deg > 0) && pr.sweep_format == 0 ? 1 : 0;
+  if (P.use_stencil) {
+    const int gu = 2 * n - 1, ga = n - 1;
+    bool ok = pack_stencil(img, b.Fu, nt, gu, gu, 2, false, fp, P.sFu);
+    Csr Mud = b.Mu;
+    for (auto& v : Mud.v) v /= b.dt;
+    ok = ok && pack_stencil(img, Mud, 1, gu, gu, 2, true, fp, P.sMu);
+    ok = ok && pack_stencil(img, b.C0, nt, ga, ga, 1, false, fp, P.sC0);
+    ok = ok && pack_stencil(img, b.C1, std::max(nt - 1, 1), ga, ga, 1, false, fp, P.sC1);
+    ok = ok && pack_stencil(img, b.C2, 1, ga, ga, 1, false, fp, P.sC2);
+    ok = ok && pack_stencil(img, b.Mj, 1, n + 1, n + 1, 1, false, fp, P.sMj, 1);
+    ok = ok && pack_stencil(img, b.KjA, 1, n + 1, n + 1, 1, false, fp, P.sKjA, 1, n - 1, n - 1, 1);
+    if (pr.adjoint) {
+      Csr FuT = csr_transpose(b.Fu), C0T = csr_transpose(b.C0), C1T = csr_transpose(b.C1), C2T = csr_transpose(b.C2);
+      ok = ok && pack_stencil(img, FuT, nt, gu, gu, 2, false, fp, P.sFuT);
+      ok = ok && pack_stencil(img, C0T, nt, ga, ga, 1, false, fp, P.sC0T);
+      ok = ok && pack_stencil(img, C1T, std::max(nt - 1, 1), ga, ga, 1, false, fp, P.sC1T);
+      ok = ok && pack_stencil(img, C2T, 1, ga, ga, 1, false, fp, P.sC2T);
+    }
+    if (!ok) {
+      err = "sweep operator does not fit a 5x5 stencil";
+      return ST_EINTERNAL;
+    }
   }
 
   // pressure normalisation weights m = 1^T M_p (FP64)

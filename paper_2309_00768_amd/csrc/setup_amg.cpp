@@ -187,6 +187,45 @@ SellGroup pack_sell(Image& img, const std::vector<const Csr*>& mats, int fp32, i
   return g;
 }
 
+// ------------------------------------------------------------ stencils ---
+bool pack_stencil(Image& img, const Csr& m, int nsets, int gx, int gy, int ncomp, bool diag_comp, int fp32,
+                  StencilOp& out, int rad, int cgx, int cgy, int shift) {
+  out = StencilOp();
+  out.gx = gx;
+  out.gy = gy;
+  out.ncomp = ncomp;
+  out.diag_comp = diag_comp ? 1 : 0;
+  out.nsets = nsets;
+  out.rad = rad;
+  out.cgx = cgx > 0 ? cgx : gx;
+  out.cgy = cgy > 0 ? cgy : gy;
+  out.shift = shift;
+  const int w = 2 * rad + 1;
+  out.nslot = diag_comp ? w * w : w * w * ncomp;
+  out.fp32 = fp32;
+  const int64_t per = int64_t(gx) * gy, cper = int64_t(out.cgx) * out.cgy;
+  out.rows = per * ncomp;
+  if (m.nr != out.rows || m.nc != cper * ncomp) return false;
+  const int64_t z = m.nnz();
+  const int msets = z ? int(m.v.size() / z) : 1;
+  std::vector<double> coef(size_t(nsets) * out.nslot * out.rows, 0.0);
+  for (int r = 0; r < m.nr; ++r) {
+    const int c = int(r / per), i = int(r % per) % gx, j = int(r % per) / gx;
+    for (int p = m.rp[r]; p < m.rp[r + 1]; ++p) {
+      const int col = m.ci[p];
+      const int cc = int(col / cper), ii = int(col % cper) % out.cgx, jj = int(col % cper) / out.cgx;
+      const int dx = ii + shift - i, dy = jj + shift - j;
+      if (dx < -rad || dx > rad || dy < -rad || dy > rad) return false;
+      if (diag_comp && cc != c) return false;
+      const int slot = (diag_comp ? 0 : cc * w * w) + (dy + rad) * w + (dx + rad);
+      for (int s = 0; s < nsets; ++s)
+        coef[(size_t(s) * out.nslot + slot) * out.rows + r] = m.v[size_t(msets == 1 ? 0 : s) * z + p];
+    }
+  }
+  out.coef = fp32 ? put_converted<float>(img, coef, 1) : img.put(coef);
+  return true;
+}
+
 // --------------------------------------------------- spectral interval ---
 void estimate_interval(Image& img, const Csr& a, int nsets, Amg& out) {
   const int n = a.nr;

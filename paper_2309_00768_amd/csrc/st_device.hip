@@ -56,7 +56,7 @@ struct Handle {
   Dims d;
   double dt = 0;
   int fp32 = 0, exact = 0, inner_iters = 1, mass_iters = 12, max_restart = 30, adjoint = 0;
-  int fu_deg = 0, ca_deg = 0;
+  int fu_deg = 0, ca_deg = 0, use_stencil = 0;
   char* base = nullptr;
   WsLayout L;
   DGroup J, JT, MA, Mj, Mp, FA, FAt, Fp, Fpt, KjA, KjAt, Bt, B, Zj, Zjt, ZAt, Mu, C1, C1t, MA64;
@@ -64,8 +64,17 @@ struct Handle {
   const double* mp_rowsum = nullptr;
   double msum = 1.0;              // 1^T M_p 1 (the area)
   DAmg amgFu, amgC0, amgKp, amgFuT, amgC0T;
+  StencilOp sFu, sMu, sC0, sC1, sC2, sFuT, sC0T, sC1T, sC2T;   // offsets into the image
+  StencilOp sMj, sKjA;
+  int use_chain = 0;               // C_A sweep + M_j solves in single-workgroup chunk kernels
   double* host_small = nullptr;   // pinned
   double precond_ms = 0.0;
+  // Second stream: the C_A sweep runs on it, chunk by chunk, while the pressure
+  // part and the F_u sweep run on the caller's stream; events order the chunks.
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_chunk;
+  int chunk = 8;
 };
 
 }  // namespace st
@@ -523,6 +532,80 @@ void sweep_step(hipStream_t s, DAmg& a, const DGroup& cg, int nseg, const Seg<T>
                    nullptr, r, x, d[(i - 1) % 2], d[i % 2], L.n, 1, i, 1, 1);
 }
 
+template <class T>
+StOp<T> st_op(char* base, const StencilOp& o) {
+  StOp<T> a;
+  a.coef = reinterpret_cast<const T*>(base + o.coef.off);
+  a.set_stride = o.nsets > 1 ? int64_t(o.nslot) * o.rows : 0;
+  a.gx = o.gx;
+  a.gy = o.gy;
+  a.ncomp = o.ncomp;
+  a.diag_comp = o.diag_comp;
+  a.nslot = o.nslot;
+  a.cgx = o.cgx;
+  a.cgy = o.cgy;
+  a.shift = o.shift;
+  a.rows = o.rows;
+  return a;
+}
+
+// One sweep step with Chebyshev-Jacobi alone on stencil operators:
+// x = p(D^{-1} A_k) D^{-1} (q + a1 S1 y1 + a2 S2 y2), `deg` kernels.
+template <class T>
+void sweep_step_stencil(hipStream_t s, Handle& H, DAmg& a, const StencilOp& A, const StencilOp* S1, int set1,
+                        double a1, const T* y1, const StencilOp* S2, int set2, double a2, const T* y2, const T* q,
+                        T* x, int k, int deg, int role) {
+  DLevel& L = a.lev[0];
+  const int64_t rows = A.rows;
+  T* r = static_cast<T*>(a.buf[2]);
+  T* d0 = static_cast<T*>(a.buf[3]);
+  T* d1 = static_cast<T*>(a.buf[4]);
+  const T* dinv = static_cast<const T*>(L.dinv) + (a.nsets > 1 ? int64_t(k) * L.n : 0);
+  const int iset = a.nsets > 1 ? k : 0;
+  const double theta = a.alone[2 * iset], delta = a.alone[2 * iset + 1];
+  StInitArgs<T> ia;
+  ia.S1 = S1 ? st_op<T>(H.base, *S1) : StOp<T>{};
+  ia.S2 = S2 ? st_op<T>(H.base, *S2) : StOp<T>{};
+  ia.set1 = set1;
+  ia.set2 = set2;
+  ia.n1 = S1 != nullptr;
+  ia.n2 = S2 != nullptr;
+  ia.a1 = a1;
+  ia.a2 = a2;
+  ia.y1 = y1;
+  ia.y2 = y2;
+  ia.q = q;
+  ia.dinv = dinv;
+  ia.theta = theta;
+  ia.r = r;
+  ia.d = d0;
+  ia.x = x;
+  ia.rows = rows;
+  const dim3 grid(unsigned((rows + kBlock - 1) / kBlock));
+  if (role == 1) hipLaunchKernelGGL((k_st_init<T, 1>), grid, dim3(kBlock), 0, s, ia);
+  else hipLaunchKernelGGL((k_st_init<T, 2>), grid, dim3(kBlock), 0, s, ia);
+  StChebArgs<T> ca;
+  ca.A = st_op<T>(H.base, A);
+  ca.set = iset;
+  ca.dinv = dinv;
+  ca.rows = rows;
+  ca.r = r;
+  ca.x = x;
+  T* d[2] = {d0, d1};
+  const double sigma = theta / delta;
+  double rho_prev = 1.0 / sigma, rho = rho_prev;
+  for (int i = 1; i < deg; ++i) {
+    rho_prev = rho;
+    rho = 1.0 / (2.0 * sigma - rho_prev);
+    ca.c1 = rho * rho_prev;
+    ca.c2 = 2.0 * rho / delta;
+    ca.dold = d[(i - 1) % 2];
+    ca.dnew = d[i % 2];
+    if (role == 1) hipLaunchKernelGGL((k_st_cheb<T, 1>), grid, dim3(kBlock), 0, s, ca);
+    else hipLaunchKernelGGL((k_st_cheb<T, 2>), grid, dim3(kBlock), 0, s, ca);
+  }
+}
+
 // ================================================= P_T^{-1} (forward) ===
 template <class T>
 int precond_forward(Handle& H, const double* r, double* z, hipStream_t s) {
@@ -548,30 +631,71 @@ int precond_forward(Handle& H, const double* r, double* z, hipStream_t s) {
   hipLaunchKernelGGL(k_slab_sums_d, dim3(nt), dim3(kBlock), 0, s, r, int64_t(ns), o2, np, nullptr, psum);
   hipLaunchKernelGGL((k_split<T>), dim3(grid_for(int64_t(ns) * nt)), dim3(kBlock), 0, s, r, ns, nt, o2, o3, o4,
                      psum, ru, rp, rj, ra);
-  // 1. magnetic Schur complement: w = M_A^{-1} r_A; s = F_A w; y_A = C_A^{-1} s (forward sweep)
+  // 1. magnetic Schur complement: w = M_A^{-1} r_A; s = F_A w (all slabs at once)
   cheb_solve<T>(s, H.MA, nt, 0, 0, static_cast<const T*>(H.dMA), 0, nullptr, mth, mde, ra, w, mr, md0, md1, na, mit,
                 0, false);
   {
     Seg<T> sg[2] = {seg<T>(H.FA, 0, 0, 1, w, na, 0, 0, nt, 1.0), seg<T>(H.FA, 1, 0, 0, w, na, -1, 1, nt, 1.0)};
     spmv<T, T>(s, H.FA, nt, 2, sg, nullptr, na, 0.0, sA, na);
   }
-  for (int k = 0; k < nt; ++k) {
-    Seg<T> sg[2];
-    int nsg = 0;
-    if (k >= 1) sg[nsg++] = seg<T>(H.C1, 0, k - 1, 0, yA + int64_t(k - 1) * na, 0, 0, 0, 1, 1.0 / dt);
-    if (k >= 2) sg[nsg++] = seg<T>(H.C1, 1, 0, 0, yA + int64_t(k - 2) * na, 0, 0, 0, 1, -1.0 / (dt * dt));
-    sweep_step<T>(s, H.amgC0, H.C1, nsg, sg, sA + int64_t(k) * na, yA + int64_t(k) * na, k, H.ca_deg, vc);
+  // y_A = C_A^{-1} s: forward sweep on the second stream, one event per chunk of slabs
+  const bool two = H.s2 != nullptr;
+  hipStream_t sa = two ? H.s2 : s;
+  if (two) {
+    (void)hipEventRecord(H.ev_fork, s);
+    (void)hipStreamWaitEvent(sa, H.ev_fork, 0);
   }
-  // 2. y_j = M_j^{-1} (r_j - K_jA y_A)
-  spmv1<T>(s, H.KjA, nt, 0, 0, yA, na, -1.0, rj, 1.0, rj, nj);
-  cheb_solve<T>(s, H.Mj, nt, 0, 0, static_cast<const T*>(H.dMj), 0, nullptr, mth, mde, rj, yj, mr, md0, md1, nj, mit,
-                0, false);
-  // 3. y_u = r_u - Z_j y_j - Z_A y_A
-  {
-    Seg<T> sg[2] = {seg<T>(H.Zj, 0, 0, 1, yj, nj, 0, 0, nt, -1.0), seg<T>(H.Zj, 1, 0, 1, yA, na, 0, 0, nt, -1.0)};
-    spmv<T, T>(s, H.Zj, nt, 2, sg, ru, nu, 1.0, yu, nu);
+  const int C = std::max(1, H.chunk);
+  const int nch = (nt + C - 1) / C;
+  for (int c = 0; c < nch; ++c) {
+    if (H.use_chain) {
+      ChainArgs<T> ch;
+      ch.C0 = st_op<T>(B, H.sC0);
+      ch.C1 = st_op<T>(B, H.sC1);
+      ch.C2 = st_op<T>(B, H.sC2);
+      ch.Mj = st_op<T>(B, H.sMj);
+      ch.KjA = st_op<T>(B, H.sKjA);
+      ch.k0 = c * C;
+      ch.k1 = std::min(nt, (c + 1) * C);
+      ch.deg = H.ca_deg;
+      ch.mit = mit;
+      ch.na = na;
+      ch.nj = nj;
+      ch.dt = dt;
+      ch.alone = H.amgC0.alone_dev;
+      ch.dinvC = static_cast<const T*>(H.amgC0.lev[0].dinv);
+      ch.dinv_stride = H.amgC0.nsets > 1 ? na : 0;
+      ch.dinvM = static_cast<const T*>(H.dMj);
+      ch.mth = mth;
+      ch.mde = mde;
+      ch.sA = sA;
+      ch.yA = yA;
+      ch.rj = rj;
+      ch.yj = yj;
+      ch.r = at<T>(B, L.chr);
+      ch.d0 = at<T>(B, L.chd0);
+      ch.d1 = at<T>(B, L.chd1);
+      hipLaunchKernelGGL((k_ca_chain<T>), dim3(1), dim3(kChainBlock), 0, sa, ch);
+      if (two) (void)hipEventRecord(H.ev_chunk[c], sa);
+      continue;
+    }
+    for (int k = c * C; k < std::min(nt, (c + 1) * C); ++k) {
+      if (H.use_stencil && H.ca_deg > 0) {
+        sweep_step_stencil<T>(sa, H, H.amgC0, H.sC0, k >= 1 ? &H.sC1 : nullptr, k - 1, 1.0 / dt,
+                              yA + int64_t(k - 1) * na, k >= 2 ? &H.sC2 : nullptr, 0, -1.0 / (dt * dt),
+                              yA + int64_t(k - 2) * na, sA + int64_t(k) * na, yA + int64_t(k) * na, k, H.ca_deg, 2);
+      } else {
+        Seg<T> sg[2];
+        int nsg = 0;
+        if (k >= 1) sg[nsg++] = seg<T>(H.C1, 0, k - 1, 0, yA + int64_t(k - 1) * na, 0, 0, 0, 1, 1.0 / dt);
+        if (k >= 2) sg[nsg++] = seg<T>(H.C1, 1, 0, 0, yA + int64_t(k - 2) * na, 0, 0, 0, 1, -1.0 / (dt * dt));
+        sweep_step<T>(sa, H.amgC0, H.C1, nsg, sg, sA + int64_t(k) * na, yA + int64_t(k) * na, k, H.ca_deg, vc);
+      }
+    }
+    if (two) (void)hipEventRecord(H.ev_chunk[c], sa);
   }
-  // 4. pressure: q = K_p^{-1} r_p; t = F_p q; x_p = -M_p^{-1} t (sign applied at the join)
+  // 2. pressure (concurrently with the C_A sweep): q = K_p^{-1} r_p; t = F_p q;
+  //    x_p = -M_p^{-1} t (xp holds M_p^{-1} t; the sign is applied where x_p is used)
   amg_solve<T>(s, H.amgKp, nt, 0, 0, q, rp, vc);
   {
     Seg<T> sg[2] = {seg<T>(H.Fp, 0, 0, 1, q, np, 0, 0, nt, 1.0), seg<T>(H.Fp, 1, 0, 0, q, np, -1, 1, nt, 1.0)};
@@ -579,13 +703,35 @@ int precond_forward(Handle& H, const double* r, double* z, hipStream_t s) {
   }
   cheb_solve<T>(s, H.Mp, nt, 0, 0, static_cast<const T*>(H.dMp), 0, nullptr, mth, mde, t, xp, mr, md0, md1, np, mit,
                 0, false);
-  // 5. x_u = F_u^{-1} (y_u - B^T x_p), x_p carrying the minus sign: y_u + B^T xp
-  spmv1<T>(s, H.Bt, nt, 0, 0, xp, np, 1.0, yu, 1.0, yu, nu);
-  for (int k = 0; k < nt; ++k) {
-    Seg<T> sg = seg<T>(H.Mu, 0, 0, 0, xu + int64_t(k - 1) * nu, 0, 0, 0, 1, 1.0 / dt);
-    sweep_step<T>(s, H.amgFu, H.Mu, k >= 1 ? 1 : 0, &sg, yu + int64_t(k) * nu, xu + int64_t(k) * nu, k, H.fu_deg, vc);
+  // 3. per chunk, once its y_A is ready: y_j = M_j^{-1}(r_j - K_jA y_A);
+  //    g_u = r_u - Z_j y_j - Z_A y_A - B^T x_p; x_u = F_u^{-1} g_u (forward sweep)
+  for (int c = 0; c < nch; ++c) {
+    const int k0 = c * C, kc = std::min(nt, (c + 1) * C) - k0;
+    if (two) (void)hipStreamWaitEvent(s, H.ev_chunk[c], 0);
+    if (!H.use_chain) {
+      spmv1<T>(s, H.KjA, kc, 0, 0, yA + int64_t(k0) * na, na, -1.0, rj + int64_t(k0) * nj, 1.0,
+               rj + int64_t(k0) * nj, nj);
+      cheb_solve<T>(s, H.Mj, kc, 0, 0, static_cast<const T*>(H.dMj), 0, nullptr, mth, mde, rj + int64_t(k0) * nj,
+                    yj + int64_t(k0) * nj, mr, md0, md1, nj, mit, 0, false);
+    }
+    {
+      Seg<T> sg[3] = {seg<T>(H.Zj, 0, k0, 1, yj + int64_t(k0) * nj, nj, 0, 0, kc, -1.0),
+                      seg<T>(H.Zj, 1, k0, 1, yA + int64_t(k0) * na, na, 0, 0, kc, -1.0),
+                      seg<T>(H.Zj, 2, 0, 0, xp + int64_t(k0) * np, np, 0, 0, kc, 1.0)};
+      spmv<T, T>(s, H.Zj, kc, 3, sg, ru + int64_t(k0) * nu, nu, 1.0, yu + int64_t(k0) * nu, nu);
+    }
+    for (int k = k0; k < k0 + kc; ++k) {
+      if (H.use_stencil && H.fu_deg > 0) {
+        sweep_step_stencil<T>(s, H, H.amgFu, H.sFu, k >= 1 ? &H.sMu : nullptr, 0, 1.0, xu + int64_t(k - 1) * nu,
+                              nullptr, 0, 0.0, nullptr, yu + int64_t(k) * nu, xu + int64_t(k) * nu, k, H.fu_deg, 1);
+      } else {
+        Seg<T> sg = seg<T>(H.Mu, 0, 0, 0, xu + int64_t(k - 1) * nu, 0, 0, 0, 1, 1.0 / dt);
+        sweep_step<T>(s, H.amgFu, H.Mu, k >= 1 ? 1 : 0, &sg, yu + int64_t(k) * nu, xu + int64_t(k) * nu, k,
+                      H.fu_deg, vc);
+      }
+    }
   }
-  // 6. join with the pressure normalisation 1^T M_p p = 0
+  // 4. join with the pressure normalisation 1^T M_p p = 0
   hipLaunchKernelGGL((k_slab_sums_t<T>), dim3(nt), dim3(kBlock), 0, s, xp, int64_t(np), np, H.mp_rowsum,
                      psum + nt);
   hipLaunchKernelGGL((k_join<T>), dim3(grid_for(int64_t(ns) * nt)), dim3(kBlock), 0, s, z, ns, nt, o2, o3, o4, xu,
@@ -620,8 +766,12 @@ int precond_transpose(Handle& H, const double* r, double* z, hipStream_t s) {
   // x_u = F_u^{-T} r_u, backward in time: F_uk^T x^k = r^k + (1/dt) M_u x^{k+1}
   for (int k = nt - 1; k >= 0; --k) {
     Seg<T> sg = seg<T>(H.Mu, 0, 0, 0, xu + int64_t(k + 1) * nu, 0, 0, 0, 1, 1.0 / dt);
-    sweep_step<T>(s, H.amgFuT, H.Mu, k + 1 < nt ? 1 : 0, &sg, ru + int64_t(k) * nu, xu + int64_t(k) * nu, k,
-                  H.fu_deg, vc);
+    if (H.use_stencil && H.fu_deg > 0)
+      sweep_step_stencil<T>(s, H, H.amgFuT, H.sFuT, k + 1 < nt ? &H.sMu : nullptr, 0, 1.0, xu + int64_t(k + 1) * nu,
+                            nullptr, 0, 0.0, nullptr, ru + int64_t(k) * nu, xu + int64_t(k) * nu, k, H.fu_deg, 1);
+    else
+      sweep_step<T>(s, H.amgFuT, H.Mu, k + 1 < nt ? 1 : 0, &sg, ru + int64_t(k) * nu, xu + int64_t(k) * nu, k,
+                    H.fu_deg, vc);
   }
   // x_p = S_p^{-T}(r_p - B x_u),  S_p^{-T} = -K_p^{-1} F_p^T M_p^{-1}
   spmv1<T>(s, H.B, nt, 0, 0, xu, nu, -1.0, rp, 1.0, rp, np);
@@ -651,7 +801,12 @@ int precond_transpose(Handle& H, const double* r, double* z, hipStream_t s) {
     int nsg = 0;
     if (k + 1 < nt) sg[nsg++] = seg<T>(H.C1t, 0, k, 0, c + int64_t(k + 1) * na, 0, 0, 0, 1, 1.0 / dt);
     if (k + 2 < nt) sg[nsg++] = seg<T>(H.C1t, 1, 0, 0, c + int64_t(k + 2) * na, 0, 0, 0, 1, -1.0 / (dt * dt));
-    sweep_step<T>(s, H.amgC0T, H.C1t, nsg, sg, ra + int64_t(k) * na, c + int64_t(k) * na, k, H.ca_deg, vc);
+    if (H.use_stencil && H.ca_deg > 0)
+      sweep_step_stencil<T>(s, H, H.amgC0T, H.sC0T, k + 1 < nt ? &H.sC1T : nullptr, k, 1.0 / dt,
+                            c + int64_t(k + 1) * na, k + 2 < nt ? &H.sC2T : nullptr, 0, -1.0 / (dt * dt),
+                            c + int64_t(k + 2) * na, ra + int64_t(k) * na, c + int64_t(k) * na, k, H.ca_deg, 2);
+    else
+      sweep_step<T>(s, H.amgC0T, H.C1t, nsg, sg, ra + int64_t(k) * na, c + int64_t(k) * na, k, H.ca_deg, vc);
   }
   // f = F_A^T c; y_A = M_A^{-1} f
   {
@@ -884,6 +1039,22 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
   H.adjoint = P.prob.adjoint;
   H.fu_deg = P.fu_deg;
   H.ca_deg = P.ca_deg;
+  H.use_stencil = P.use_stencil;
+  H.sFu = P.sFu;
+  H.sMu = P.sMu;
+  H.sC0 = P.sC0;
+  H.sC1 = P.sC1;
+  H.sC2 = P.sC2;
+  H.sFuT = P.sFuT;
+  H.sC0T = P.sC0T;
+  H.sC1T = P.sC1T;
+  H.sC2T = P.sC2T;
+  H.sMj = P.sMj;
+  H.sKjA = P.sKjA;
+  // One workgroup covers the C_A grid with at most one row per thread: then the
+  // chain kernel (no dispatch per step) beats per-step launches; on larger
+  // grids one CU is too slow for it.
+  H.use_chain = H.use_stencil && H.ca_deg > 0 && std::max(H.d.na, H.d.nj) <= kChainBlock ? 1 : 0;
   H.base = static_cast<char*>(ws);
   H.L = workspace_layout(P);
   char* base = H.base;
@@ -941,6 +1112,20 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
     delete hh;
     return ST_EHIP;
   }
+  // The second stream (default priority) and the chunk events of the pipelined sweeps.
+  H.chunk = std::max(4, (H.d.nt + 15) / 16);
+  if (H.d.nt > 1 && P.prob.single_stream == 0) {
+    const int nch = (H.d.nt + H.chunk - 1) / H.chunk;
+    bool ok = hipStreamCreateWithFlags(&H.s2, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&H.ev_fork, hipEventDisableTiming) == hipSuccess;
+    H.ev_chunk.assign(nch, nullptr);
+    for (int c = 0; ok && c < nch; ++c)
+      ok = hipEventCreateWithFlags(&H.ev_chunk[c], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      std::fprintf(stderr, "libst: second stream unavailable, sweeps run on one stream\n");
+      H.s2 = nullptr;
+    }
+  }
   *out = hh;
   return ST_OK;
 }
@@ -948,6 +1133,11 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
 int st_destroy(st_handle* h) {
   if (!h) return ST_OK;
   if (h->h.host_small) (void)hipHostFree(h->h.host_small);
+  if (h->h.s2) (void)hipStreamSynchronize(h->h.s2);
+  for (hipEvent_t e : h->h.ev_chunk)
+    if (e) (void)hipEventDestroy(e);
+  if (h->h.ev_fork) (void)hipEventDestroy(h->h.ev_fork);
+  if (h->h.s2) (void)hipStreamDestroy(h->h.s2);
   delete h;
   return ST_OK;
 }

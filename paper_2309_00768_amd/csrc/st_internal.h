@@ -164,6 +164,25 @@ int build_amg(Image& img, const Csr& a, int nsets, Grid2 grid, int fp32, int che
 // and stores the widened Chebyshev interval in out.cheb_alone.
 void estimate_interval(Image& img, const Csr& a, int nsets, Amg& out);
 
+// ------------------------------------------------------------ stencils ---
+// A block on a structured node grid stored as 5x5 stencil coefficients:
+// coef[set][slot][row], slot = c_col*25 + (dy+2)*5 + (dx+2), row = c*gx*gy +
+// iy*gx + ix.  Neighbours outside the grid have zero coefficients.  With
+// diag_comp the columns are taken from the row's own component only (25 slots).
+// Generalised: radius rad (3x3 or 5x5 neighbourhoods, w = 2 rad + 1, slot =
+// c_col*w*w + (dy+rad)*w + (dx+rad)) and a column grid cgx x cgy whose node
+// (ii, jj) sits at row-grid position (ii + shift, jj + shift) (e.g. interior
+// nodes of the full Q1 grid: shift 1).
+struct StencilOp {
+  int gx = 0, gy = 0, ncomp = 1, diag_comp = 0, nsets = 0, nslot = 0, fp32 = 0;
+  int rad = 2, cgx = 0, cgy = 0, shift = 0;
+  int64_t rows = 0;
+  Span coef;
+};
+// Returns false if an entry of `m` lies outside the neighbourhood.
+bool pack_stencil(Image& img, const Csr& m, int nsets, int gx, int gy, int ncomp, bool diag_comp, int fp32,
+                  StencilOp& out, int rad = 2, int cgx = 0, int cgy = 0, int shift = 0);
+
 // ---------------------------------------------------------------- plan ---
 struct Plan {
   st_problem prob{};
@@ -184,6 +203,10 @@ struct Plan {
   SellGroup Mu;                   // sweep coupling of F_u
   SellGroup C1, C2, C1t, C2t;     // sweep couplings of C_A
   SellGroup MA64;                 // M_A / dt in FP64 (initial-condition coupling)
+  // Stencil forms of the sweep operators (used with Chebyshev-alone sweeps).
+  StencilOp sFu, sMu, sC0, sC1, sC2, sFuT, sC0T, sC1T, sC2T;
+  StencilOp sMj, sKjA;            // 3x3 stencils of the single-workgroup C_A chain
+  int use_stencil = 0;
   Amg amgFu, amgC0, amgKp;        // spatial solvers (per-slab for Fu, C0; shared Kp)
   Amg amgFuT, amgC0T;             // transposed hierarchies for the adjoint
   Span mp_rowsum;                 // double [np]: 1^T M_p (pressure normalisation)
@@ -194,7 +217,7 @@ struct Plan {
 struct WsLayout {
   size_t V = 0, Z = 0, w = 0, r = 0, hess = 0, small = 0, partial = 0, psum = 0;
   size_t ru = 0, yu = 0, xu = 0, rp = 0, q = 0, t = 0, xp = 0, rj = 0, yj = 0;
-  size_t ra = 0, wA = 0, sA = 0, yA = 0, mr = 0, md0 = 0, md1 = 0;
+  size_t ra = 0, wA = 0, sA = 0, yA = 0, mr = 0, md0 = 0, md1 = 0, chr = 0, chd0 = 0, chd1 = 0;
   std::vector<size_t> kp_lev, fu_lev, ca_lev;   // 6 vectors per level each
   size_t end = 0;
 };
