@@ -57,6 +57,29 @@ def cpu_baseline(cfg, nt_sample, rtol):
                       f"single-threaded SuperLU/SciPy, host has {os.cpu_count()} logical CPUs)"}
 
 
+def probe_jacobian(cfg, ub, ab, b, dev, launches=5, copy_bytes=1 << 30):
+    """A few J applies and one device copy of `copy_bytes` (read + write), for
+    FETCH_SIZE / WRITE_SIZE counter runs: the copy calibrates the counters."""
+    import torch
+    from paper_2309_00768_amd import binding
+    plan = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp32")
+    N = plan.ns * cfg.nt
+    jbytes, _, _ = jacobian_bytes(plan, cfg.nt, N)
+    sysg = binding.System(plan, dev)
+    plan.close()
+    x = torch.from_numpy(b).to(dev)
+    y = torch.empty_like(x)
+    src = torch.ones(copy_bytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(launches):
+        sysg.apply_jacobian(x, y)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "jacobian", "launches": launches, "algorithmic_bytes_per_launch": jbytes,
+                      "copy_bytes_read": copy_bytes, "copy_bytes_written": copy_bytes}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +90,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-slabs", type=int, default=8)
+    ap.add_argument("--probe", choices=["jacobian"], default=None,
+                    help="run only a few J applies and a copy of known size (for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (one system is not sharded "
@@ -80,6 +105,9 @@ def main():
     ub, ab = inputs.state(cfg)
     b = inputs.rhs(cfg, cfg.rhs_seeds[0])
     dev = torch.device("cuda:0")
+    if args.probe == "jacobian":
+        probe_jacobian(cfg, ub, ab, b, dev)
+        return
     t0 = time.perf_counter()
     plan32 = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp32")
     N = plan32.ns * cfg.nt

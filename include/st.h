@@ -95,7 +95,8 @@ typedef struct st_problem {
                          1 SELL (same arithmetic, for comparison)            */
   int single_stream;  /* 1: run the whole of P_T^{-1} on the caller's stream
                          (no overlap of the C_A and F_u sweeps)               */
-  int reserved[4];
+  int sweep_chunk;    /* slabs per chunk of the pipelined C_A sweep (0: auto) */
+  int reserved[3];
   double inner_reduction; /* auto inner solver of F_u,k: target error reduction
                              per spatial solve (0: 0.1)                        */
   double ca_reduction;    /* auto inner solver of C_A,k: target reduction (0:

@@ -33,7 +33,7 @@ class StProblem(ctypes.Structure):
         ("mass_iters", ctypes.c_int), ("cheb_degree", ctypes.c_int), ("fu_solver", ctypes.c_int),
         ("ca_solver", ctypes.c_int), ("max_restart", ctypes.c_int), ("sell_sigma", ctypes.c_int),
         ("adjoint", ctypes.c_int), ("j_lanes", ctypes.c_int), ("sweep_format", ctypes.c_int),
-        ("single_stream", ctypes.c_int), ("reserved", ctypes.c_int * 4),
+        ("single_stream", ctypes.c_int), ("sweep_chunk", ctypes.c_int), ("reserved", ctypes.c_int * 3),
         ("inner_reduction", ctypes.c_double), ("ca_reduction", ctypes.c_double),
     ]
 
@@ -130,7 +130,7 @@ class Plan:
     def __init__(self, n, nt, dt, mu, eta, mu0, ubar, abar, jbar=None, precision="fp64", inner="amg",
                  inner_iters=0, mass_iters=0, cheb_degree=0, max_restart=0, sell_sigma=0, adjoint=False,
                  fu_solver=0, ca_solver=0, inner_reduction=0.0, j_lanes=0, ca_reduction=0.0, sweep_format=0,
-                 single_stream=False):
+                 single_stream=False, sweep_chunk=0):
         self._ub = np.ascontiguousarray(ubar, dtype=np.float64)
         self._ab = np.ascontiguousarray(abar, dtype=np.float64)
         assert self._ub.shape == (nt, 2, (2 * n + 1) ** 2) and self._ab.shape == (nt, (n + 1) ** 2)
@@ -145,6 +145,7 @@ class Plan:
         p.max_restart, p.sell_sigma, p.adjoint = max_restart, sell_sigma, int(adjoint)
         p.fu_solver, p.ca_solver, p.inner_reduction, p.j_lanes = fu_solver, ca_solver, inner_reduction, j_lanes
         p.ca_reduction, p.sweep_format, p.single_stream = ca_reduction, sweep_format, int(single_stream)
+        p.sweep_chunk = sweep_chunk
         self.problem = p
         self.n, self.nt = n, nt
         h = ctypes.c_void_p()

@@ -1113,7 +1113,8 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
     return ST_EHIP;
   }
   // The second stream (default priority) and the chunk events of the pipelined sweeps.
-  H.chunk = std::max(4, (H.d.nt + 15) / 16);
+  // About 16 chunks: the F_u sweep of a chunk starts as soon as its C_A part is done.
+  H.chunk = P.prob.sweep_chunk > 0 ? P.prob.sweep_chunk : std::max(4, (H.d.nt + 15) / 16);
   if (H.d.nt > 1 && P.prob.single_stream == 0) {
     const int nch = (H.d.nt + H.chunk - 1) / H.chunk;
     bool ok = hipStreamCreateWithFlags(&H.s2, hipStreamNonBlocking) == hipSuccess &&

@@ -143,7 +143,7 @@ def test_pipelined_sweeps_match_single_stream(precision, inner):
     out = []
     for single in (False, True):
         plan = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision=precision,
-                            inner=inner, single_stream=single)
+                            inner=inner, single_stream=single, sweep_chunk=6)
         sysg = binding.System(plan, "cuda:0")
         r = np.random.default_rng(9).standard_normal(ref.N)
         z = sysg.apply_precond(dev(r))
