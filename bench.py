@@ -92,6 +92,91 @@ def probe_jacobian(cfg, ub, ab, b, dev, launches=5, copy_bytes=1 << 30):
                       "copy_bytes_read": copy_bytes, "copy_bytes_written": copy_bytes}), flush=True)
 
 
+def bench_batch(args, dev):
+    """Uneven batch: 16 systems (n in {16,...,96}, Nt in {16,...,256}, dt = 1/Nt,
+    Re = S = 300), FP32 preconditioner, solved together in lockstep; a step is
+    one batched solve of every member to 1e-8.  The same systems solved one at
+    a time (each with its default two-stream preconditioner) are timed beside it."""
+    import torch
+    from paper_2309_00768_amd import binding, inputs
+    cfgs = inputs.batch_configs()
+    systems, rhs, singles, ntot = [], [], [], 0
+    t0 = time.perf_counter()
+    for c in cfgs:
+        ub, ab = inputs.state(c)
+        plan = binding.Plan(c.n, c.nt, c.dt, c.mu, c.eta, c.mu0, ub, ab, precision="fp32", single_stream=True,
+                            sweep_chain=False)
+        si = plan.solver_info()
+        systems.append(binding.System(plan, dev))
+        plan.close()
+        rhs.append(torch.from_numpy(inputs.rhs(c, c.rhs_seeds[0])).to(dev))
+        ntot += systems[-1].N
+        log(f"setup {c.name}: n={c.n} Nt={c.nt} N={systems[-1].N}, inner degrees F_u {si[0]} C_A {si[1]} "
+            f"(kappa {si[2]:.1f}, {si[3]:.1f})")
+    log(f"setup {time.perf_counter() - t0:.1f} s, {len(cfgs)} systems, N total {ntot}")
+    batch = binding.Batch(systems, restart=30)
+    lock, sep = batch.launch_counts()
+    chunk, cap = 240, 6000   # whole restart cycles per call; the next call restarts from the iterate
+
+    def solve_all():
+        xs = [torch.zeros_like(b) for b in rhs]
+        total = [0] * len(rhs)
+        for call in range(cap // chunk):
+            xs, infos, sts, rc, _ = batch.solve(rhs, xs, rtol=args.rtol, maxit=chunk, x0=call > 0)
+            total = [t + i.iterations for t, i in zip(total, infos)]
+            if rc < 0:
+                raise RuntimeError(f"batched solve: status {rc}, member statuses {sts}")
+            left = [k for k, st in enumerate(sts) if st != 0]
+            log(f"  {sum(total)} member iterations; not converged: "
+                f"{[(k, f'{infos[k].true_rel_residual:.1e}') for k in left]}")
+            if rc == 0:
+                return total
+        raise RuntimeError(f"batched solve did not reach {args.rtol:g} within {cap} iterations")
+
+    for i in range(args.warmup):
+        its = solve_all()
+        log(f"warmup {i}: {max(its)} max its")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [solve_all() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    dof_its = sum(s.N * k for its in runs for s, k in zip(systems, its))
+    its = runs[-1]
+    log(f"batched: {elapsed / args.steps:.2f} s per batch, iterations {its}")
+    out = {
+        "metric": METRIC, "value": dof_its / elapsed, "unit": "DOF-iter/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32-precond/f64-krylov", "data": "synthetic",
+        "config": {"workload": f"cfg4: {len(cfgs)} uneven systems (n, Nt) = "
+                               f"{[(c.n, c.nt) for c in cfgs]}, dt = 1/Nt, Re=S=300; lockstep FGMRES(30) to "
+                               f"{args.rtol:g}, P_T in FP32", "N_total": ntot},
+        "time_to_1e8_s": elapsed / args.steps, "fgmres_iters": its,
+        "launches_per_arnoldi_step": {"lockstep": lock, "one_at_a_time": sep},
+    }
+    if not args.no_separate:
+        # the same systems one at a time (same arithmetic, one stream each)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k, (sg, b) in enumerate(zip(systems, rhs)):
+            x = torch.zeros_like(b)
+            done = 0
+            for call in range(cap // chunk):
+                x, info, rc, _ = sg.solve(b, x, rtol=args.rtol, maxit=chunk, x0=call > 0)
+                done += info.iterations
+                if rc < 0:
+                    raise RuntimeError(f"separate solve: status {rc}")
+                if rc == 0:
+                    break
+            log(f"  one at a time: member {k} done ({done} its), {time.perf_counter() - t0:.1f} s")
+        torch.cuda.synchronize()
+        tsep = time.perf_counter() - t0
+        out["one_at_a_time_s"] = tsep
+        out["batch_speedup"] = tsep / (elapsed / args.steps)
+        log(f"one at a time: {tsep:.2f} s")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +187,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-slabs", type=int, default=16)
+    ap.add_argument("--no-separate", action="store_true", help="cfg4: skip the one-at-a-time comparison")
     ap.add_argument("--probe", choices=["jacobian"], default=None,
                     help="run only a few J applies and a copy of known size (for hardware-counter runs)")
     args = ap.parse_args()
@@ -113,10 +199,13 @@ def main():
     import torch
     from paper_2309_00768_amd import binding, inputs
 
+    dev = torch.device("cuda:0")
+    if args.config == "cfg4":
+        bench_batch(args, dev)
+        return
     cfg = inputs.CONFIGS[args.config]
     ub, ab = inputs.state(cfg)
     b = inputs.rhs(cfg, cfg.rhs_seeds[0])
-    dev = torch.device("cuda:0")
     if args.probe == "jacobian":
         probe_jacobian(cfg, ub, ab, b, dev)
         return

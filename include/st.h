@@ -92,16 +92,21 @@ typedef struct st_problem {
   int adjoint;        /* 1: also build the transposed operators (J^T, P_T^{-T}) */
   int j_lanes;        /* wavefront lanes per row of the J apply (0: auto)     */
   int sweep_format;   /* Chebyshev-alone sweeps: 0 structured 5x5 stencils,
-                         1 SELL (same arithmetic, for comparison)            */
+                         each step solving for its increment over a predictor
+                         from the earlier slabs (the approximate solve's error
+                         is then not amplified by the recursion in time);
+                         1 SELL, each step solved from zero (for comparison:
+                         the two agree when the spatial solves converge)    */
   int single_stream;  /* 1: run the whole of P_T^{-1} on the caller's stream
                          (no overlap of the C_A and F_u sweeps)               */
   int sweep_chunk;    /* slabs per chunk of the pipelined C_A sweep (0: auto) */
-  int reserved[3];
+  int sweep_chain;    /* 0: on grids of at most 1024 unknowns the C_A sweep and
+                         the M_j solves of a chunk run in one workgroup (no
+                         launch per step); -1: never (per-step launches)      */
+  int reserved[2];
   double inner_reduction; /* auto inner solver of F_u,k: target error reduction
                              per spatial solve (0: 0.1)                        */
-  double ca_reduction;    /* auto inner solver of C_A,k: target reduction (0:
-                             min(0.05, 0.25/Nt); the C_A sweep is a second-order
-                             recursion in time that accumulates inner errors)  */
+  double ca_reduction;    /* auto inner solver of C_A,k: target reduction (0: 0.05) */
 } st_problem;
 
 typedef struct st_opts {
@@ -128,6 +133,7 @@ typedef struct st_info {
 
 typedef struct st_plan st_plan;       /* host-side setup result             */
 typedef struct st_handle st_handle;   /* device-resident system             */
+typedef struct st_batch st_batch;     /* lockstep solver over several systems */
 
 /* ---------------------------------------------------------------- setup --- */
 
@@ -202,6 +208,40 @@ int st_fgmres_solve(st_handle* h, const double* b, double* x, const st_opts* o,
 /* Adjoint solve J^T lam = g with FGMRES right-preconditioned by P_T^{-T}. */
 int st_adjoint_solve(st_handle* h, const double* g, double* lam, const st_opts* o,
                      st_info* info, void* stream);
+
+/* ------------------------------------------------------------ batches --- */
+/* Many independent space-time systems (uneven n and Nt) solved together: the
+ * same right-preconditioned FGMRES(m) as st_fgmres_solve on each member, run
+ * in lockstep so that one launch carries the same step of every member (a
+ * sweep step, a Gram-Schmidt pass, ...).  Each member's arithmetic, and so its
+ * iterates and result, is the one st_fgmres_solve produces on that handle
+ * with single_stream = 1 and sweep_chain = -1.
+ *
+ * st_batch_create: host-only; records the launch programs of the members.
+ *   hs: 1..32 distinct handles with the same precond_precision, each with
+ *   max_restart >= restart (0: 30).  The handles must outlive the batch and
+ *   must not be used by other calls while a batched solve runs.
+ * st_batch_workspace_size: device bytes the batch needs besides the handles'
+ *   workspaces (argument blocks of the recorded launches).
+ * st_batch_upload: copies the recorded launches into `ws` (caller-owned,
+ *   256-byte aligned, >= the workspace size) on `stream` and waits for it.
+ * st_batch_launch_counts: launches of one Arnoldi step (preconditioner, J and
+ *   Gram-Schmidt) in lockstep and summed over members solved one at a time.  */
+int st_batch_create(st_handle* const* hs, int nsys, int restart, st_batch** out);
+int st_batch_workspace_size(const st_batch* b, size_t* bytes);
+int st_batch_upload(st_batch* b, void* ws, size_t ws_bytes, void* stream);
+int st_batch_launch_counts(const st_batch* b, int64_t* lockstep, int64_t* separate);
+
+/* Solves J_i x_i = b_i for every member i (b, x: host arrays of nsys device
+ * pointers, each of that member's length N_i).  o->restart must be 0 or the
+ * batch's restart; the history buffer, if given, holds nsys rows of
+ * history_len entries.  infos[i] (and statuses[i] if not NULL) receive each
+ * member's result and status; seconds is the wall time of the whole batch and
+ * the per-phase times are 0.  Returns ST_OK if every member converged,
+ * ST_ENOTCONV if some did not, else the first error.  Blocks until done. */
+int st_fgmres_solve_batched(st_batch* b, const double* const* bvec, double* const* x, const st_opts* o,
+                            st_info* infos, int* statuses, void* stream);
+int st_batch_destroy(st_batch* b);
 
 /* Sizes of a created system: N, Ns, Nt. */
 int st_sizes(const st_handle* h, int64_t* n_total, int* ns, int* nt);

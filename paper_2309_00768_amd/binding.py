@@ -33,7 +33,8 @@ class StProblem(ctypes.Structure):
         ("mass_iters", ctypes.c_int), ("cheb_degree", ctypes.c_int), ("fu_solver", ctypes.c_int),
         ("ca_solver", ctypes.c_int), ("max_restart", ctypes.c_int), ("sell_sigma", ctypes.c_int),
         ("adjoint", ctypes.c_int), ("j_lanes", ctypes.c_int), ("sweep_format", ctypes.c_int),
-        ("single_stream", ctypes.c_int), ("sweep_chunk", ctypes.c_int), ("reserved", ctypes.c_int * 3),
+        ("single_stream", ctypes.c_int), ("sweep_chunk", ctypes.c_int), ("sweep_chain", ctypes.c_int),
+        ("reserved", ctypes.c_int * 2),
         ("inner_reduction", ctypes.c_double), ("ca_reduction", ctypes.c_double),
     ]
 
@@ -58,7 +59,8 @@ EXPORTED = [
     "st_plan_solver_info",
     "st_plan_destroy", "st_create", "st_destroy", "st_apply_jacobian", "st_apply_jacobian_t",
     "st_apply_precond", "st_apply_precond_t", "st_apply_initial_coupling", "st_fgmres_solve", "st_adjoint_solve",
-    "st_sizes",
+    "st_sizes", "st_batch_create", "st_batch_workspace_size", "st_batch_upload", "st_batch_launch_counts",
+    "st_fgmres_solve_batched", "st_batch_destroy",
     "st_error_string",
 ]
 
@@ -88,6 +90,13 @@ def _load(path=LIB_PATH):
         "st_fgmres_solve": ([vp, vp, vp, ctypes.POINTER(StOpts), ctypes.POINTER(StInfo), vp], ctypes.c_int),
         "st_adjoint_solve": ([vp, vp, vp, ctypes.POINTER(StOpts), ctypes.POINTER(StInfo), vp], ctypes.c_int),
         "st_sizes": ([vp, i64p, ip, ip], ctypes.c_int),
+        "st_batch_create": ([ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
+        "st_batch_workspace_size": ([vp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "st_batch_upload": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
+        "st_batch_launch_counts": ([vp, i64p, i64p], ctypes.c_int),
+        "st_fgmres_solve_batched": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(StOpts),
+                                     ctypes.POINTER(StInfo), ip, vp], ctypes.c_int),
+        "st_batch_destroy": ([vp], ctypes.c_int),
         "st_error_string": ([ctypes.c_int], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -130,7 +139,7 @@ class Plan:
     def __init__(self, n, nt, dt, mu, eta, mu0, ubar, abar, jbar=None, precision="fp64", inner="amg",
                  inner_iters=0, mass_iters=0, cheb_degree=0, max_restart=0, sell_sigma=0, adjoint=False,
                  fu_solver=0, ca_solver=0, inner_reduction=0.0, j_lanes=0, ca_reduction=0.0, sweep_format=0,
-                 single_stream=False, sweep_chunk=0):
+                 single_stream=False, sweep_chunk=0, sweep_chain=True):
         self._ub = np.ascontiguousarray(ubar, dtype=np.float64)
         self._ab = np.ascontiguousarray(abar, dtype=np.float64)
         assert self._ub.shape == (nt, 2, (2 * n + 1) ** 2) and self._ab.shape == (nt, (n + 1) ** 2)
@@ -146,6 +155,7 @@ class Plan:
         p.fu_solver, p.ca_solver, p.inner_reduction, p.j_lanes = fu_solver, ca_solver, inner_reduction, j_lanes
         p.ca_reduction, p.sweep_format, p.single_stream = ca_reduction, sweep_format, int(single_stream)
         p.sweep_chunk = sweep_chunk
+        p.sweep_chain = 0 if sweep_chain else -1
         self.problem = p
         self.n, self.nt = n, nt
         h = ctypes.c_void_p()
@@ -279,6 +289,72 @@ class System:
     def close(self):
         if getattr(self, "ptr", None):
             lib().st_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Lockstep FGMRES over several systems (``st_batch_*``, ``st_fgmres_solve_batched``).
+
+    The systems must share the preconditioner precision and stay alive while
+    the batch exists; the batch's own device memory (the recorded launches) is
+    a torch tensor.
+    """
+
+    def __init__(self, systems, restart=30, stream=None):
+        import torch
+        self.systems = list(systems)
+        n = len(self.systems)
+        arr = (ctypes.c_void_p * n)(*[s.ptr.value for s in self.systems])
+        h = ctypes.c_void_p()
+        _check(lib().st_batch_create(arr, n, restart, ctypes.byref(h)), "st_batch_create")
+        self.ptr = h
+        self.restart = restart
+        wb = ctypes.c_size_t()
+        _check(lib().st_batch_workspace_size(self.ptr, ctypes.byref(wb)), "st_batch_workspace_size")
+        self.workspace_bytes = wb.value
+        dev = self.systems[0].device
+        self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=dev)
+        self._ws_ptr = (self.ws.data_ptr() + 255) & ~255
+        _check(lib().st_batch_upload(self.ptr, ctypes.c_void_p(self._ws_ptr), ctypes.c_size_t(self.workspace_bytes),
+                                     _stream_ptr(stream)), "st_batch_upload")
+
+    def launch_counts(self):
+        """(lockstep, separate) launches of one Arnoldi step over the batch."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().st_batch_launch_counts(self.ptr, ctypes.byref(a), ctypes.byref(b)), "launch_counts")
+        return a.value, b.value
+
+    def solve(self, bs, xs=None, rtol=1e-8, atol=0.0, maxit=1000, x0=False, history=0, stream=None):
+        """Solves every member; returns (xs, infos, statuses, rc, histories)."""
+        import torch
+        n = len(self.systems)
+        assert len(bs) == n
+        xs = [torch.zeros_like(b) for b in bs] if xs is None else xs
+        for s, b, x in zip(self.systems, bs, xs):
+            s._vec(b)
+            s._vec(x)
+        barr = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs])
+        xarr = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        o = StOpts()
+        o.restart, o.maxit, o.rtol, o.atol, o.x0_given = self.restart, maxit, rtol, atol, int(x0)
+        hist = np.zeros((n, max(history, 0)))
+        o.history_len = hist.shape[1]
+        o.history = _dptr(hist) if hist.size else ctypes.POINTER(ctypes.c_double)()
+        infos = (StInfo * n)()
+        st = (ctypes.c_int * n)()
+        rc = _check(lib().st_fgmres_solve_batched(self.ptr, barr, xarr, ctypes.byref(o), infos, st,
+                                                  _stream_ptr(stream)), "st_fgmres_solve_batched")
+        return xs, list(infos), list(st), rc, hist
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().st_batch_destroy(self.ptr)
             self.ptr = None
 
     def __del__(self):

@@ -110,10 +110,10 @@ __device__ inline TA group_sum(TA v, int lanes) {
 }
 
 // y[v][row] = sum_seg alpha_seg (A_seg x_seg)[row] + beta b[v][row]
-template <class T, class TX, class TA, int Role>
-__global__ ST_LATENCY_KERNEL void k_spmv(SpmvArgs<T, TX> a) {
-  const int v = blockIdx.y;
-  const int slice = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
+// Workgroup bx covers slices 4 bx .. 4 bx + 3 of vector v.
+template <class T, class TX, class TA>
+__device__ inline void spmv_body(const SpmvArgs<T, TX>& a, int bx, int v) {
+  const int slice = bx * (kBlock / kWave) + (threadIdx.x / kWave);
   if (slice >= a.nslices) return;          // uniform per wavefront
   const int lane = threadIdx.x % kWave;
   const int L = a.lanes;
@@ -146,6 +146,11 @@ __global__ ST_LATENCY_KERNEL void k_spmv(SpmvArgs<T, TX> a) {
   a.y[int64_t(v) * a.ystride + row] = TX(acc);
 }
 
+template <class T, class TX, class TA, int Role>
+__global__ ST_LATENCY_KERNEL void k_spmv(SpmvArgs<T, TX> a) {
+  spmv_body<T, TX, TA>(a, blockIdx.x, blockIdx.y);
+}
+
 // Fused Chebyshev-Jacobi step for A x = b (A one SELL segment), per vector v.
 //   mode 0: r = b (if b), d_new = Dinv r / theta, x = d_new (or x += d_new)
 //   mode 1: r -= A d_old; d_new = c1 d_old + c2 Dinv r; x += d_new   (step >= 1)
@@ -174,10 +179,9 @@ struct ChebArgs {
 };
 
 // Role: 0 mass-matrix solves, 1 finest AMG level / single-level solves, 2 coarser AMG levels.
-template <class T, int Role>
-__global__ ST_LATENCY_KERNEL void k_cheb(ChebArgs<T> a) {
-  const int v = blockIdx.y;
-  const int slice = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
+template <class T>
+__device__ inline void cheb_body(const ChebArgs<T>& a, int bx, int v) {
+  const int slice = bx * (kBlock / kWave) + (threadIdx.x / kWave);
   if (slice >= a.nslices) return;          // uniform per wavefront
   const int lane = threadIdx.x % kWave;
   const int L = a.lanes;
@@ -223,6 +227,11 @@ __global__ ST_LATENCY_KERNEL void k_cheb(ChebArgs<T> a) {
   const T d = c1 * d0[row] + c2 * dg * rn;
   a.dnew[o + row] = d;
   a.x[o + row] += d;
+}
+
+template <class T, int Role>
+__global__ ST_LATENCY_KERNEL void k_cheb(ChebArgs<T> a) {
+  cheb_body<T>(a, blockIdx.x, blockIdx.y);
 }
 
 // ------------------------------------------------------------ stencils ---
@@ -273,7 +282,10 @@ __device__ inline TA stencil_row(const StOp<T>& A, int set, int64_t row, const T
 }
 
 // First step of a sweep solve with Chebyshev-Jacobi alone, fused with the
-// sweep right-hand side: q' = q + a1 S1 y1 + a2 S2 y2, r = q', d = Dinv q'/theta, x = d.
+// sweep right-hand side: r = q + a1 S1 y1 + a2 S2 y2, d = Dinv r/theta and
+// x = x0 + d, where the predictor x0 = g1 y1 + g2 y2 (guess != 0) or 0.  With a
+// predictor the couplings S1, S2 already contain the diagonal block's action
+// on it, so that r is the residual of x0.
 template <class T>
 struct StInitArgs {
   StOp<T> S1, S2;
@@ -288,19 +300,31 @@ struct StInitArgs {
   T* d;
   T* x;
   int64_t rows;
+  int guess;
+  double g1, g2;
 };
 
-template <class T, int Role>
-__global__ ST_LATENCY_KERNEL void k_st_init(StInitArgs<T> a) {
-  const int64_t row = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+template <class T>
+__device__ inline void st_init_body(const StInitArgs<T>& a, int bx) {
+  const int64_t row = int64_t(bx) * kBlock + threadIdx.x;
   if (row >= a.rows) return;
   T acc = a.q[row];
   if (a.n1) acc += T(a.a1) * stencil_row<2, T, T>(a.S1, a.set1, row, a.y1);
   if (a.n2) acc += T(a.a2) * stencil_row<2, T, T>(a.S2, a.set2, row, a.y2);
   const T d = a.dinv[row] * acc / T(a.theta);
+  T x0 = T(0);
+  if (a.guess) {
+    x0 = T(a.g1) * a.y1[row];
+    if (a.g2 != 0.0) x0 += T(a.g2) * a.y2[row];
+  }
   a.r[row] = acc;
   a.d[row] = d;
-  a.x[row] = d;
+  a.x[row] = x0 + d;
+}
+
+template <class T, int Role>
+__global__ ST_LATENCY_KERNEL void k_st_init(StInitArgs<T> a) {
+  st_init_body<T>(a, blockIdx.x);
 }
 
 // Chebyshev step i >= 1 on a stencil operator: r -= A d_old; d_new = c1 d_old + c2 Dinv r; x += d_new.
@@ -317,9 +341,9 @@ struct StChebArgs {
   int64_t rows;
 };
 
-template <class T, int Role>
-__global__ ST_LATENCY_KERNEL void k_st_cheb(StChebArgs<T> a) {
-  const int64_t row = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+template <class T>
+__device__ inline void st_cheb_body(const StChebArgs<T>& a, int bx) {
+  const int64_t row = int64_t(bx) * kBlock + threadIdx.x;
   if (row >= a.rows) return;
   const T od = a.dold[row];
   const T dg = a.dinv[row];
@@ -332,14 +356,20 @@ __global__ ST_LATENCY_KERNEL void k_st_cheb(StChebArgs<T> a) {
   a.x[row] += d;
 }
 
+template <class T, int Role>
+__global__ ST_LATENCY_KERNEL void k_st_cheb(StChebArgs<T> a) {
+  st_cheb_body<T>(a, blockIdx.x);
+}
+
 // The C_A sweep for slabs [k0, k1) in one workgroup, each slab followed by
 // its current solve y_j = M_j^{-1}(r_j - K_jA y_A): Chebyshev-Jacobi of degree
-// `deg` on C_A,k (first step fused with the sweep right-hand side
-// s^k + (1/dt) C1_{k-1} y^{k-1} - (1/dt^2) C2 y^{k-2}) and of degree `mit` on
+// `deg` on C_A,k for the increment over the predictor (y^0 for slab 1,
+// 2 y^{k-1} - y^{k-2} after; first step fused with the residual
+// s^k + P_k y^{k-1} + Q_k y^{k-2} of the predictor) and of degree `mit` on
 // M_j.  Only workgroup barriers: no inter-workgroup synchronisation.
 template <class T>
 struct ChainArgs {
-  StOp<T> C0, C1, C2, Mj, KjA;
+  StOp<T> C0, CP, CQ, Mj, KjA;
   int k0, k1, deg, mit, na, nj;
   double dt;
   const double* alone;  // (theta, delta) per slab for C_A
@@ -367,15 +397,23 @@ __global__ __launch_bounds__(kChainBlock) void k_ca_chain(ChainArgs<T> a) {
     const T* dinv = a.dinvC + int64_t(k) * a.dinv_stride;
     T* yk = a.yA + int64_t(k) * na;
     const T* sk = a.sA + int64_t(k) * na;
-    const T inv_dt = T(1.0 / a.dt), inv_dt2 = T(1.0 / (a.dt * a.dt));
     for (int row = tid; row < na; row += kChainBlock) {
       T acc = sk[row];
-      if (k >= 1) acc += inv_dt * stencil_row<2, T, T>(a.C1, k - 1, row, a.yA + int64_t(k - 1) * na);
-      if (k >= 2) acc -= inv_dt2 * stencil_row<2, T, T>(a.C2, 0, row, a.yA + int64_t(k - 2) * na);
+      T x0 = T(0);
+      if (k >= 1) {
+        const T* y1 = a.yA + int64_t(k - 1) * na;
+        acc += stencil_row<2, T, T>(a.CP, k, row, y1);
+        x0 = y1[row];
+      }
+      if (k >= 2) {
+        const T* y2 = a.yA + int64_t(k - 2) * na;
+        acc += stencil_row<2, T, T>(a.CQ, k, row, y2);
+        x0 = T(2) * x0 - y2[row];
+      }
       const T dd = dinv[row] * acc / T(theta);
       a.r[row] = acc;
       a.d0[row] = dd;
-      yk[row] = dd;
+      yk[row] = x0 + dd;
     }
     __syncthreads();
     {
@@ -433,21 +471,39 @@ __global__ __launch_bounds__(kChainBlock) void k_ca_chain(ChainArgs<T> a) {
 }
 
 // Coarsest AMG level: x[v] (+)= Ainv(set) * b[v]; Ainv stored column-major.
+constexpr int kMaxCoarse = 512;
+
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_coarse(int n, const T* inv, int64_t istride, int set_base, int set_step,
-                                                    const T* b, T* x, int64_t vec, int accumulate) {
-  __shared__ T sb[512];
-  const int v = blockIdx.x;
-  const int set = set_base + v * set_step;
-  const T* A = inv + (istride ? int64_t(set) * istride : 0);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) sb[i] = b[int64_t(v) * vec + i];
+struct CoarseArgs {
+  int n;                // coarse size, <= kMaxCoarse
+  const T* inv;
+  int64_t istride;      // per-set stride of the inverses (0 = shared)
+  int set_base, set_step;
+  const T* b;
+  T* x;
+  int64_t vec;
+  int accumulate;
+};
+
+template <class T>
+__device__ inline void coarse_body(const CoarseArgs<T>& a, int v) {
+  __shared__ T sb[kMaxCoarse];
+  const int n = a.n;
+  const int set = a.set_base + v * a.set_step;
+  const T* A = a.inv + (a.istride ? int64_t(set) * a.istride : 0);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sb[i] = a.b[int64_t(v) * a.vec + i];
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     T s = T(0);
     for (int j = 0; j < n; ++j) s += A[int64_t(j) * n + i] * sb[j];
-    T* xp = x + int64_t(v) * vec + i;
-    *xp = accumulate ? *xp + s : s;
+    T* xp = a.x + int64_t(v) * a.vec + i;
+    *xp = a.accumulate ? *xp + s : s;
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_coarse(CoarseArgs<T> a) {
+  coarse_body<T>(a, blockIdx.x);
 }
 
 // ----------------------------------------------------------- reductions ---

@@ -1,0 +1,341 @@
+// Vector kernels of libst: the precision boundary and pressure handling of
+// P_T^{-1}, and the FGMRES building blocks (multi-dot, Gram-Schmidt update,
+// Givens rotations, back substitution).  Each kernel is a device body taking
+// explicit workgroup coordinates (bx, by) and the x-extent gx of its grid,
+// plus a thin __global__ wrapper, so that the batched launcher can run the
+// same body for several systems in one launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace st {
+
+// Index of the current Krylov vector for a preconditioner apply whose input
+// and output are columns of V and Z (batched solves); null: use the pointers.
+__device__ inline int64_t jsel_offset(const int* jsel, int64_t jstride) {
+  return jsel ? int64_t(*jsel) * jstride : 0;
+}
+
+// Per-slab sums of src[k*ld + off + i], i < len (weights w[i] if w): out[k]; bx = k.
+struct SlabSumsDArgs {
+  const double* src;
+  int64_t ld;
+  int off, len;
+  const double* w;
+  double* out;
+  const int* jsel;
+  int64_t jstride;
+};
+
+__device__ inline void slab_sums_d_body(const SlabSumsDArgs& a, int k) {
+  const double* p = a.src + jsel_offset(a.jsel, a.jstride) + int64_t(k) * a.ld + a.off;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < a.len; i += blockDim.x) acc += (a.w ? a.w[i] : 1.0) * p[i];
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) a.out[k] = acc;
+}
+
+template <class T>
+struct SlabSumsTArgs {
+  const T* src;
+  int64_t ld;
+  int len;
+  const double* w;
+  double* out;
+};
+
+template <class T>
+__device__ inline void slab_sums_t_body(const SlabSumsTArgs<T>& a, int k) {
+  const T* p = a.src + int64_t(k) * a.ld;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < a.len; i += blockDim.x) acc += (a.w ? a.w[i] : 1.0) * double(p[i]);
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) a.out[k] = acc;
+}
+
+// Split an FP64 slab-major vector into per-block arrays (precision T); the
+// pressure rows lose their per-slab mean psum[k] / np.
+template <class T>
+struct SplitArgs {
+  const double* r;
+  int ns, nt, o2, o3, o4;
+  const double* psum;
+  T *ru, *rp, *rj, *ra;
+  const int* jsel;
+  int64_t jstride;
+};
+
+template <class T>
+__device__ inline void split_body(const SplitArgs<T>& a, int bx, int gx) {
+  const int64_t N = int64_t(a.ns) * a.nt;
+  const int ns = a.ns, o2 = a.o2, o3 = a.o3, o4 = a.o4;
+  const int np = o3 - o2, nj = o4 - o3, na = ns - o4;
+  const double* r = a.r + jsel_offset(a.jsel, a.jstride);
+  for (int64_t i = bx * int64_t(kBlock) + threadIdx.x; i < N; i += int64_t(gx) * kBlock) {
+    const int k = int(i / ns), c = int(i % ns);
+    const double v = r[i];
+    if (c < o2) a.ru[int64_t(k) * o2 + c] = T(v);
+    else if (c < o3) a.rp[int64_t(k) * np + (c - o2)] = T(v - a.psum[k] / np);
+    else if (c < o4) a.rj[int64_t(k) * nj + (c - o3)] = T(v);
+    else a.ra[int64_t(k) * na + (c - o4)] = T(v);
+  }
+}
+
+// Join per-block arrays into an FP64 slab-major vector; pressure is
+// psign * xp shifted so that 1^T M_p p^k = 0 (wsum[k] = m . xp^k, msum = sum m).
+template <class T>
+struct JoinArgs {
+  double* z;
+  int ns, nt, o2, o3, o4;
+  const T* xu;
+  const T* xp;
+  double psign;
+  const double* wsum;
+  double msum;
+  const T* yj;
+  const T* ya;
+  const int* jsel;
+  int64_t jstride;
+};
+
+template <class T>
+__device__ inline void join_body(const JoinArgs<T>& a, int bx, int gx) {
+  const int64_t N = int64_t(a.ns) * a.nt;
+  const int ns = a.ns, o2 = a.o2, o3 = a.o3, o4 = a.o4;
+  const int np = o3 - o2, nj = o4 - o3, na = ns - o4;
+  double* z = a.z + jsel_offset(a.jsel, a.jstride);
+  for (int64_t i = bx * int64_t(kBlock) + threadIdx.x; i < N; i += int64_t(gx) * kBlock) {
+    const int k = int(i / ns), c = int(i % ns);
+    double v;
+    if (c < o2) v = double(a.xu[int64_t(k) * o2 + c]);
+    else if (c < o3) v = a.psign * (double(a.xp[int64_t(k) * np + (c - o2)]) - a.wsum[k] / a.msum);
+    else if (c < o4) v = double(a.yj[int64_t(k) * nj + (c - o3)]);
+    else v = double(a.ya[int64_t(k) * na + (c - o4)]);
+    z[i] = v;
+  }
+}
+
+// x[k*ld + i] -= sums[k] * scale (i < len)
+template <class T>
+struct SlabShiftArgs {
+  T* x;
+  int64_t ld;
+  int len, nt;
+  const double* sums;
+  double scale;
+};
+
+template <class T>
+__device__ inline void slab_shift_body(const SlabShiftArgs<T>& a, int bx, int gx) {
+  const int64_t N = int64_t(a.len) * a.nt;
+  for (int64_t i = bx * int64_t(kBlock) + threadIdx.x; i < N; i += int64_t(gx) * kBlock) {
+    const int k = int(i / a.len), c = int(i % a.len);
+    T* p = a.x + int64_t(k) * a.ld + c;
+    *p = T(double(*p) - a.sums[k] * a.scale);
+  }
+}
+
+// FP64 slab-major: p rows (offset o2..o3) minus psum[k]/np, written to dst.
+struct ProjectPArgs {
+  const double* src;
+  double* dst;
+  int ns, nt, o2, o3;
+  const double* psum;
+};
+
+__device__ inline void project_p_body(const ProjectPArgs& a, int bx, int gx) {
+  const int64_t N = int64_t(a.ns) * a.nt;
+  const int np = a.o3 - a.o2;
+  for (int64_t i = bx * int64_t(kBlock) + threadIdx.x; i < N; i += int64_t(gx) * kBlock) {
+    const int k = int(i / a.ns), c = int(i % a.ns);
+    double v = a.src[i];
+    if (c >= a.o2 && c < a.o3) v -= a.psum[k] / np;
+    a.dst[i] = v;
+  }
+}
+
+// partial[i * gx + bx] = sum over the workgroup's rows of V_i . w   (i = by)
+struct MdotArgs {
+  const double* V;
+  int64_t N;
+  const double* w;
+  double* partial;
+};
+
+__device__ inline void mdot_body(const MdotArgs& a, int bx, int i, int gx) {
+  const double* v = a.V + int64_t(i) * a.N;
+  double acc = 0.0;
+  for (int64_t r = bx * int64_t(kBlock) + threadIdx.x; r < a.N; r += int64_t(gx) * kBlock) acc += v[r] * a.w[r];
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) a.partial[int64_t(i) * gx + bx] = acc;
+}
+
+// out[i] (+)= sum_b partial[i * nb + b]  (i = bx); mode 1: out[0] = sqrt(sum), mode 2: add.
+struct ReduceArgs {
+  const double* partial;
+  int nb;
+  double* out;
+  int mode;
+  double* copy_to;
+};
+
+__device__ inline void reduce_body(const ReduceArgs& a, int i) {
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < a.nb; b += kBlock) acc += a.partial[int64_t(i) * a.nb + b];
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) {
+    if (a.mode == 1) acc = std::sqrt(acc);
+    if (a.mode == 2) a.out[i] += acc;
+    else a.out[i] = acc;
+    if (a.copy_to) a.copy_to[i] = a.out[i];
+  }
+}
+
+// w -= sum_{i < nv} h[i] V_i   (sign -1), or x += sum_i y[i] Z_i (sign +1)
+struct CombineArgs {
+  double* w;
+  const double* V;
+  int64_t N;
+  const double* h;
+  int nv;
+  double sign;
+};
+
+__device__ inline void combine_body(const CombineArgs& a, int bx, int gx) {
+  for (int64_t r = bx * int64_t(kBlock) + threadIdx.x; r < a.N; r += int64_t(gx) * kBlock) {
+    double acc = a.w[r];
+    if (a.sign < 0.0)
+      for (int i = 0; i < a.nv; ++i) acc -= a.h[i] * a.V[int64_t(i) * a.N + r];
+    else
+      for (int i = 0; i < a.nv; ++i) acc += a.h[i] * a.V[int64_t(i) * a.N + r];
+    a.w[r] = acc;
+  }
+}
+
+// dst = src / *nrm (zero if the norm is zero)
+struct ScaleArgs {
+  double* dst;
+  const double* src;
+  int64_t N;
+  const double* nrm;
+};
+
+__device__ inline void scale_body(const ScaleArgs& a, int bx, int gx) {
+  const double s = *a.nrm;
+  const double f = s != 0.0 ? 1.0 / s : 0.0;
+  for (int64_t r = bx * int64_t(kBlock) + threadIdx.x; r < a.N; r += int64_t(gx) * kBlock) a.dst[r] = a.src[r] * f;
+}
+
+// Givens update of Hessenberg column j (rotations 0..j-1 applied, rotation j
+// formed); g is the rotated right-hand side; est = |g[j+1]|.  One thread.
+struct GivensArgs {
+  double* H;      // column j at H + j * ldh
+  int j, ldh;
+  double *g, *cs, *sn, *est;
+};
+
+__device__ inline void givens_body(const GivensArgs& a) {
+  if (threadIdx.x != 0) return;
+  double* h = a.H + int64_t(a.j) * a.ldh;
+  const int j = a.j;
+  for (int i = 0; i < j; ++i) {
+    const double t = a.cs[i] * h[i] + a.sn[i] * h[i + 1];
+    h[i + 1] = -a.sn[i] * h[i] + a.cs[i] * h[i + 1];
+    h[i] = t;
+  }
+  const double x = h[j], y = h[j + 1];
+  const double d = std::hypot(x, y);
+  const double c = d != 0.0 ? x / d : 1.0, s = d != 0.0 ? y / d : 0.0;
+  a.cs[j] = c;
+  a.sn[j] = s;
+  h[j] = d;
+  h[j + 1] = 0.0;
+  a.g[j + 1] = -s * a.g[j];
+  a.g[j] = c * a.g[j];
+  a.est[0] = std::fabs(a.g[j + 1]);
+}
+
+// Back substitution of the rotated upper-triangular m x m system H y = g.  One thread.
+struct TrisolveArgs {
+  const double* H;
+  int m, ldh;
+  const double* g;
+  double* y;
+};
+
+__device__ inline void trisolve_body(const TrisolveArgs& a) {
+  if (threadIdx.x != 0) return;
+  for (int i = a.m - 1; i >= 0; --i) {
+    double acc = a.g[i];
+    for (int l = i + 1; l < a.m; ++l) acc -= a.H[int64_t(l) * a.ldh + i] * a.y[l];
+    a.y[i] = acc / a.H[int64_t(i) * a.ldh + i];
+  }
+}
+
+// g = (beta, 0, ..., 0), m1 entries.
+struct InitGArgs {
+  double* g;
+  int m1;
+  const double* beta;
+};
+
+__device__ inline void init_g_body(const InitGArgs& a) {
+  for (int i = threadIdx.x; i < a.m1; i += blockDim.x) a.g[i] = i == 0 ? *a.beta : 0.0;
+}
+
+// x[i] = v for i < n (also clears memory in place of a memset).
+struct FillArgs {
+  double* x;
+  int64_t n;
+  double v;
+};
+
+__device__ inline void fill_body(const FillArgs& a, int bx, int gx) {
+  for (int64_t i = bx * int64_t(kBlock) + threadIdx.x; i < a.n; i += int64_t(gx) * kBlock) a.x[i] = a.v;
+}
+
+// dst[i] = src[i] for i < n (small gathers), then *iset = ival if iset.
+struct CopySmallArgs {
+  const double* src;
+  double* dst;
+  int n;
+  int* iset;
+  int ival;
+};
+
+__device__ inline void copy_small_body(const CopySmallArgs& a) {
+  for (int i = threadIdx.x; i < a.n; i += blockDim.x) a.dst[i] = a.src[i];
+  if (a.iset && threadIdx.x == 0) *a.iset = a.ival;
+}
+
+// ------------------------------------------------------------ wrappers ---
+__global__ __launch_bounds__(kBlock) void k_slab_sums_d(SlabSumsDArgs a) { slab_sums_d_body(a, blockIdx.x); }
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_slab_sums_t(SlabSumsTArgs<T> a) { slab_sums_t_body<T>(a, blockIdx.x); }
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_split(SplitArgs<T> a) { split_body<T>(a, blockIdx.x, gridDim.x); }
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_join(JoinArgs<T> a) { join_body<T>(a, blockIdx.x, gridDim.x); }
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_slab_shift(SlabShiftArgs<T> a) {
+  slab_shift_body<T>(a, blockIdx.x, gridDim.x);
+}
+__global__ __launch_bounds__(kBlock) void k_project_p(ProjectPArgs a) { project_p_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kBlock) void k_mdot_partial(MdotArgs a) {
+  mdot_body(a, blockIdx.x, blockIdx.y, gridDim.x);
+}
+__global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) { reduce_body(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_combine(CombineArgs a) { combine_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kBlock) void k_scale(ScaleArgs a) { scale_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kBlock) void k_givens(GivensArgs a) { givens_body(a); }
+__global__ __launch_bounds__(kBlock) void k_trisolve(TrisolveArgs a) { trisolve_body(a); }
+__global__ __launch_bounds__(kBlock) void k_init_g(InitGArgs a) { init_g_body(a); }
+__global__ __launch_bounds__(kBlock) void k_fill(FillArgs a) { fill_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kBlock) void k_copy_small(CopySmallArgs a) { copy_small_body(a); }
+
+}  // namespace st

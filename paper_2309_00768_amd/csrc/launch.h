@@ -1,0 +1,162 @@
+// Launch sink of libst.  Every kernel launch of the preconditioner and of
+// FGMRES goes through emit(): it either launches the kernel on a stream
+// (immediate mode) or appends the launch -- kernel kind, grid and argument
+// block -- to a program (record mode).  A batch of systems replays the
+// programs of all its systems in lockstep: launch t of a batched phase runs
+// op t of every member system in one heterogeneous kernel, k_multi, whose
+// workgroups find their system and kernel body from a small descriptor
+// passed as kernel arguments.  Launches per phase then follow the longest
+// member program instead of the sum over members.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "kernels.h"
+#include "kernels_vec.h"
+
+namespace st {
+
+// Kernel bodies a batched launch can run.  Ids of precision-dependent bodies
+// refer to the preconditioner precision T of the k_multi<T> instance.
+enum Kind : int {
+  kKSpmvJ = 0,      // SpmvArgs<double, double>, FP64 (J apply)
+  kKSpmvT,          // SpmvArgs<T, T> (every P_T product, all roles)
+  kKCheb,           // ChebArgs<T>
+  kKStInit,         // StInitArgs<T>
+  kKStCheb,         // StChebArgs<T>
+  kKCoarse,         // CoarseArgs<T>
+  kKSlabSumsD,      // SlabSumsDArgs
+  kKSlabSumsT,      // SlabSumsTArgs<T>
+  kKSplit,          // SplitArgs<T>
+  kKJoin,           // JoinArgs<T>
+  kKSlabShiftD,     // SlabShiftArgs<double>
+  kKSlabShiftT,     // SlabShiftArgs<T>
+  kKProjectP,       // ProjectPArgs
+  kKMdot,           // MdotArgs
+  kKReduce,         // ReduceArgs
+  kKCombine,        // CombineArgs
+  kKScale,          // ScaleArgs
+  kKGivens,         // GivensArgs
+  kKTrisolve,       // TrisolveArgs
+  kKInitG,          // InitGArgs
+  kKFill,           // FillArgs
+  kKCopySmall,      // CopySmallArgs
+  kKNumKinds
+};
+
+constexpr int kOpArgBytes = 448;
+
+// One recorded launch.
+struct Op {
+  int kind = 0;
+  int gx = 1, gy = 1;
+  int size = 0;
+  alignas(16) unsigned char args[kOpArgBytes];
+};
+
+struct Ctx {
+  hipStream_t s = nullptr;
+  std::vector<Op>* rec = nullptr;   // record mode when set
+  bool recording() const { return rec != nullptr; }
+};
+
+template <class A>
+inline void emit(Ctx& c, int kind, dim3 grid, void (*kern)(A), const A& a) {
+  static_assert(sizeof(A) <= kOpArgBytes, "kernel arguments exceed an op record");
+  if (c.rec) {
+    Op op;
+    op.kind = kind;
+    op.gx = int(grid.x);
+    op.gy = int(grid.y);
+    op.size = int(sizeof(A));
+    std::memset(op.args, 0, sizeof(op.args));
+    std::memcpy(op.args, &a, sizeof(A));
+    c.rec->push_back(op);
+    return;
+  }
+  void* params[] = {const_cast<A*>(&a)};
+  (void)hipLaunchKernel(reinterpret_cast<const void*>(kern), grid, dim3(kBlock), params, 0, c.s);
+}
+
+// ----------------------------------------------------- batched launches ---
+constexpr int kMaxMembers = 32;
+
+struct Member {
+  const unsigned char* args;   // device copy of the op's argument block
+  int kind;
+  int blocks;                  // gx * gy
+  int gx;
+  int pad;
+};
+
+struct MultiArgs {
+  int nmem;
+  int pad;
+  Member m[kMaxMembers];
+};
+
+template <class T, class A>
+__device__ inline A load_args(const unsigned char* p) {
+  return *reinterpret_cast<const A* __restrict__>(p);
+}
+
+// Workgroup b of the launch belongs to member i with prefix(i) <= b <
+// prefix(i+1); it runs that member's body with its own workgroup coordinates.
+template <class T>
+__global__ ST_LATENCY_KERNEL void k_multi(MultiArgs a) {
+  int rem = blockIdx.x, sel = 0;
+  bool found = false;
+#pragma unroll
+  for (int i = 0; i < kMaxMembers; ++i) {
+    if (!found && i < a.nmem) {
+      if (rem < a.m[i].blocks) {
+        sel = i;
+        found = true;
+      } else {
+        rem -= a.m[i].blocks;
+      }
+    }
+  }
+  if (!found) return;
+  int kind = 0, gx = 1;
+  const unsigned char* p = nullptr;
+#pragma unroll
+  for (int i = 0; i < kMaxMembers; ++i)
+    if (i == sel) {
+      kind = a.m[i].kind;
+      gx = a.m[i].gx;
+      p = a.m[i].args;
+    }
+  const int bx = rem % gx, by = rem / gx;
+  switch (kind) {
+    case kKSpmvJ: spmv_body<double, double, double>(load_args<T, SpmvArgs<double, double>>(p), bx, by); break;
+    case kKSpmvT: spmv_body<T, T, T>(load_args<T, SpmvArgs<T, T>>(p), bx, by); break;
+    case kKCheb: cheb_body<T>(load_args<T, ChebArgs<T>>(p), bx, by); break;
+    case kKStInit: st_init_body<T>(load_args<T, StInitArgs<T>>(p), bx); break;
+    case kKStCheb: st_cheb_body<T>(load_args<T, StChebArgs<T>>(p), bx); break;
+    case kKCoarse: coarse_body<T>(load_args<T, CoarseArgs<T>>(p), bx); break;
+    case kKSlabSumsD: slab_sums_d_body(load_args<T, SlabSumsDArgs>(p), bx); break;
+    case kKSlabSumsT: slab_sums_t_body<T>(load_args<T, SlabSumsTArgs<T>>(p), bx); break;
+    case kKSplit: split_body<T>(load_args<T, SplitArgs<T>>(p), bx, gx); break;
+    case kKJoin: join_body<T>(load_args<T, JoinArgs<T>>(p), bx, gx); break;
+    case kKSlabShiftD: slab_shift_body<double>(load_args<T, SlabShiftArgs<double>>(p), bx, gx); break;
+    case kKSlabShiftT: slab_shift_body<T>(load_args<T, SlabShiftArgs<T>>(p), bx, gx); break;
+    case kKProjectP: project_p_body(load_args<T, ProjectPArgs>(p), bx, gx); break;
+    case kKMdot: mdot_body(load_args<T, MdotArgs>(p), bx, by, gx); break;
+    case kKReduce: reduce_body(load_args<T, ReduceArgs>(p), bx); break;
+    case kKCombine: combine_body(load_args<T, CombineArgs>(p), bx, gx); break;
+    case kKScale: scale_body(load_args<T, ScaleArgs>(p), bx, gx); break;
+    case kKGivens: givens_body(load_args<T, GivensArgs>(p)); break;
+    case kKTrisolve: trisolve_body(load_args<T, TrisolveArgs>(p)); break;
+    case kKInitG: init_g_body(load_args<T, InitGArgs>(p)); break;
+    case kKFill: fill_body(load_args<T, FillArgs>(p), bx, gx); break;
+    case kKCopySmall: copy_small_body(load_args<T, CopySmallArgs>(p)); break;
+    default: break;
+  }
+}
+
+}  // namespace st

@@ -3,6 +3,7 @@
 // the pieces of P_T (eq. (PT)) and the AMG hierarchies, and packs everything
 // into a device image that st_create() uploads in one copy.
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <new>
@@ -83,6 +84,37 @@ Span put_diag_inv(Image& img, const Csr& a, int fp32) {
 
 }  // namespace
 
+// sum_t coef_t * m_t(value set set_t(k)) for every output set k on the union
+// pattern; set_t(k) < 0 leaves term t out of set k.
+struct SetTerm {
+  const Csr* m;
+  double coef;
+  std::function<int(int)> set;
+};
+
+static Csr combine_sets(int nsets, const std::vector<SetTerm>& terms) {
+  const int nr = terms[0].m->nr, nc = terms[0].m->nc;
+  PatternBuilder pb(nr, nc);
+  for (const SetTerm& t : terms)
+    for (int r = 0; r < nr; ++r)
+      for (int p = t.m->rp[r]; p < t.m->rp[r + 1]; ++p) pb.add(r, t.m->ci[p]);
+  Csr out = pb.finish();
+  const int64_t z = out.nnz();
+  out.v.assign(size_t(nsets) * size_t(z), 0.0);
+  for (const SetTerm& t : terms) {
+    const int64_t tz = t.m->nnz();
+    parallel_for(nsets, host_threads(), [&](int k) {
+      const int s = t.set(k);
+      if (s < 0) return;
+      const double* src = t.m->v.data() + size_t(s) * size_t(tz);
+      double* dst = out.v.data() + size_t(k) * size_t(z);
+      for (int r = 0; r < nr; ++r)
+        for (int p = t.m->rp[r]; p < t.m->rp[r + 1]; ++p) dst[out.find(r, t.m->ci[p])] += t.coef * src[p];
+    });
+  }
+  return out;
+}
+
 WsLayout workspace_layout(const Plan& P) {
   WsLayout L;
   const Dims& d = P.blk.d;
@@ -124,6 +156,7 @@ WsLayout workspace_layout(const Plan& P) {
   L.chr = take(ts * mm);
   L.chd0 = take(ts * mm);
   L.chd1 = take(ts * mm);
+  L.jsel = take(sizeof(int));
   for (const AmgLevel& lv : P.amgKp.lev)
     for (int i = 0; i < 6; ++i) L.kp_lev.push_back(take(ts * nt * lv.nrows));
   for (const AmgLevel& lv : P.amgFu.lev)
@@ -243,37 +276,70 @@ static int build_plan(Plan& P, std::string& err) {
   estimate_interval(img, b.C0, nt, P.amgC0);
   {
     const double red_fu = pr.inner_reduction > 0 ? pr.inner_reduction : 0.1;
-    const double red_ca = pr.ca_reduction > 0 ? pr.ca_reduction : std::min(0.05, 0.25 / nt);
+    const double red_ca = pr.ca_reduction > 0 ? pr.ca_reduction : 0.05;
+    // The degree meets the reduction target on the estimated interval (the
+    // sweeps solve for increments, so the error of a step is not amplified by
+    // the recursion in time).  Beyond kMaxAlone steps one V-cycle is cheaper
+    // per slab.
+    constexpr int kMaxAlone = 48;
     auto pick = [&](int opt, const Amg& a, double red) -> int {
       if (P.exact || opt < 0) return 0;
       if (opt > 0) return opt;
-      if (a.kappa > 60.0) return 0;
       const double sk = std::sqrt(a.kappa), r = (sk - 1.0) / (sk + 1.0);
-      int deg = int(std::ceil(std::log(red / 2.0) / std::log(r)));
-      return std::max(2, std::min(16, deg));
+      const int deg = int(std::ceil(std::log(red / 2.0) / std::log(r)));
+      return deg > kMaxAlone ? 0 : std::max(2, deg);
     };
     P.fu_deg = pick(pr.fu_solver, P.amgFu, red_fu);
     P.ca_deg = pick(pr.ca_solver, P.amgC0, red_ca);
   }
   // Stencil forms of the sweep operators (structured grids, 5x5 neighbourhoods).
   P.use_stencil = (P.fu_deg > 0 || P.ca_deg > 0) && pr.sweep_format == 0 ? 1 : 0;
+  // Each sweep step solves for the increment over a predictor from the earlier
+  // slabs (the previous slab for F_u, linear extrapolation for the second-order
+  // C_A recursion), so the couplings enter combined with the diagonal block:
+  //   F_u:  r0 = q^k - A_k x^{k-1},  A_k = F_u,k - M_u/dt,  x^k = x^{k-1} + F_u,k^{-1} r0;
+  //   C_A:  r0 = s^k + P_k y^{k-1} + Q_k y^{k-2},  y^k = (2 y^{k-1} - y^{k-2}) + C0_k^{-1} r0,
+  //         P_k = C1_{k-1}/dt - 2 C0_k,  Q_k = C0_k - C2/dt^2  (k >= 2),
+  //         P_1 = C1_0/dt - C0_1,  Q_1 = 0  (predictor y^0).
+  // With exact spatial solves this is the same forward substitution; with
+  // approximate ones the error is that of the increment, propagated by the
+  // exact (contracting) recursion.  The combinations are formed here in FP64.
   if (P.use_stencil) {
     const int gu = 2 * n - 1, ga = n - 1;
+    const double dt = b.dt;
+    auto same = [](int k) { return k; };
     bool ok = pack_stencil(img, b.Fu, nt, gu, gu, 2, false, fp, P.sFu);
-    Csr Mud = b.Mu;
-    for (auto& v : Mud.v) v /= b.dt;
-    ok = ok && pack_stencil(img, Mud, 1, gu, gu, 2, true, fp, P.sMu);
+    {
+      Csr Au = combine_sets(nt, {{&b.Fu, 1.0, same}, {&b.Mu, -1.0 / dt, [](int) { return 0; }}});
+      ok = ok && pack_stencil(img, Au, nt, gu, gu, 2, false, fp, P.sAu);
+    }
     ok = ok && pack_stencil(img, b.C0, nt, ga, ga, 1, false, fp, P.sC0);
-    ok = ok && pack_stencil(img, b.C1, std::max(nt - 1, 1), ga, ga, 1, false, fp, P.sC1);
-    ok = ok && pack_stencil(img, b.C2, 1, ga, ga, 1, false, fp, P.sC2);
+    {
+      Csr CP = combine_sets(nt, {{&b.C1, 1.0 / dt, [](int k) { return k >= 1 ? k - 1 : -1; }},
+                                 {&b.C0, -1.0, [](int k) { return k >= 1 ? k : -1; }},
+                                 {&b.C0, -1.0, [](int k) { return k >= 2 ? k : -1; }}});
+      Csr CQ = combine_sets(nt, {{&b.C0, 1.0, [](int k) { return k >= 2 ? k : -1; }},
+                                 {&b.C2, -1.0 / (dt * dt), [](int k) { return k >= 2 ? 0 : -1; }}});
+      ok = ok && pack_stencil(img, CP, nt, ga, ga, 1, false, fp, P.sCP);
+      ok = ok && pack_stencil(img, CQ, nt, ga, ga, 1, false, fp, P.sCQ);
+    }
     ok = ok && pack_stencil(img, b.Mj, 1, n + 1, n + 1, 1, false, fp, P.sMj, 1);
     ok = ok && pack_stencil(img, b.KjA, 1, n + 1, n + 1, 1, false, fp, P.sKjA, 1, n - 1, n - 1, 1);
     if (pr.adjoint) {
+      // Backward sweeps of the transposes: predictors x^{k+1} and 2 c^{k+1} - c^{k+2}.
       Csr FuT = csr_transpose(b.Fu), C0T = csr_transpose(b.C0), C1T = csr_transpose(b.C1), C2T = csr_transpose(b.C2);
       ok = ok && pack_stencil(img, FuT, nt, gu, gu, 2, false, fp, P.sFuT);
+      Csr AuT = combine_sets(nt, {{&FuT, 1.0, same}, {&b.Mu, -1.0 / dt, [](int) { return 0; }}});
+      ok = ok && pack_stencil(img, AuT, nt, gu, gu, 2, false, fp, P.sAuT);
       ok = ok && pack_stencil(img, C0T, nt, ga, ga, 1, false, fp, P.sC0T);
-      ok = ok && pack_stencil(img, C1T, std::max(nt - 1, 1), ga, ga, 1, false, fp, P.sC1T);
-      ok = ok && pack_stencil(img, C2T, 1, ga, ga, 1, false, fp, P.sC2T);
+      const int last = nt - 1;
+      Csr CPT = combine_sets(nt, {{&C1T, 1.0 / dt, [last](int k) { return k <= last - 1 ? k : -1; }},
+                                  {&C0T, -1.0, [last](int k) { return k <= last - 1 ? k : -1; }},
+                                  {&C0T, -1.0, [last](int k) { return k <= last - 2 ? k : -1; }}});
+      Csr CQT = combine_sets(nt, {{&C0T, 1.0, [last](int k) { return k <= last - 2 ? k : -1; }},
+                                  {&C2T, -1.0 / (dt * dt), [last](int k) { return k <= last - 2 ? 0 : -1; }}});
+      ok = ok && pack_stencil(img, CPT, nt, ga, ga, 1, false, fp, P.sCPT);
+      ok = ok && pack_stencil(img, CQT, nt, ga, ga, 1, false, fp, P.sCQT);
     }
     if (!ok) {
       err = "sweep operator does not fit a 5x5 stencil";

@@ -12,10 +12,14 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.h"
+#include "kernels_vec.h"
+#include "launch.h"
 #include "st_internal.h"
 
 struct st_plan {
@@ -64,7 +68,7 @@ struct Handle {
   const double* mp_rowsum = nullptr;
   double msum = 1.0;              // 1^T M_p 1 (the area)
   DAmg amgFu, amgC0, amgKp, amgFuT, amgC0T;
-  StencilOp sFu, sMu, sC0, sC1, sC2, sFuT, sC0T, sC1T, sC2T;   // offsets into the image
+  StencilOp sFu, sAu, sC0, sCP, sCQ, sFuT, sAuT, sC0T, sCPT, sCQT;   // offsets into the image
   StencilOp sMj, sKjA;
   int use_chain = 0;               // C_A sweep + M_j solves in single-workgroup chunk kernels
   double* host_small = nullptr;   // pinned
@@ -139,6 +143,7 @@ DAmg mirror_amg(char* base, const Amg& a, const std::vector<size_t>& bufs) {
   return d;
 }
 
+
 // ---------------------------------------------------------- launchers ---
 template <class T>
 Seg<T> seg(const DGroup& g, int s, int set_base, int set_step, const void* x, int64_t xstride, int xshift,
@@ -167,9 +172,10 @@ struct Epilogue {
 };
 
 template <class T, class TX>
-void spmv(hipStream_t s, const DGroup& g, int nvec, int nseg, const Seg<T>* segs, const TX* b, int64_t bstride,
+void spmv(Ctx& c, const DGroup& g, int nvec, int nseg, const Seg<T>* segs, const TX* b, int64_t bstride,
           double beta, TX* y, int64_t ystride, int role = kRoleSlab, const Epilogue* ep = nullptr) {
   SpmvArgs<T, TX> a;
+  std::memset(&a, 0, sizeof(a));
   a.perm = g.perm;
   a.nslices = g.nslices;
   a.lanes = g.lanes;
@@ -193,28 +199,33 @@ void spmv(hipStream_t s, const DGroup& g, int nvec, int nseg, const Seg<T>* segs
     a.x = static_cast<TX*>(ep->x);
   }
   dim3 grid((g.nslices + 3) / 4, nvec);
-  using TA = T;
+  // In a batched launch the FP64 J apply has its own body; every other product
+  // runs in the preconditioner precision of the batch.
+  static_assert(std::is_same<T, TX>::value, "products take and give vectors of their own precision");
   switch (role) {
-    case kRoleJ: hipLaunchKernelGGL((k_spmv<T, TX, TA, kRoleJ>), grid, dim3(kBlock), 0, s, a); break;
-    case kRoleSweep: hipLaunchKernelGGL((k_spmv<T, TX, TA, kRoleSweep>), grid, dim3(kBlock), 0, s, a); break;
-    case kRoleAmg: hipLaunchKernelGGL((k_spmv<T, TX, TA, kRoleAmg>), grid, dim3(kBlock), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_spmv<T, TX, TA, kRoleSlab>), grid, dim3(kBlock), 0, s, a); break;
+    case kRoleJ:
+      emit(c, std::is_same<T, double>::value ? kKSpmvJ : kKSpmvT, grid, &k_spmv<T, TX, T, kRoleJ>, a);
+      break;
+    case kRoleSweep: emit(c, kKSpmvT, grid, &k_spmv<T, TX, T, kRoleSweep>, a); break;
+    case kRoleAmg: emit(c, kKSpmvT, grid, &k_spmv<T, TX, T, kRoleAmg>, a); break;
+    default: emit(c, kKSpmvT, grid, &k_spmv<T, TX, T, kRoleSlab>, a); break;
   }
 }
 
 // y = alpha A x + beta b for a one-segment group, nvec vectors of length n.
 template <class T>
-void spmv1(hipStream_t s, const DGroup& g, int nvec, int set_base, int set_step, const T* x, int64_t xstride,
+void spmv1(Ctx& c, const DGroup& g, int nvec, int set_base, int set_step, const T* x, int64_t xstride,
            double alpha, const T* b, double beta, T* y, int64_t ystride, int role = kRoleSlab) {
   Seg<T> sg = seg<T>(g, 0, set_base, set_step, x, xstride, 0, 0, nvec, alpha);
-  spmv<T, T>(s, g, nvec, 1, &sg, b, ystride, beta, y, ystride, role);
+  spmv<T, T>(c, g, nvec, 1, &sg, b, ystride, beta, y, ystride, role);
 }
 
 template <class T>
-void cheb_launch(hipStream_t s, const DGroup& A, int nvec, int set_base, int set_step, const T* dinv,
-                 int64_t dstride, const double* cheb, double theta, double delta, const T* b, T* r, T* x,
-                 const T* dold, T* dnew, int64_t vec, int mode, int step, int x_add, int role) {
+void cheb_launch(Ctx& c, const DGroup& A, int nvec, int set_base, int set_step, const T* dinv, int64_t dstride,
+                 const double* cheb, double theta, double delta, const T* b, T* r, T* x, const T* dold, T* dnew,
+                 int64_t vec, int mode, int step, int x_add, int role) {
   ChebArgs<T> a;
+  std::memset(&a, 0, sizeof(a));
   a.perm = A.perm;
   a.nslices = A.nslices;
   a.lanes = A.lanes;
@@ -239,25 +250,25 @@ void cheb_launch(hipStream_t s, const DGroup& A, int nvec, int set_base, int set
   a.step = step;
   a.x_add = x_add;
   dim3 grid((A.nslices + 3) / 4, nvec);
-  if (role == 1) hipLaunchKernelGGL((k_cheb<T, 1>), grid, dim3(kBlock), 0, s, a);
-  else if (role == 2) hipLaunchKernelGGL((k_cheb<T, 2>), grid, dim3(kBlock), 0, s, a);
-  else hipLaunchKernelGGL((k_cheb<T, 0>), grid, dim3(kBlock), 0, s, a);
+  if (role == 1) emit(c, kKCheb, grid, &k_cheb<T, 1>, a);
+  else if (role == 2) emit(c, kKCheb, grid, &k_cheb<T, 2>, a);
+  else emit(c, kKCheb, grid, &k_cheb<T, 0>, a);
 }
 
 // Chebyshev-Jacobi polynomial solve of A x = b with `steps` steps from x = 0
 // (or x += correction when x_add), using caller scratch r, d0, d1.
 template <class T>
-void cheb_solve(hipStream_t s, const DGroup& A, int nvec, int set_base, int set_step, const T* dinv,
-                int64_t dstride, const double* cheb, double theta, double delta, const T* b, T* x, T* r, T* d0,
-                T* d1, int64_t vec, int steps, int x_add, bool final_residual, int role = 0) {
-  cheb_launch<T>(s, A, nvec, set_base, set_step, dinv, dstride, cheb, theta, delta, b, r, x, nullptr, d0, vec, 0, 0,
+void cheb_solve(Ctx& c, const DGroup& A, int nvec, int set_base, int set_step, const T* dinv, int64_t dstride,
+                const double* cheb, double theta, double delta, const T* b, T* x, T* r, T* d0, T* d1, int64_t vec,
+                int steps, int x_add, bool final_residual, int role = 0) {
+  cheb_launch<T>(c, A, nvec, set_base, set_step, dinv, dstride, cheb, theta, delta, b, r, x, nullptr, d0, vec, 0, 0,
                  x_add, role);
   T* d[2] = {d0, d1};
   for (int i = 1; i < steps; ++i)
-    cheb_launch<T>(s, A, nvec, set_base, set_step, dinv, dstride, cheb, theta, delta, nullptr, r, x, d[(i - 1) % 2],
+    cheb_launch<T>(c, A, nvec, set_base, set_step, dinv, dstride, cheb, theta, delta, nullptr, r, x, d[(i - 1) % 2],
                    d[i % 2], vec, 1, i, 1, role);
   if (final_residual)
-    cheb_launch<T>(s, A, nvec, set_base, set_step, dinv, dstride, cheb, theta, delta, nullptr, r, x,
+    cheb_launch<T>(c, A, nvec, set_base, set_step, dinv, dstride, cheb, theta, delta, nullptr, r, x,
                    d[(steps - 1) % 2], d[steps % 2], vec, 2, 0, 1, role);
 }
 
@@ -265,7 +276,7 @@ void cheb_solve(hipStream_t s, const DGroup& A, int nvec, int set_base, int set_
 // One V(1,1) cycle on level l for nvec vectors (value set set_base + v*set_step).
 // Level-0 vectors may be supplied by the caller (x0, b0); x_add: x holds a guess.
 template <class T>
-void vcycle(hipStream_t s, DAmg& a, int l, int nvec, int set_base, int set_step, T* x0, const T* b0, int x_add,
+void vcycle(Ctx& c, DAmg& a, int l, int nvec, int set_base, int set_step, T* x0, const T* b0, int x_add,
             bool need_residual) {
   DLevel& L = a.lev[l];
   const int64_t vec = L.n;   // vectors of one level are stored back to back
@@ -280,24 +291,33 @@ void vcycle(hipStream_t s, DAmg& a, int l, int nvec, int set_base, int set_step,
   if (coarsest) {
     const T* rhs = b;
     if (x_add) {   // x += Ainv (b - A x)
-      spmv1<T>(s, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec, kRoleAmg);
+      spmv1<T>(c, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec, kRoleAmg);
       rhs = r;
     }
-    const int64_t istride = a.nsets > 1 ? int64_t(a.ncoarse) * a.ncoarse : 0;
-    hipLaunchKernelGGL((k_coarse<T>), dim3(nvec), dim3(kBlock), 0, s, a.ncoarse, static_cast<const T*>(a.cinv),
-                       istride, set_base, set_step, rhs, x, vec, x_add);
-    if (need_residual) spmv1<T>(s, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec, kRoleAmg);
+    CoarseArgs<T> ca;
+    std::memset(&ca, 0, sizeof(ca));
+    ca.n = a.ncoarse;
+    ca.inv = static_cast<const T*>(a.cinv);
+    ca.istride = a.nsets > 1 ? int64_t(a.ncoarse) * a.ncoarse : 0;
+    ca.set_base = set_base;
+    ca.set_step = set_step;
+    ca.b = rhs;
+    ca.x = x;
+    ca.vec = vec;
+    ca.accumulate = x_add;
+    emit(c, kKCoarse, dim3(nvec), &k_coarse<T>, ca);
+    if (need_residual) spmv1<T>(c, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec, kRoleAmg);
     return;
   }
   const int deg = a.deg;
   const int crole = l == 0 ? 1 : 2;
   // pre-smoothing (leaves r = b - A x)
   if (x_add) {
-    spmv1<T>(s, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec, kRoleAmg);
-    cheb_solve<T>(s, L.A, nvec, set_base, set_step, dinv, dstride, L.cheb, 0, 0, nullptr, x, r, d0, d1, vec, deg, 1,
+    spmv1<T>(c, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec, kRoleAmg);
+    cheb_solve<T>(c, L.A, nvec, set_base, set_step, dinv, dstride, L.cheb, 0, 0, nullptr, x, r, d0, d1, vec, deg, 1,
                   true, crole);
   } else {
-    cheb_solve<T>(s, L.A, nvec, set_base, set_step, dinv, dstride, L.cheb, 0, 0, b, x, r, d0, d1, vec, deg, 0, true,
+    cheb_solve<T>(c, L.A, nvec, set_base, set_step, dinv, dstride, L.cheb, 0, 0, b, x, r, d0, d1, vec, deg, 0, true,
                   crole);
   }
   // coarse-grid correction
@@ -305,197 +325,46 @@ void vcycle(hipStream_t s, DAmg& a, int l, int nvec, int set_base, int set_step,
   const int64_t cvec = C.n;
   T* cb = static_cast<T*>(a.buf[6 * (l + 1) + 1]);
   T* cx = static_cast<T*>(a.buf[6 * (l + 1) + 0]);
-  spmv1<T>(s, L.R, nvec, 0, 0, r, vec, 1.0, nullptr, 0.0, cb, cvec, kRoleAmg);
-  vcycle<T>(s, a, l + 1, nvec, set_base, set_step, nullptr, nullptr, 0, false);
-  spmv1<T>(s, L.P, nvec, 0, 0, cx, cvec, 1.0, x, 1.0, x, vec, kRoleAmg);   // x += P x_c
+  spmv1<T>(c, L.R, nvec, 0, 0, r, vec, 1.0, nullptr, 0.0, cb, cvec, kRoleAmg);
+  vcycle<T>(c, a, l + 1, nvec, set_base, set_step, nullptr, nullptr, 0, false);
+  spmv1<T>(c, L.P, nvec, 0, 0, cx, cvec, 1.0, x, 1.0, x, vec, kRoleAmg);   // x += P x_c
   // post-smoothing
-  spmv1<T>(s, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec, kRoleAmg);
-  cheb_solve<T>(s, L.A, nvec, set_base, set_step, dinv, dstride, L.cheb, 0, 0, nullptr, x, r, d0, d1, vec, deg, 1,
+  spmv1<T>(c, L.A, nvec, set_base, set_step, x, vec, -1.0, b, 1.0, r, vec, kRoleAmg);
+  cheb_solve<T>(c, L.A, nvec, set_base, set_step, dinv, dstride, L.cheb, 0, 0, nullptr, x, r, d0, d1, vec, deg, 1,
                 need_residual, crole);
 }
 
 // Spatial solve A x = b with `iters` V-cycles (x starts from zero).
 template <class T>
-void amg_solve(hipStream_t s, DAmg& a, int nvec, int set_base, int set_step, T* x, const T* b, int iters) {
-  for (int it = 0; it < iters; ++it) vcycle<T>(s, a, 0, nvec, set_base, set_step, x, b, it > 0 ? 1 : 0, false);
+void amg_solve(Ctx& c, DAmg& a, int nvec, int set_base, int set_step, T* x, const T* b, int iters) {
+  for (int it = 0; it < iters; ++it) vcycle<T>(c, a, 0, nvec, set_base, set_step, x, b, it > 0 ? 1 : 0, false);
 }
 
-// ------------------------------------------------- vector kernels (P_T) ---
-// Per-slab sums of src[k*ld + off + i], i < len (weights w[i] if w): out[k].
-__global__ __launch_bounds__(kBlock) void k_slab_sums_d(const double* src, int64_t ld, int off, int len,
-                                                        const double* w, double* out) {
-  const int k = blockIdx.x;
-  const double* p = src + int64_t(k) * ld + off;
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < len; i += blockDim.x) acc += (w ? w[i] : 1.0) * p[i];
-  acc = block_sum(acc);
-  if (threadIdx.x == 0) out[k] = acc;
-}
-
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_slab_sums_t(const T* src, int64_t ld, int len, const double* w,
-                                                        double* out) {
-  const int k = blockIdx.x;
-  const T* p = src + int64_t(k) * ld;
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < len; i += blockDim.x) acc += (w ? w[i] : 1.0) * double(p[i]);
-  acc = block_sum(acc);
-  if (threadIdx.x == 0) out[k] = acc;
-}
-
-// Split an FP64 slab-major vector into per-block arrays (precision T); the
-// pressure rows lose their per-slab mean psum[k] / np.
-template <class T>
-__global__ void k_split(const double* r, int ns, int nt, int o2, int o3, int o4, const double* psum, T* ru,
-                        T* rp, T* rj, T* ra) {
-  const int64_t N = int64_t(ns) * nt;
-  const int np = o3 - o2, nj = o4 - o3, na = ns - o4;
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
-    const int k = int(i / ns), c = int(i % ns);
-    const double v = r[i];
-    if (c < o2) ru[int64_t(k) * o2 + c] = T(v);
-    else if (c < o3) rp[int64_t(k) * np + (c - o2)] = T(v - psum[k] / np);
-    else if (c < o4) rj[int64_t(k) * nj + (c - o3)] = T(v);
-    else ra[int64_t(k) * na + (c - o4)] = T(v);
-  }
-}
-
-// Join per-block arrays into an FP64 slab-major vector; pressure is
-// sign * xp shifted so that 1^T M_p p^k = 0 (wsum[k] = m . xp^k, msum = sum m).
-template <class T>
-__global__ void k_join(double* z, int ns, int nt, int o2, int o3, int o4, const T* xu, const T* xp, double psign,
-                       const double* wsum, double msum, const T* yj, const T* ya) {
-  const int64_t N = int64_t(ns) * nt;
-  const int np = o3 - o2, nj = o4 - o3, na = ns - o4;
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
-    const int k = int(i / ns), c = int(i % ns);
-    double v;
-    if (c < o2) v = double(xu[int64_t(k) * o2 + c]);
-    else if (c < o3) v = psign * (double(xp[int64_t(k) * np + (c - o2)]) - wsum[k] / msum);
-    else if (c < o4) v = double(yj[int64_t(k) * nj + (c - o3)]);
-    else v = double(ya[int64_t(k) * na + (c - o4)]);
-    z[i] = v;
-  }
-}
-
-// x[k*ld + i] -= sums[k] * scale (i < len)
-template <class T>
-__global__ void k_slab_shift(T* x, int64_t ld, int len, int nt, const double* sums, double scale) {
-  const int64_t N = int64_t(len) * nt;
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
-    const int k = int(i / len), c = int(i % len);
-    x[int64_t(k) * ld + c] = T(double(x[int64_t(k) * ld + c]) - sums[k] * scale);
-  }
-}
-
-// FP64 slab-major: p rows (offset o2..o3) minus psum[k]/np, written to dst.
-__global__ void k_project_p(const double* src, double* dst, int ns, int nt, int o2, int o3, const double* psum) {
-  const int64_t N = int64_t(ns) * nt;
-  const int np = o3 - o2;
-  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
-    const int k = int(i / ns), c = int(i % ns);
-    double v = src[i];
-    if (c >= o2 && c < o3) v -= psum[k] / np;
-    dst[i] = v;
-  }
-}
-
-// ------------------------------------------------------ FGMRES kernels ---
-// partial[i * nb + blk] = sum over the block's rows of V_i . w   (i = blockIdx.y)
-__global__ __launch_bounds__(kBlock) void k_mdot_partial(const double* V, int64_t N, const double* w,
-                                                         double* partial) {
-  const int i = blockIdx.y;
-  const double* v = V + int64_t(i) * N;
-  double acc = 0.0;
-  for (int64_t r = blockIdx.x * int64_t(kBlock) + threadIdx.x; r < N; r += int64_t(gridDim.x) * kBlock)
-    acc += v[r] * w[r];
-  acc = block_sum(acc);
-  if (threadIdx.x == 0) partial[int64_t(i) * gridDim.x + blockIdx.x] = acc;
-}
-
-// out[i] (+)= sum_b partial[i * nb + b]; mode 1: out[0] = sqrt(sum), mode 2: add.
-__global__ __launch_bounds__(kBlock) void k_reduce(const double* partial, int nb, double* out, int mode,
-                                                   double* copy_to) {
-  const int i = blockIdx.x;
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kBlock) acc += partial[int64_t(i) * nb + b];
-  acc = block_sum(acc);
-  if (threadIdx.x == 0) {
-    if (mode == 1) acc = std::sqrt(acc);
-    if (mode == 2) out[i] += acc;
-    else out[i] = acc;
-    if (copy_to) copy_to[i] = out[i];
-  }
-}
-
-// w -= sum_{i < nv} h[i] V_i
-__global__ __launch_bounds__(kBlock) void k_mgs_update(double* w, const double* V, int64_t N, const double* h,
-                                                       int nv) {
-  for (int64_t r = blockIdx.x * int64_t(kBlock) + threadIdx.x; r < N; r += int64_t(gridDim.x) * kBlock) {
-    double acc = w[r];
-    for (int i = 0; i < nv; ++i) acc -= h[i] * V[int64_t(i) * N + r];
-    w[r] = acc;
-  }
-}
-
-// x += sum_i y[i] Z_i
-__global__ __launch_bounds__(kBlock) void k_update_x(double* x, const double* Z, int64_t N, const double* y, int nv) {
-  for (int64_t r = blockIdx.x * int64_t(kBlock) + threadIdx.x; r < N; r += int64_t(gridDim.x) * kBlock) {
-    double acc = x[r];
-    for (int i = 0; i < nv; ++i) acc += y[i] * Z[int64_t(i) * N + r];
-    x[r] = acc;
-  }
-}
-
-// dst = src / *nrm (zero if the norm is zero)
-__global__ __launch_bounds__(kBlock) void k_scale(double* dst, const double* src, int64_t N, const double* nrm) {
-  const double s = *nrm;
-  const double f = s != 0.0 ? 1.0 / s : 0.0;
-  for (int64_t r = blockIdx.x * int64_t(kBlock) + threadIdx.x; r < N; r += int64_t(gridDim.x) * kBlock)
-    dst[r] = src[r] * f;
-}
-
-// Givens update of Hessenberg column j; g, cs, sn in `sm`; est = |g[j+1]|.
-// Layout of sm: g[0..m], cs[m+1..], sn[...]
-__global__ void k_givens(double* Hcol, int j, int ldh, double* g, double* cs, double* sn, double* est) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double* h = Hcol + int64_t(j) * ldh;
-  for (int i = 0; i < j; ++i) {
-    const double t = cs[i] * h[i] + sn[i] * h[i + 1];
-    h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
-    h[i] = t;
-  }
-  const double a = h[j], b = h[j + 1];
-  const double d = std::hypot(a, b);
-  const double c = d != 0.0 ? a / d : 1.0, s = d != 0.0 ? b / d : 0.0;
-  cs[j] = c;
-  sn[j] = s;
-  h[j] = d;
-  h[j + 1] = 0.0;
-  g[j + 1] = -s * g[j];
-  g[j] = c * g[j];
-  est[0] = std::fabs(g[j + 1]);
-}
-
-// Back substitution of the rotated upper-triangular m x m system H y = g.
-__global__ void k_trisolve(const double* Hcol, int m, int ldh, const double* g, double* y) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  for (int i = m - 1; i >= 0; --i) {
-    double acc = g[i];
-    for (int l = i + 1; l < m; ++l) acc -= Hcol[int64_t(l) * ldh + i] * y[l];
-    y[i] = acc / Hcol[int64_t(i) * ldh + i];
-  }
-}
-
-__global__ void k_init_g(double* g, int m1, const double* beta) {
-  for (int i = threadIdx.x; i < m1; i += blockDim.x) g[i] = i == 0 ? *beta : 0.0;
-}
-
+// ----------------------------------------------- vector launch helpers ---
 inline int grid_for(int64_t n) {
   int64_t b = (n + kBlock - 1) / kBlock;
   if (b > 8192) b = 8192;
   if (b < 1) b = 1;
   return int(b);
+}
+
+inline void slab_sums_d(Ctx& c, const double* src, int64_t ld, int off, int len, const double* w, double* out,
+                        int nt, const int* jsel = nullptr, int64_t jstride = 0) {
+  SlabSumsDArgs a{src, ld, off, len, w, out, jsel, jstride};
+  emit(c, kKSlabSumsD, dim3(nt), &k_slab_sums_d, a);
+}
+
+template <class T>
+inline void slab_sums_t(Ctx& c, const T* src, int64_t ld, int len, const double* w, double* out, int nt) {
+  SlabSumsTArgs<T> a{src, ld, len, w, out};
+  emit(c, kKSlabSumsT, dim3(nt), &k_slab_sums_t<T>, a);
+}
+
+template <class T>
+inline void slab_shift(Ctx& c, T* x, int64_t ld, int len, int nt, const double* sums, double scale) {
+  SlabShiftArgs<T> a{x, ld, len, nt, sums, scale};
+  const int kind = std::is_same<T, double>::value ? kKSlabShiftD : kKSlabShiftT;
+  emit(c, kind, dim3(grid_for(int64_t(len) * nt)), &k_slab_shift<T>, a);
 }
 
 // One sweep step: x = A_k^{-1} (q + coupling), the coupling given as segments
@@ -504,12 +373,12 @@ inline int grid_for(int64_t n) {
 // coupling product; otherwise the right-hand side is formed and `vc`
 // V-cycles of the hierarchy are applied.
 template <class T>
-void sweep_step(hipStream_t s, DAmg& a, const DGroup& cg, int nseg, const Seg<T>* segs, const T* q, T* x, int k,
-                int deg, int vc) {
+void sweep_step(Ctx& c, DAmg& a, const DGroup& cg, int nseg, const Seg<T>* segs, const T* q, T* x, int k, int deg,
+                int vc) {
   T* rhs = static_cast<T*>(a.buf[1]);
   if (deg <= 0) {
-    spmv<T, T>(s, cg, 1, nseg, segs, q, 0, 1.0, rhs, 0, kRoleSweep);
-    amg_solve<T>(s, a, 1, k, 0, x, rhs, vc);
+    spmv<T, T>(c, cg, 1, nseg, segs, q, 0, 1.0, rhs, 0, kRoleSweep);
+    amg_solve<T>(c, a, 1, k, 0, x, rhs, vc);
     return;
   }
   DLevel& L = a.lev[0];
@@ -525,10 +394,10 @@ void sweep_step(hipStream_t s, DAmg& a, const DGroup& cg, int nseg, const Seg<T>
   ep.r = r;
   ep.d = d0;
   ep.x = x;
-  spmv<T, T>(s, cg, 1, nseg, segs, q, 0, 1.0, rhs, 0, kRoleSweep, &ep);
+  spmv<T, T>(c, cg, 1, nseg, segs, q, 0, 1.0, rhs, 0, kRoleSweep, &ep);
   T* d[2] = {d0, d1};
   for (int i = 1; i < deg; ++i)
-    cheb_launch<T>(s, L.A, 1, a.nsets > 1 ? k : 0, 0, static_cast<const T*>(L.dinv), dstride, a.alone_dev, 0, 0,
+    cheb_launch<T>(c, L.A, 1, a.nsets > 1 ? k : 0, 0, static_cast<const T*>(L.dinv), dstride, a.alone_dev, 0, 0,
                    nullptr, r, x, d[(i - 1) % 2], d[i % 2], L.n, 1, i, 1, 1);
 }
 
@@ -549,12 +418,13 @@ StOp<T> st_op(char* base, const StencilOp& o) {
   return a;
 }
 
-// One sweep step with Chebyshev-Jacobi alone on stencil operators:
-// x = p(D^{-1} A_k) D^{-1} (q + a1 S1 y1 + a2 S2 y2), `deg` kernels.
+// One sweep step with Chebyshev-Jacobi alone on stencil operators, `deg`
+// kernels: x = x0 + p(D^{-1} A_k) D^{-1} r0 with r0 = q + a1 S1 y1 + a2 S2 y2
+// the residual of the predictor x0 = g1 y1 + g2 y2 (x0 = 0 when !guess).
 template <class T>
-void sweep_step_stencil(hipStream_t s, Handle& H, DAmg& a, const StencilOp& A, const StencilOp* S1, int set1,
-                        double a1, const T* y1, const StencilOp* S2, int set2, double a2, const T* y2, const T* q,
-                        T* x, int k, int deg, int role) {
+void sweep_step_stencil(Ctx& c, Handle& H, DAmg& a, const StencilOp& A, const StencilOp* S1, int set1, double a1,
+                        const T* y1, const StencilOp* S2, int set2, double a2, const T* y2, const T* q, T* x, int k,
+                        int deg, int role, bool guess = false, double g1 = 0.0, double g2 = 0.0) {
   DLevel& L = a.lev[0];
   const int64_t rows = A.rows;
   T* r = static_cast<T*>(a.buf[2]);
@@ -564,6 +434,7 @@ void sweep_step_stencil(hipStream_t s, Handle& H, DAmg& a, const StencilOp& A, c
   const int iset = a.nsets > 1 ? k : 0;
   const double theta = a.alone[2 * iset], delta = a.alone[2 * iset + 1];
   StInitArgs<T> ia;
+  std::memset(&ia, 0, sizeof(ia));
   ia.S1 = S1 ? st_op<T>(H.base, *S1) : StOp<T>{};
   ia.S2 = S2 ? st_op<T>(H.base, *S2) : StOp<T>{};
   ia.set1 = set1;
@@ -581,10 +452,14 @@ void sweep_step_stencil(hipStream_t s, Handle& H, DAmg& a, const StencilOp& A, c
   ia.d = d0;
   ia.x = x;
   ia.rows = rows;
+  ia.guess = guess ? 1 : 0;
+  ia.g1 = g1;
+  ia.g2 = g2;
   const dim3 grid(unsigned((rows + kBlock - 1) / kBlock));
-  if (role == 1) hipLaunchKernelGGL((k_st_init<T, 1>), grid, dim3(kBlock), 0, s, ia);
-  else hipLaunchKernelGGL((k_st_init<T, 2>), grid, dim3(kBlock), 0, s, ia);
+  if (role == 1) emit(c, kKStInit, grid, &k_st_init<T, 1>, ia);
+  else emit(c, kKStInit, grid, &k_st_init<T, 2>, ia);
   StChebArgs<T> ca;
+  std::memset(&ca, 0, sizeof(ca));
   ca.A = st_op<T>(H.base, A);
   ca.set = iset;
   ca.dinv = dinv;
@@ -601,14 +476,19 @@ void sweep_step_stencil(hipStream_t s, Handle& H, DAmg& a, const StencilOp& A, c
     ca.c2 = 2.0 * rho / delta;
     ca.dold = d[(i - 1) % 2];
     ca.dnew = d[i % 2];
-    if (role == 1) hipLaunchKernelGGL((k_st_cheb<T, 1>), grid, dim3(kBlock), 0, s, ca);
-    else hipLaunchKernelGGL((k_st_cheb<T, 2>), grid, dim3(kBlock), 0, s, ca);
+    if (role == 1) emit(c, kKStCheb, grid, &k_st_cheb<T, 1>, ca);
+    else emit(c, kKStCheb, grid, &k_st_cheb<T, 2>, ca);
   }
 }
 
 // ================================================= P_T^{-1} (forward) ===
+// z = P_T^{-1} r.  With jsel, r and z are the bases of the Krylov blocks V, Z
+// and the column is *jsel (read on the device; batched solves).  Recording
+// (batched) runs everything on one stream in slab order: one chunk, no chain
+// kernel, no second stream.
 template <class T>
-int precond_forward(Handle& H, const double* r, double* z, hipStream_t s) {
+int precond_forward(Handle& H, const double* r, double* z, Ctx& c, const int* jsel = nullptr,
+                    int64_t jstride = 0) {
   const Dims& d = H.d;
   const int nt = d.nt;
   char* B = H.base;
@@ -626,122 +506,130 @@ int precond_forward(Handle& H, const double* r, double* z, hipStream_t s) {
   const int mit = H.mass_iters;
   // Q1 mass: eigenvalues of D^{-1} M lie in [1/4, 9/4] on squares; widened slightly.
   const double mlo = 0.24, mhi = 2.3, mth = 0.5 * (mhi + mlo), mde = 0.5 * (mhi - mlo);
+  const bool rec = c.recording();
 
   // 0. split r, projecting the pressure rows to zero sum per slab
-  hipLaunchKernelGGL(k_slab_sums_d, dim3(nt), dim3(kBlock), 0, s, r, int64_t(ns), o2, np, nullptr, psum);
-  hipLaunchKernelGGL((k_split<T>), dim3(grid_for(int64_t(ns) * nt)), dim3(kBlock), 0, s, r, ns, nt, o2, o3, o4,
-                     psum, ru, rp, rj, ra);
+  slab_sums_d(c, r, int64_t(ns), o2, np, nullptr, psum, nt, jsel, jstride);
+  {
+    SplitArgs<T> a{r, ns, nt, o2, o3, o4, psum, ru, rp, rj, ra, jsel, jstride};
+    emit(c, kKSplit, dim3(grid_for(int64_t(ns) * nt)), &k_split<T>, a);
+  }
   // 1. magnetic Schur complement: w = M_A^{-1} r_A; s = F_A w (all slabs at once)
-  cheb_solve<T>(s, H.MA, nt, 0, 0, static_cast<const T*>(H.dMA), 0, nullptr, mth, mde, ra, w, mr, md0, md1, na, mit,
+  cheb_solve<T>(c, H.MA, nt, 0, 0, static_cast<const T*>(H.dMA), 0, nullptr, mth, mde, ra, w, mr, md0, md1, na, mit,
                 0, false);
   {
     Seg<T> sg[2] = {seg<T>(H.FA, 0, 0, 1, w, na, 0, 0, nt, 1.0), seg<T>(H.FA, 1, 0, 0, w, na, -1, 1, nt, 1.0)};
-    spmv<T, T>(s, H.FA, nt, 2, sg, nullptr, na, 0.0, sA, na);
+    spmv<T, T>(c, H.FA, nt, 2, sg, nullptr, na, 0.0, sA, na);
   }
-  // y_A = C_A^{-1} s: forward sweep on the second stream, one event per chunk of slabs
-  const bool two = H.s2 != nullptr;
-  hipStream_t sa = two ? H.s2 : s;
+  // y_A = C_A^{-1} s: forward sweep, on the second stream one chunk of slabs at a time
+  const bool two = !rec && H.s2 != nullptr;
+  Ctx ca{two ? H.s2 : c.s, c.rec};
   if (two) {
-    (void)hipEventRecord(H.ev_fork, s);
-    (void)hipStreamWaitEvent(sa, H.ev_fork, 0);
+    (void)hipEventRecord(H.ev_fork, c.s);
+    (void)hipStreamWaitEvent(ca.s, H.ev_fork, 0);
   }
-  const int C = std::max(1, H.chunk);
+  const bool chain = H.use_chain && !rec;
+  const int C = two ? std::max(1, H.chunk) : nt;
   const int nch = (nt + C - 1) / C;
-  for (int c = 0; c < nch; ++c) {
-    if (H.use_chain) {
-      ChainArgs<T> ch;
-      ch.C0 = st_op<T>(B, H.sC0);
-      ch.C1 = st_op<T>(B, H.sC1);
-      ch.C2 = st_op<T>(B, H.sC2);
-      ch.Mj = st_op<T>(B, H.sMj);
-      ch.KjA = st_op<T>(B, H.sKjA);
-      ch.k0 = c * C;
-      ch.k1 = std::min(nt, (c + 1) * C);
-      ch.deg = H.ca_deg;
-      ch.mit = mit;
-      ch.na = na;
-      ch.nj = nj;
-      ch.dt = dt;
-      ch.alone = H.amgC0.alone_dev;
-      ch.dinvC = static_cast<const T*>(H.amgC0.lev[0].dinv);
-      ch.dinv_stride = H.amgC0.nsets > 1 ? na : 0;
-      ch.dinvM = static_cast<const T*>(H.dMj);
-      ch.mth = mth;
-      ch.mde = mde;
-      ch.sA = sA;
-      ch.yA = yA;
-      ch.rj = rj;
-      ch.yj = yj;
-      ch.r = at<T>(B, L.chr);
-      ch.d0 = at<T>(B, L.chd0);
-      ch.d1 = at<T>(B, L.chd1);
-      hipLaunchKernelGGL((k_ca_chain<T>), dim3(1), dim3(kChainBlock), 0, sa, ch);
-      if (two) (void)hipEventRecord(H.ev_chunk[c], sa);
+  for (int ch = 0; ch < nch; ++ch) {
+    if (chain) {
+      ChainArgs<T> cha;
+      cha.C0 = st_op<T>(B, H.sC0);
+      cha.CP = st_op<T>(B, H.sCP);
+      cha.CQ = st_op<T>(B, H.sCQ);
+      cha.Mj = st_op<T>(B, H.sMj);
+      cha.KjA = st_op<T>(B, H.sKjA);
+      cha.k0 = ch * C;
+      cha.k1 = std::min(nt, (ch + 1) * C);
+      cha.deg = H.ca_deg;
+      cha.mit = mit;
+      cha.na = na;
+      cha.nj = nj;
+      cha.dt = dt;
+      cha.alone = H.amgC0.alone_dev;
+      cha.dinvC = static_cast<const T*>(H.amgC0.lev[0].dinv);
+      cha.dinv_stride = H.amgC0.nsets > 1 ? na : 0;
+      cha.dinvM = static_cast<const T*>(H.dMj);
+      cha.mth = mth;
+      cha.mde = mde;
+      cha.sA = sA;
+      cha.yA = yA;
+      cha.rj = rj;
+      cha.yj = yj;
+      cha.r = at<T>(B, L.chr);
+      cha.d0 = at<T>(B, L.chd0);
+      cha.d1 = at<T>(B, L.chd1);
+      hipLaunchKernelGGL((k_ca_chain<T>), dim3(1), dim3(kChainBlock), 0, ca.s, cha);
+      if (two) (void)hipEventRecord(H.ev_chunk[ch], ca.s);
       continue;
     }
-    for (int k = c * C; k < std::min(nt, (c + 1) * C); ++k) {
+    for (int k = ch * C; k < std::min(nt, (ch + 1) * C); ++k) {
       if (H.use_stencil && H.ca_deg > 0) {
-        sweep_step_stencil<T>(sa, H, H.amgC0, H.sC0, k >= 1 ? &H.sC1 : nullptr, k - 1, 1.0 / dt,
-                              yA + int64_t(k - 1) * na, k >= 2 ? &H.sC2 : nullptr, 0, -1.0 / (dt * dt),
-                              yA + int64_t(k - 2) * na, sA + int64_t(k) * na, yA + int64_t(k) * na, k, H.ca_deg, 2);
+        // increment over the predictor y^0 (k = 1) or 2 y^{k-1} - y^{k-2} (k >= 2)
+        sweep_step_stencil<T>(ca, H, H.amgC0, H.sC0, k >= 1 ? &H.sCP : nullptr, k, 1.0, yA + int64_t(k - 1) * na,
+                              k >= 2 ? &H.sCQ : nullptr, k, 1.0, yA + int64_t(k - 2) * na, sA + int64_t(k) * na,
+                              yA + int64_t(k) * na, k, H.ca_deg, 2, k >= 1, k >= 2 ? 2.0 : 1.0, k >= 2 ? -1.0 : 0.0);
       } else {
         Seg<T> sg[2];
         int nsg = 0;
         if (k >= 1) sg[nsg++] = seg<T>(H.C1, 0, k - 1, 0, yA + int64_t(k - 1) * na, 0, 0, 0, 1, 1.0 / dt);
         if (k >= 2) sg[nsg++] = seg<T>(H.C1, 1, 0, 0, yA + int64_t(k - 2) * na, 0, 0, 0, 1, -1.0 / (dt * dt));
-        sweep_step<T>(sa, H.amgC0, H.C1, nsg, sg, sA + int64_t(k) * na, yA + int64_t(k) * na, k, H.ca_deg, vc);
+        sweep_step<T>(ca, H.amgC0, H.C1, nsg, sg, sA + int64_t(k) * na, yA + int64_t(k) * na, k, H.ca_deg, vc);
       }
     }
-    if (two) (void)hipEventRecord(H.ev_chunk[c], sa);
+    if (two) (void)hipEventRecord(H.ev_chunk[ch], ca.s);
   }
   // 2. pressure (concurrently with the C_A sweep): q = K_p^{-1} r_p; t = F_p q;
   //    x_p = -M_p^{-1} t (xp holds M_p^{-1} t; the sign is applied where x_p is used)
-  amg_solve<T>(s, H.amgKp, nt, 0, 0, q, rp, vc);
+  amg_solve<T>(c, H.amgKp, nt, 0, 0, q, rp, vc);
   {
     Seg<T> sg[2] = {seg<T>(H.Fp, 0, 0, 1, q, np, 0, 0, nt, 1.0), seg<T>(H.Fp, 1, 0, 0, q, np, -1, 1, nt, 1.0)};
-    spmv<T, T>(s, H.Fp, nt, 2, sg, nullptr, np, 0.0, t, np);
+    spmv<T, T>(c, H.Fp, nt, 2, sg, nullptr, np, 0.0, t, np);
   }
-  cheb_solve<T>(s, H.Mp, nt, 0, 0, static_cast<const T*>(H.dMp), 0, nullptr, mth, mde, t, xp, mr, md0, md1, np, mit,
+  cheb_solve<T>(c, H.Mp, nt, 0, 0, static_cast<const T*>(H.dMp), 0, nullptr, mth, mde, t, xp, mr, md0, md1, np, mit,
                 0, false);
   // 3. per chunk, once its y_A is ready: y_j = M_j^{-1}(r_j - K_jA y_A);
   //    g_u = r_u - Z_j y_j - Z_A y_A - B^T x_p; x_u = F_u^{-1} g_u (forward sweep)
-  for (int c = 0; c < nch; ++c) {
-    const int k0 = c * C, kc = std::min(nt, (c + 1) * C) - k0;
-    if (two) (void)hipStreamWaitEvent(s, H.ev_chunk[c], 0);
-    if (!H.use_chain) {
-      spmv1<T>(s, H.KjA, kc, 0, 0, yA + int64_t(k0) * na, na, -1.0, rj + int64_t(k0) * nj, 1.0,
+  for (int ch = 0; ch < nch; ++ch) {
+    const int k0 = ch * C, kc = std::min(nt, (ch + 1) * C) - k0;
+    if (two) (void)hipStreamWaitEvent(c.s, H.ev_chunk[ch], 0);
+    if (!chain) {
+      spmv1<T>(c, H.KjA, kc, 0, 0, yA + int64_t(k0) * na, na, -1.0, rj + int64_t(k0) * nj, 1.0,
                rj + int64_t(k0) * nj, nj);
-      cheb_solve<T>(s, H.Mj, kc, 0, 0, static_cast<const T*>(H.dMj), 0, nullptr, mth, mde, rj + int64_t(k0) * nj,
+      cheb_solve<T>(c, H.Mj, kc, 0, 0, static_cast<const T*>(H.dMj), 0, nullptr, mth, mde, rj + int64_t(k0) * nj,
                     yj + int64_t(k0) * nj, mr, md0, md1, nj, mit, 0, false);
     }
     {
       Seg<T> sg[3] = {seg<T>(H.Zj, 0, k0, 1, yj + int64_t(k0) * nj, nj, 0, 0, kc, -1.0),
                       seg<T>(H.Zj, 1, k0, 1, yA + int64_t(k0) * na, na, 0, 0, kc, -1.0),
                       seg<T>(H.Zj, 2, 0, 0, xp + int64_t(k0) * np, np, 0, 0, kc, 1.0)};
-      spmv<T, T>(s, H.Zj, kc, 3, sg, ru + int64_t(k0) * nu, nu, 1.0, yu + int64_t(k0) * nu, nu);
+      spmv<T, T>(c, H.Zj, kc, 3, sg, ru + int64_t(k0) * nu, nu, 1.0, yu + int64_t(k0) * nu, nu);
     }
     for (int k = k0; k < k0 + kc; ++k) {
       if (H.use_stencil && H.fu_deg > 0) {
-        sweep_step_stencil<T>(s, H, H.amgFu, H.sFu, k >= 1 ? &H.sMu : nullptr, 0, 1.0, xu + int64_t(k - 1) * nu,
-                              nullptr, 0, 0.0, nullptr, yu + int64_t(k) * nu, xu + int64_t(k) * nu, k, H.fu_deg, 1);
+        // increment over the predictor x^{k-1}: r0 = g^k - (F_u,k - M_u/dt) x^{k-1}
+        sweep_step_stencil<T>(c, H, H.amgFu, H.sFu, k >= 1 ? &H.sAu : nullptr, k, -1.0, xu + int64_t(k - 1) * nu,
+                              nullptr, 0, 0.0, nullptr, yu + int64_t(k) * nu, xu + int64_t(k) * nu, k, H.fu_deg, 1,
+                              k >= 1, 1.0, 0.0);
       } else {
         Seg<T> sg = seg<T>(H.Mu, 0, 0, 0, xu + int64_t(k - 1) * nu, 0, 0, 0, 1, 1.0 / dt);
-        sweep_step<T>(s, H.amgFu, H.Mu, k >= 1 ? 1 : 0, &sg, yu + int64_t(k) * nu, xu + int64_t(k) * nu, k,
+        sweep_step<T>(c, H.amgFu, H.Mu, k >= 1 ? 1 : 0, &sg, yu + int64_t(k) * nu, xu + int64_t(k) * nu, k,
                       H.fu_deg, vc);
       }
     }
   }
   // 4. join with the pressure normalisation 1^T M_p p = 0
-  hipLaunchKernelGGL((k_slab_sums_t<T>), dim3(nt), dim3(kBlock), 0, s, xp, int64_t(np), np, H.mp_rowsum,
-                     psum + nt);
-  hipLaunchKernelGGL((k_join<T>), dim3(grid_for(int64_t(ns) * nt)), dim3(kBlock), 0, s, z, ns, nt, o2, o3, o4, xu,
-                     xp, -1.0, psum + nt, H.msum, yj, yA);
+  slab_sums_t<T>(c, xp, int64_t(np), np, H.mp_rowsum, psum + nt, nt);
+  {
+    JoinArgs<T> a{z, ns, nt, o2, o3, o4, xu, xp, -1.0, psum + nt, H.msum, yj, yA, jsel, jstride};
+    emit(c, kKJoin, dim3(grid_for(int64_t(ns) * nt)), &k_join<T>, a);
+  }
   return ST_OK;
 }
 
 // ================================================ P_T^{-T} (adjoint) ====
 template <class T>
-int precond_transpose(Handle& H, const double* r, double* z, hipStream_t s) {
+int precond_transpose(Handle& H, const double* r, double* z, Ctx& c) {
   if (!H.adjoint) return ST_EINVAL;
   const Dims& d = H.d;
   const int nt = d.nt;
@@ -750,7 +638,7 @@ int precond_transpose(Handle& H, const double* r, double* z, hipStream_t s) {
   T* ru = at<T>(B, L.ru); T* xu = at<T>(B, L.xu);
   T* rp = at<T>(B, L.rp); T* q = at<T>(B, L.q); T* t = at<T>(B, L.t); T* xp = at<T>(B, L.xp);
   T* rj = at<T>(B, L.rj); T* yj = at<T>(B, L.yj);
-  T* ra = at<T>(B, L.ra); T* c = at<T>(B, L.wA); T* f = at<T>(B, L.sA); T* yA = at<T>(B, L.yA);
+  T* ra = at<T>(B, L.ra); T* cA = at<T>(B, L.wA); T* f = at<T>(B, L.sA); T* yA = at<T>(B, L.yA);
   T* mr = at<T>(B, L.mr); T* md0 = at<T>(B, L.md0); T* md1 = at<T>(B, L.md1);
   double* psum = at<double>(B, L.psum);
   const int o2 = d.off[2], o3 = d.off[3], o4 = d.off[4], ns = d.ns;
@@ -760,133 +648,215 @@ int precond_transpose(Handle& H, const double* r, double* z, hipStream_t s) {
   const int mit = H.mass_iters;
   const double mlo = 0.24, mhi = 2.3, mth = 0.5 * (mhi + mlo), mde = 0.5 * (mhi - mlo);
 
-  hipLaunchKernelGGL(k_slab_sums_d, dim3(nt), dim3(kBlock), 0, s, r, int64_t(ns), o2, np, nullptr, psum);
-  hipLaunchKernelGGL((k_split<T>), dim3(grid_for(int64_t(ns) * nt)), dim3(kBlock), 0, s, r, ns, nt, o2, o3, o4,
-                     psum, ru, rp, rj, ra);
+  slab_sums_d(c, r, int64_t(ns), o2, np, nullptr, psum, nt);
+  {
+    SplitArgs<T> a{r, ns, nt, o2, o3, o4, psum, ru, rp, rj, ra, nullptr, 0};
+    emit(c, kKSplit, dim3(grid_for(int64_t(ns) * nt)), &k_split<T>, a);
+  }
   // x_u = F_u^{-T} r_u, backward in time: F_uk^T x^k = r^k + (1/dt) M_u x^{k+1}
   for (int k = nt - 1; k >= 0; --k) {
     Seg<T> sg = seg<T>(H.Mu, 0, 0, 0, xu + int64_t(k + 1) * nu, 0, 0, 0, 1, 1.0 / dt);
     if (H.use_stencil && H.fu_deg > 0)
-      sweep_step_stencil<T>(s, H, H.amgFuT, H.sFuT, k + 1 < nt ? &H.sMu : nullptr, 0, 1.0, xu + int64_t(k + 1) * nu,
-                            nullptr, 0, 0.0, nullptr, ru + int64_t(k) * nu, xu + int64_t(k) * nu, k, H.fu_deg, 1);
+      sweep_step_stencil<T>(c, H, H.amgFuT, H.sFuT, k + 1 < nt ? &H.sAuT : nullptr, k, -1.0,
+                            xu + int64_t(k + 1) * nu, nullptr, 0, 0.0, nullptr, ru + int64_t(k) * nu,
+                            xu + int64_t(k) * nu, k, H.fu_deg, 1, k + 1 < nt, 1.0, 0.0);
     else
-      sweep_step<T>(s, H.amgFuT, H.Mu, k + 1 < nt ? 1 : 0, &sg, ru + int64_t(k) * nu, xu + int64_t(k) * nu, k,
+      sweep_step<T>(c, H.amgFuT, H.Mu, k + 1 < nt ? 1 : 0, &sg, ru + int64_t(k) * nu, xu + int64_t(k) * nu, k,
                     H.fu_deg, vc);
   }
   // x_p = S_p^{-T}(r_p - B x_u),  S_p^{-T} = -K_p^{-1} F_p^T M_p^{-1}
-  spmv1<T>(s, H.B, nt, 0, 0, xu, nu, -1.0, rp, 1.0, rp, np);
-  hipLaunchKernelGGL((k_slab_sums_t<T>), dim3(nt), dim3(kBlock), 0, s, rp, int64_t(np), np, nullptr, psum);
-  hipLaunchKernelGGL((k_slab_shift<T>), dim3(grid_for(int64_t(np) * nt)), dim3(kBlock), 0, s, rp, int64_t(np), np,
-                     nt, psum, 1.0 / np);
-  cheb_solve<T>(s, H.Mp, nt, 0, 0, static_cast<const T*>(H.dMp), 0, nullptr, mth, mde, rp, q, mr, md0, md1, np, mit,
+  spmv1<T>(c, H.B, nt, 0, 0, xu, nu, -1.0, rp, 1.0, rp, np);
+  slab_sums_t<T>(c, rp, int64_t(np), np, nullptr, psum, nt);
+  slab_shift<T>(c, rp, int64_t(np), np, nt, psum, 1.0 / np);
+  cheb_solve<T>(c, H.Mp, nt, 0, 0, static_cast<const T*>(H.dMp), 0, nullptr, mth, mde, rp, q, mr, md0, md1, np, mit,
                 0, false);
   {
     Seg<T> sg[2] = {seg<T>(H.Fpt, 0, 0, 1, q, np, 0, 0, nt, 1.0), seg<T>(H.Fpt, 1, 0, 0, q, np, 1, 0, nt - 1, 1.0)};
-    spmv<T, T>(s, H.Fpt, nt, 2, sg, nullptr, np, 0.0, t, np);
+    spmv<T, T>(c, H.Fpt, nt, 2, sg, nullptr, np, 0.0, t, np);
   }
-  hipLaunchKernelGGL((k_slab_sums_t<T>), dim3(nt), dim3(kBlock), 0, s, t, int64_t(np), np, nullptr, psum);
-  hipLaunchKernelGGL((k_slab_shift<T>), dim3(grid_for(int64_t(np) * nt)), dim3(kBlock), 0, s, t, int64_t(np), np,
-                     nt, psum, 1.0 / np);
-  amg_solve<T>(s, H.amgKp, nt, 0, 0, xp, t, vc);
+  slab_sums_t<T>(c, t, int64_t(np), np, nullptr, psum, nt);
+  slab_shift<T>(c, t, int64_t(np), np, nt, psum, 1.0 / np);
+  amg_solve<T>(c, H.amgKp, nt, 0, 0, xp, t, vc);
   // y_j = M_j^{-1}(r_j - Z_j^T x_u)
-  spmv1<T>(s, H.Zjt, nt, 0, 1, xu, nu, -1.0, rj, 1.0, rj, nj);
-  cheb_solve<T>(s, H.Mj, nt, 0, 0, static_cast<const T*>(H.dMj), 0, nullptr, mth, mde, rj, yj, mr, md0, md1, nj, mit,
+  spmv1<T>(c, H.Zjt, nt, 0, 1, xu, nu, -1.0, rj, 1.0, rj, nj);
+  cheb_solve<T>(c, H.Mj, nt, 0, 0, static_cast<const T*>(H.dMj), 0, nullptr, mth, mde, rj, yj, mr, md0, md1, nj, mit,
                 0, false);
   // h = r_A - Z_A^T x_u - K_jA^T y_j  (in ra)
-  spmv1<T>(s, H.ZAt, nt, 0, 1, xu, nu, -1.0, ra, 1.0, ra, na);
-  spmv1<T>(s, H.KjAt, nt, 0, 0, yj, nj, -1.0, ra, 1.0, ra, na);
+  spmv1<T>(c, H.ZAt, nt, 0, 1, xu, nu, -1.0, ra, 1.0, ra, na);
+  spmv1<T>(c, H.KjAt, nt, 0, 0, yj, nj, -1.0, ra, 1.0, ra, na);
   // c = C_A^{-T} h backward: C0_k^T c^k = h^k + (1/dt) C1_k^T c^{k+1} - (1/dt^2) C2^T c^{k+2}
   for (int k = nt - 1; k >= 0; --k) {
     Seg<T> sg[2];
     int nsg = 0;
-    if (k + 1 < nt) sg[nsg++] = seg<T>(H.C1t, 0, k, 0, c + int64_t(k + 1) * na, 0, 0, 0, 1, 1.0 / dt);
-    if (k + 2 < nt) sg[nsg++] = seg<T>(H.C1t, 1, 0, 0, c + int64_t(k + 2) * na, 0, 0, 0, 1, -1.0 / (dt * dt));
+    if (k + 1 < nt) sg[nsg++] = seg<T>(H.C1t, 0, k, 0, cA + int64_t(k + 1) * na, 0, 0, 0, 1, 1.0 / dt);
+    if (k + 2 < nt) sg[nsg++] = seg<T>(H.C1t, 1, 0, 0, cA + int64_t(k + 2) * na, 0, 0, 0, 1, -1.0 / (dt * dt));
     if (H.use_stencil && H.ca_deg > 0)
-      sweep_step_stencil<T>(s, H, H.amgC0T, H.sC0T, k + 1 < nt ? &H.sC1T : nullptr, k, 1.0 / dt,
-                            c + int64_t(k + 1) * na, k + 2 < nt ? &H.sC2T : nullptr, 0, -1.0 / (dt * dt),
-                            c + int64_t(k + 2) * na, ra + int64_t(k) * na, c + int64_t(k) * na, k, H.ca_deg, 2);
+      sweep_step_stencil<T>(c, H, H.amgC0T, H.sC0T, k + 1 < nt ? &H.sCPT : nullptr, k, 1.0, cA + int64_t(k + 1) * na,
+                            k + 2 < nt ? &H.sCQT : nullptr, k, 1.0, cA + int64_t(k + 2) * na, ra + int64_t(k) * na,
+                            cA + int64_t(k) * na, k, H.ca_deg, 2, k + 1 < nt, k + 2 < nt ? 2.0 : 1.0,
+                            k + 2 < nt ? -1.0 : 0.0);
     else
-      sweep_step<T>(s, H.amgC0T, H.C1t, nsg, sg, ra + int64_t(k) * na, c + int64_t(k) * na, k, H.ca_deg, vc);
+      sweep_step<T>(c, H.amgC0T, H.C1t, nsg, sg, ra + int64_t(k) * na, cA + int64_t(k) * na, k, H.ca_deg, vc);
   }
   // f = F_A^T c; y_A = M_A^{-1} f
   {
-    Seg<T> sg[2] = {seg<T>(H.FAt, 0, 0, 1, c, na, 0, 0, nt, 1.0), seg<T>(H.FAt, 1, 0, 0, c, na, 1, 0, nt - 1, 1.0)};
-    spmv<T, T>(s, H.FAt, nt, 2, sg, nullptr, na, 0.0, f, na);
+    Seg<T> sg[2] = {seg<T>(H.FAt, 0, 0, 1, cA, na, 0, 0, nt, 1.0), seg<T>(H.FAt, 1, 0, 0, cA, na, 1, 0, nt - 1, 1.0)};
+    spmv<T, T>(c, H.FAt, nt, 2, sg, nullptr, na, 0.0, f, na);
   }
-  cheb_solve<T>(s, H.MA, nt, 0, 0, static_cast<const T*>(H.dMA), 0, nullptr, mth, mde, f, yA, mr, md0, md1, na, mit,
+  cheb_solve<T>(c, H.MA, nt, 0, 0, static_cast<const T*>(H.dMA), 0, nullptr, mth, mde, f, yA, mr, md0, md1, na, mit,
                 0, false);
-  hipLaunchKernelGGL((k_slab_sums_t<T>), dim3(nt), dim3(kBlock), 0, s, xp, int64_t(np), np, H.mp_rowsum,
-                     psum + nt);
-  hipLaunchKernelGGL((k_join<T>), dim3(grid_for(int64_t(ns) * nt)), dim3(kBlock), 0, s, z, ns, nt, o2, o3, o4, xu,
-                     xp, -1.0, psum + nt, H.msum, yj, yA);
+  slab_sums_t<T>(c, xp, int64_t(np), np, H.mp_rowsum, psum + nt, nt);
+  {
+    JoinArgs<T> a{z, ns, nt, o2, o3, o4, xu, xp, -1.0, psum + nt, H.msum, yj, yA, nullptr, 0};
+    emit(c, kKJoin, dim3(grid_for(int64_t(ns) * nt)), &k_join<T>, a);
+  }
   return ST_OK;
 }
 
-int apply_precond(Handle& H, const double* r, double* z, hipStream_t s, bool transpose) {
+int apply_precond(Handle& H, const double* r, double* z, Ctx& c, bool transpose, const int* jsel = nullptr,
+                  int64_t jstride = 0) {
   int rc;
   if (H.fp32)
-    rc = transpose ? precond_transpose<float>(H, r, z, s) : precond_forward<float>(H, r, z, s);
+    rc = transpose ? precond_transpose<float>(H, r, z, c) : precond_forward<float>(H, r, z, c, jsel, jstride);
   else
-    rc = transpose ? precond_transpose<double>(H, r, z, s) : precond_forward<double>(H, r, z, s);
+    rc = transpose ? precond_transpose<double>(H, r, z, c) : precond_forward<double>(H, r, z, c, jsel, jstride);
   return rc;
 }
 
 // y = alpha J x + beta b  (J or J^T), FP64
-void apply_J(Handle& H, const double* x, double* y, hipStream_t s, bool transpose, double alpha, const double* b) {
+void apply_J(Handle& H, const double* x, double* y, Ctx& c, bool transpose, double alpha, const double* b) {
   const DGroup& g = transpose ? H.JT : H.J;
   const int nt = H.d.nt, ns = H.d.ns;
   Seg<double> sg[3] = {
       seg<double>(g, 0, 0, 1, x, ns, 0, 0, nt, alpha),
       seg<double>(g, 1, 0, 0, x, ns, 0, 0, nt, alpha),
       transpose ? seg<double>(g, 2, 0, 0, x, ns, 1, 0, nt - 1, alpha) : seg<double>(g, 2, 0, 0, x, ns, -1, 1, nt, alpha)};
-  spmv<double, double>(s, g, nt, 3, sg, b, ns, b ? 1.0 : 0.0, y, ns, kRoleJ);
+  spmv<double, double>(c, g, nt, 3, sg, b, ns, b ? 1.0 : 0.0, y, ns, kRoleJ);
 }
 
 // ============================================================ FGMRES ===
-struct Reducer {
-  Handle& H;
-  hipStream_t s;
-  double* partial;
-  int64_t N;
-  // out[i] = V_i . w for i < nv (mode 0 set, 2 add); mode 1: out[0] = ||w||
-  void dots(const double* V, int nv, const double* w, double* out, int mode, double* copy_to = nullptr) {
-    hipLaunchKernelGGL(k_mdot_partial, dim3(kPartialBlocks, nv), dim3(kBlock), 0, s, V, N, w, partial);
-    hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(kBlock), 0, s, partial, kPartialBlocks, out, mode, copy_to);
-  }
+// Device pointers of one system's Krylov workspace for restart length m.
+struct Krylov {
+  int64_t N = 0;
+  int m = 0, ldh = 0;
+  double *V = nullptr, *Z = nullptr, *w = nullptr, *bp = nullptr, *Hc = nullptr, *sm = nullptr;
+  double *g = nullptr, *cs = nullptr, *sn = nullptr, *y = nullptr, *psum = nullptr, *partial = nullptr;
+  int* jsel = nullptr;
 };
+
+Krylov krylov(Handle& H, int m) {
+  Krylov K;
+  char* B = H.base;
+  const WsLayout& L = H.L;
+  K.N = int64_t(H.d.nt) * H.d.ns;
+  K.m = m;
+  K.ldh = m + 1;
+  K.V = at<double>(B, L.V);
+  K.Z = at<double>(B, L.Z);
+  K.w = at<double>(B, L.w);
+  K.bp = at<double>(B, L.r);
+  K.Hc = at<double>(B, L.hess);     // column j at Hc + j*(m+1)
+  K.sm = at<double>(B, L.small);
+  K.g = K.sm + 64;
+  K.cs = K.g + (m + 2);
+  K.sn = K.cs + (m + 2);
+  K.y = K.sn + (m + 2);
+  K.psum = at<double>(B, L.psum);
+  K.partial = at<double>(B, L.partial);
+  K.jsel = at<int>(B, L.jsel);
+  return K;
+}
+
+// out[i] = V_i . w for i < nv (mode 0 set, 2 add); mode 1: out[0] = ||w||
+void emit_dots(Ctx& c, const Krylov& K, const double* V, int nv, const double* w, double* out, int mode,
+               double* copy_to = nullptr) {
+  MdotArgs a{V, K.N, w, K.partial};
+  emit(c, kKMdot, dim3(kPartialBlocks, nv), &k_mdot_partial, a);
+  ReduceArgs r{K.partial, kPartialBlocks, out, mode, copy_to};
+  emit(c, kKReduce, dim3(nv), &k_reduce, r);
+}
+
+// bp = b with the pressure rows projected per slab; sm[0] = ||bp||; x = 0 unless given.
+void emit_fgmres_init(Ctx& c, Handle& H, const Krylov& K, const double* b, double* x, bool zero_x) {
+  const Dims& d = H.d;
+  slab_sums_d(c, b, int64_t(d.ns), d.off[2], d.np, nullptr, K.psum, d.nt);
+  ProjectPArgs pa{b, K.bp, d.ns, d.nt, d.off[2], d.off[3], K.psum};
+  emit(c, kKProjectP, dim3(grid_for(K.N)), &k_project_p, pa);
+  emit_dots(c, K, K.bp, 1, K.bp, K.sm + 0, 1);
+  if (zero_x) {
+    FillArgs f{x, K.N, 0.0};
+    emit(c, kKFill, dim3(grid_for(K.N)), &k_fill, f);
+  }
+}
+
+// V_0 = bp - J x (unnormalised); sm[0] = ||V_0||.  The J apply goes through `jac`.
+template <class JacFn>
+void emit_residual(Ctx& c, const Krylov& K, double* x, JacFn&& jac) {
+  jac(x, K.V, -1.0, K.bp);
+  emit_dots(c, K, K.V, 1, K.V, K.sm + 0, 1);
+}
+
+// V_0 /= beta; g = (beta, 0, ...).
+void emit_cycle_head(Ctx& c, const Krylov& K) {
+  ScaleArgs s{K.V, K.V, K.N, K.sm + 0};
+  emit(c, kKScale, dim3(grid_for(K.N)), &k_scale, s);
+  InitGArgs ig{K.g, K.m + 1, K.sm + 0};
+  emit(c, kKInitG, dim3(1), &k_init_g, ig);
+}
+
+// After w = J z_j: CGS2 against V_0..V_j, h_{j+1,j} = ||w|| (copied to sm[1]),
+// the Givens update (estimate in sm[2]) and V_{j+1} = w / h_{j+1,j}.
+void emit_arnoldi(Ctx& c, const Krylov& K, int j) {
+  double* hcol = K.Hc + int64_t(j) * K.ldh;
+  emit_dots(c, K, K.V, j + 1, K.w, hcol, 0);
+  CombineArgs u1{K.w, K.V, K.N, hcol, j + 1, -1.0};
+  emit(c, kKCombine, dim3(grid_for(K.N)), &k_combine, u1);
+  emit_dots(c, K, K.V, j + 1, K.w, K.y, 0);
+  CombineArgs u2{K.w, K.V, K.N, K.y, j + 1, -1.0};
+  emit(c, kKCombine, dim3(grid_for(K.N)), &k_combine, u2);
+  // H[:, j] += second-pass coefficients (one-element partials per entry)
+  ReduceArgs add{K.y, 1, hcol, 2, nullptr};
+  emit(c, kKReduce, dim3(j + 1), &k_reduce, add);
+  emit_dots(c, K, K.w, 1, K.w, hcol + (j + 1), 1, K.sm + 1);
+  GivensArgs gv{K.Hc, j, K.ldh, K.g, K.cs, K.sn, K.sm + 2};
+  emit(c, kKGivens, dim3(1), &k_givens, gv);
+  if (j + 1 < K.m) {
+    ScaleArgs s{K.V + int64_t(j + 1) * K.N, K.w, K.N, K.sm + 1};
+    emit(c, kKScale, dim3(grid_for(K.N)), &k_scale, s);
+  }
+}
+
+// x += Z y with y from the rotated Hessenberg system of size mused.
+void emit_cycle_end(Ctx& c, const Krylov& K, double* x, int mused) {
+  TrisolveArgs ts{K.Hc, mused, K.ldh, K.g, K.y};
+  emit(c, kKTrisolve, dim3(1), &k_trisolve, ts);
+  CombineArgs u{x, K.Z, K.N, K.y, mused, 1.0};
+  emit(c, kKCombine, dim3(grid_for(K.N)), &k_combine, u);
+}
+
+// Pressure of x normalised per slab: 1^T M_p p^k = 0.
+void emit_finalize(Ctx& c, Handle& H, const Krylov& K, double* x) {
+  const Dims& d = H.d;
+  slab_sums_d(c, x, int64_t(d.ns), d.off[2], d.np, H.mp_rowsum, K.psum, d.nt);
+  slab_shift<double>(c, x + d.off[2], int64_t(d.ns), d.np, d.nt, K.psum, 1.0 / H.msum);
+}
 
 int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* info, hipStream_t s, bool adjoint) {
   auto t0 = std::chrono::steady_clock::now();
-  const Dims& d = H.d;
-  const int64_t N = int64_t(d.nt) * d.ns;
   const int m = o->restart > 0 ? o->restart : 30;
   if (m > H.max_restart) return ST_EINVAL;
   if (adjoint && !H.adjoint) return ST_EINVAL;
   const int maxit = o->maxit > 0 ? o->maxit : 1000;
-  char* B = H.base;
-  const WsLayout& L = H.L;
-  double* V = at<double>(B, L.V);
-  double* Z = at<double>(B, L.Z);
-  double* w = at<double>(B, L.w);
-  double* bp = at<double>(B, L.r);
-  double* Hc = at<double>(B, L.hess);     // column j at Hc + j*(m+1)
-  double* sm = at<double>(B, L.small);
-  double* g = sm + 64;
-  double* cs = g + (m + 2);
-  double* sn = cs + (m + 2);
-  double* y = sn + (m + 2);
-  double* psum = at<double>(B, L.psum);
-  const int ldh = m + 1;
-  Reducer red{H, s, at<double>(B, L.partial), N};
+  const Krylov K = krylov(H, m);
+  Ctx c{s, nullptr};
   double* hs = H.host_small;
-  const int gr = grid_for(N);
   std::vector<hipEvent_t> evs, jevs;
   auto jac = [&](const double* xin, double* yout, double alpha, const double* bb) {
     hipEvent_t a, bev;
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&bev);
     (void)hipEventRecord(a, s);
-    apply_J(H, xin, yout, s, adjoint, alpha, bb);
+    apply_J(H, xin, yout, c, adjoint, alpha, bb);
     (void)hipEventRecord(bev, s);
     jevs.push_back(a);
     jevs.push_back(bev);
@@ -896,7 +866,7 @@ int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* 
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&bev);
     (void)hipEventRecord(a, s);
-    apply_precond(H, r, z, s, adjoint);
+    apply_precond(H, r, z, c, adjoint);
     (void)hipEventRecord(bev, s);
     evs.push_back(a);
     evs.push_back(bev);
@@ -906,33 +876,28 @@ int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* 
     if (hipStreamSynchronize(s) != hipSuccess) return ST_EHIP;
     return ST_OK;
   };
-  // project b's pressure rows: bp = P b
-  hipLaunchKernelGGL(k_slab_sums_d, dim3(d.nt), dim3(kBlock), 0, s, b_in, int64_t(d.ns), d.off[2], d.np, nullptr,
-                     psum);
-  hipLaunchKernelGGL(k_project_p, dim3(gr), dim3(kBlock), 0, s, b_in, bp, d.ns, d.nt, d.off[2], d.off[3], psum);
-  red.dots(bp, 1, bp, sm + 0, 1);
-  int rc = fetch(sm, 1);
+  emit_fgmres_init(c, H, K, b_in, x, !o->x0_given);
+  int rc = fetch(K.sm, 1);
   if (rc) return rc;
   const double bnorm = hs[0];
   if (!std::isfinite(bnorm)) return ST_EBREAKDOWN;
   const double tol = std::max(o->rtol * bnorm, o->atol);
-  if (!o->x0_given) HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * N, s));
   info->iterations = 0;
   info->restarts = 0;
   info->converged = 0;
   int its = 0, status = ST_ENOTCONV;
   double true_res = 0.0;
   if (bnorm == 0.0) {
-    HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * N, s));
+    FillArgs f{x, K.N, 0.0};
+    emit(c, kKFill, dim3(grid_for(K.N)), &k_fill, f);
+    HIP_TRY(hipStreamSynchronize(s));
     info->converged = 1;
     info->true_rel_residual = 0.0;
     return ST_OK;
   }
   for (;;) {
-    // r = bp - J x  -> V_0 (unnormalised), beta
-    jac(x, V, -1.0, bp);
-    red.dots(V, 1, V, sm + 0, 1);
-    rc = fetch(sm, 1);
+    emit_residual(c, K, x, jac);
+    rc = fetch(K.sm, 1);
     if (rc) return rc;
     const double beta = hs[0];
     true_res = beta;
@@ -943,29 +908,13 @@ int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* 
     }
     if (its >= maxit) break;
     if (o->history && its < o->history_len && its == 0) o->history[0] = beta / bnorm;
-    hipLaunchKernelGGL(k_scale, dim3(gr), dim3(kBlock), 0, s, V, V, N, sm + 0);
-    hipLaunchKernelGGL(k_init_g, dim3(1), dim3(64), 0, s, g, m + 1, sm + 0);
-    int j = 0, mused = 0;
-    for (; j < m; ++j) {
-      double* vj = V + int64_t(j) * N;
-      double* zj = Z + int64_t(j) * N;
-      precond(vj, zj);
-      jac(zj, w, 1.0, nullptr);
-      double* hcol = Hc + int64_t(j) * ldh;
-      // CGS2: two classical Gram-Schmidt passes
-      red.dots(V, j + 1, w, hcol, 0);
-      hipLaunchKernelGGL(k_mgs_update, dim3(gr), dim3(kBlock), 0, s, w, V, N, hcol, j + 1);
-      red.dots(V, j + 1, w, y, 0);
-      hipLaunchKernelGGL(k_mgs_update, dim3(gr), dim3(kBlock), 0, s, w, V, N, y, j + 1);
-      // H[:, j] += second-pass coefficients
-      {
-        // hcol[i] += y[i]: reuse k_reduce in add mode with a one-element partial per entry
-        hipLaunchKernelGGL(k_reduce, dim3(j + 1), dim3(kBlock), 0, s, y, 1, hcol, 2, nullptr);
-      }
-      red.dots(w, 1, w, hcol + (j + 1), 1, sm + 1);   // h_{j+1,j} = ||w||, copy to sm[1]
-      hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, s, Hc, j, ldh, g, cs, sn, sm + 2);
-      if (j + 1 < m) hipLaunchKernelGGL(k_scale, dim3(gr), dim3(kBlock), 0, s, V + int64_t(j + 1) * N, w, N, sm + 1);
-      rc = fetch(sm, 3);
+    emit_cycle_head(c, K);
+    int mused = 0;
+    for (int j = 0; j < m; ++j) {
+      precond(K.V + int64_t(j) * K.N, K.Z + int64_t(j) * K.N);
+      jac(K.Z + int64_t(j) * K.N, K.w, 1.0, nullptr);
+      emit_arnoldi(c, K, j);
+      rc = fetch(K.sm, 3);
       if (rc) return rc;
       ++its;
       mused = j + 1;
@@ -974,15 +923,10 @@ int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* 
       if (!std::isfinite(est) || !std::isfinite(hs[1])) return ST_EBREAKDOWN;
       if (est <= tol || its >= maxit) break;
     }
-    hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(1), 0, s, Hc, mused, ldh, g, y);
-    hipLaunchKernelGGL(k_update_x, dim3(gr), dim3(kBlock), 0, s, x, Z, N, y, mused);
+    emit_cycle_end(c, K, x, mused);
     info->restarts++;
   }
-  // normalise the pressure of x: 1^T M_p p^k = 0
-  hipLaunchKernelGGL(k_slab_sums_d, dim3(d.nt), dim3(kBlock), 0, s, x, int64_t(d.ns), d.off[2], d.np, H.mp_rowsum,
-                     psum);
-  hipLaunchKernelGGL((k_slab_shift<double>), dim3(grid_for(int64_t(d.np) * d.nt)), dim3(kBlock), 0, s,
-                     x + d.off[2], int64_t(d.ns), d.np, d.nt, psum, 1.0 / H.msum);
+  emit_finalize(c, H, K, x);
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipGetLastError());
   auto elapsed = [](std::vector<hipEvent_t>& v) {
@@ -1007,8 +951,296 @@ int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* 
   return status;
 }
 
+// ============================================================ batches ===
+// Lockstep FGMRES over several systems.  Each system's launches are recorded
+// once (the preconditioner with its Krylov column read from the device, one
+// Arnoldi tail per column j, the cycle head) and again per solve for the
+// launches that name the caller's b and x.  A batched phase runs launch t of
+// every member's program in one k_multi launch.
+struct ProgRef {
+  const std::vector<Member>* a = nullptr;
+  const std::vector<Member>* b = nullptr;
+  size_t size() const { return (a ? a->size() : 0) + (b ? b->size() : 0); }
+  const Member& at(size_t t) const { return (a && t < a->size()) ? (*a)[t] : (*b)[t - (a ? a->size() : 0)]; }
+};
+
+struct BatchSys {
+  Handle* H = nullptr;
+  Krylov K;
+  std::vector<Member> pt, head;
+  std::vector<std::vector<Member>> tail;   // per Krylov column j
+  std::vector<Member> init, resid, fin;    // per solve (b, x)
+  std::vector<std::vector<Member>> end;    // per solve, index mused - 1
+};
+
+struct Batch {
+  std::vector<BatchSys> sys;
+  int m = 30, fp32 = 0;
+  size_t out_off = 0, static_off = 0, static_bytes = 0, dyn_off = 0, dyn_bytes = 0, ws_bytes = 0;
+  char* base = nullptr;
+  double* out = nullptr;                 // device [nsys][4]: gathered sm[0..2]
+  double* host_out = nullptr;            // pinned
+  unsigned char* staging = nullptr;      // pinned, dyn_bytes
+  int64_t lock_launches = 0, sep_launches = 0;   // one Arnoldi step, lockstep vs one system at a time
+};
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Appends the argument blocks of `ops` to `pool` (the host image of a device
+// region starting at dev) and returns their launch descriptors.
+std::vector<Member> place(const std::vector<Op>& ops, std::vector<unsigned char>& pool, const unsigned char* dev) {
+  std::vector<Member> out;
+  out.reserve(ops.size());
+  for (const Op& op : ops) {
+    const size_t off = align_up(pool.size(), 16);
+    pool.resize(off + size_t(op.size));
+    std::memcpy(pool.data() + off, op.args, size_t(op.size));
+    Member mb;
+    mb.args = dev ? dev + off : nullptr;
+    mb.kind = op.kind;
+    mb.blocks = op.gx * op.gy;
+    mb.gx = op.gx;
+    mb.pad = 0;
+    out.push_back(mb);
+  }
+  return out;
+}
+
+// Static programs of every member; dev = device address of the static pool (null: sizing only).
+void record_static(Batch& Bt, std::vector<unsigned char>& pool, const unsigned char* dev) {
+  pool.clear();
+  for (size_t s = 0; s < Bt.sys.size(); ++s) {
+    BatchSys& S = Bt.sys[s];
+    Handle& H = *S.H;
+    S.K = krylov(H, Bt.m);
+    const Krylov& K = S.K;
+    std::vector<Op> ops;
+    Ctx c{nullptr, &ops};
+    apply_precond(H, K.V, K.Z, c, false, K.jsel, K.N);
+    S.pt = place(ops, pool, dev);
+    ops.clear();
+    emit_cycle_head(c, K);
+    CopySmallArgs cs0{K.sm, nullptr, 0, K.jsel, 0};
+    emit(c, kKCopySmall, dim3(1), &k_copy_small, cs0);
+    S.head = place(ops, pool, dev);
+    S.tail.assign(size_t(Bt.m), {});
+    for (int j = 0; j < Bt.m; ++j) {
+      ops.clear();
+      apply_J(H, K.Z + int64_t(j) * K.N, K.w, c, false, 1.0, nullptr);
+      emit_arnoldi(c, K, j);
+      CopySmallArgs cs{K.sm, Bt.out + 4 * s, 3, K.jsel, j + 1};
+      emit(c, kKCopySmall, dim3(1), &k_copy_small, cs);
+      S.tail[size_t(j)] = place(ops, pool, dev);
+    }
+  }
+}
+
+// Per-solve programs (they name b and x); dev = device address of the dynamic pool.
+void record_dynamic(Batch& Bt, std::vector<unsigned char>& pool, const unsigned char* dev, const double* const* b,
+                    double* const* x, bool zero_x) {
+  pool.clear();
+  for (size_t s = 0; s < Bt.sys.size(); ++s) {
+    BatchSys& S = Bt.sys[s];
+    Handle& H = *S.H;
+    const Krylov& K = S.K;
+    const double* bs = b ? b[s] : nullptr;
+    double* xs = x ? x[s] : nullptr;
+    std::vector<Op> ops;
+    Ctx c{nullptr, &ops};
+    emit_fgmres_init(c, H, K, bs, xs, zero_x);
+    CopySmallArgs g0{K.sm, Bt.out + 4 * s, 3, nullptr, 0};
+    emit(c, kKCopySmall, dim3(1), &k_copy_small, g0);
+    S.init = place(ops, pool, dev);
+    ops.clear();
+    emit_residual(c, K, xs, [&](const double* xin, double* yout, double alpha, const double* bb) {
+      apply_J(H, xin, yout, c, false, alpha, bb);
+    });
+    emit(c, kKCopySmall, dim3(1), &k_copy_small, g0);
+    S.resid = place(ops, pool, dev);
+    S.end.assign(size_t(Bt.m), {});
+    for (int mu = 1; mu <= Bt.m; ++mu) {
+      ops.clear();
+      emit_cycle_end(c, K, xs, mu);
+      S.end[size_t(mu - 1)] = place(ops, pool, dev);
+    }
+    ops.clear();
+    emit_finalize(c, H, K, xs);
+    S.fin = place(ops, pool, dev);
+  }
+}
+
+template <class T>
+int run_phase(const std::vector<ProgRef>& progs, hipStream_t s) {
+  size_t len = 0;
+  for (const ProgRef& p : progs) len = std::max(len, p.size());
+  for (size_t t = 0; t < len; ++t) {
+    MultiArgs a;
+    std::memset(&a, 0, sizeof(a));
+    int64_t total = 0;
+    for (const ProgRef& p : progs) {
+      if (t >= p.size()) continue;
+      a.m[a.nmem++] = p.at(t);
+      total += p.at(t).blocks;
+    }
+    if (a.nmem == 0 || total <= 0) continue;
+    if (total > int64_t(0x7fffffff)) return ST_EINTERNAL;
+    hipLaunchKernelGGL((k_multi<T>), dim3(unsigned(total)), dim3(kBlock), 0, s, a);
+  }
+  return hipGetLastError() == hipSuccess ? ST_OK : ST_EHIP;
+}
+
+int run_phase_any(const Batch& Bt, const std::vector<ProgRef>& progs, hipStream_t s) {
+  return Bt.fp32 ? run_phase<float>(progs, s) : run_phase<double>(progs, s);
+}
+
+int batch_solve(Batch& Bt, const double* const* b, double* const* x, const st_opts* o, st_info* infos,
+                int* statuses, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int ns = int(Bt.sys.size());
+  const int m = Bt.m;
+  if ((o->restart > 0 && o->restart != m)) return ST_EINVAL;
+  const int maxit = o->maxit > 0 ? o->maxit : 1000;
+  for (int i = 0; i < ns; ++i)
+    if (!b[i] || !x[i] || b[i] == x[i]) return ST_EINVAL;
+  // per-solve programs: record, copy to the device, wait for the copy
+  std::vector<unsigned char> pool;
+  record_dynamic(Bt, pool, reinterpret_cast<unsigned char*>(Bt.base + Bt.dyn_off), b, x, !o->x0_given);
+  if (pool.size() > Bt.dyn_bytes) return ST_EINTERNAL;
+  std::memcpy(Bt.staging, pool.data(), pool.size());
+  HIP_TRY(hipMemcpyAsync(Bt.base + Bt.dyn_off, Bt.staging, pool.size(), hipMemcpyHostToDevice, s));
+  auto fetch = [&]() -> int {
+    if (hipMemcpyAsync(Bt.host_out, Bt.out, sizeof(double) * 4 * ns, hipMemcpyDeviceToHost, s) != hipSuccess)
+      return ST_EHIP;
+    return hipStreamSynchronize(s) == hipSuccess ? ST_OK : ST_EHIP;
+  };
+  std::vector<double> bnorm(ns, 0.0), tol(ns, 0.0), true_res(ns, 0.0);
+  std::vector<int> its(ns, 0), status(ns, ST_ENOTCONV), restarts(ns, 0), done(ns, 0), mused(ns, 0);
+  std::vector<ProgRef> progs;
+  for (int i = 0; i < ns; ++i) progs.push_back(ProgRef{&Bt.sys[i].init, nullptr});
+  int rc = run_phase_any(Bt, progs, s);
+  if (!rc) rc = fetch();
+  if (rc) return rc;
+  std::vector<int> active;
+  for (int i = 0; i < ns; ++i) {
+    bnorm[i] = Bt.host_out[4 * i];
+    if (!std::isfinite(bnorm[i])) {
+      status[i] = ST_EBREAKDOWN;
+      done[i] = 1;
+    } else if (bnorm[i] == 0.0) {
+      Ctx c{s, nullptr};
+      FillArgs f{x[i], Bt.sys[i].K.N, 0.0};
+      emit(c, kKFill, dim3(grid_for(Bt.sys[i].K.N)), &k_fill, f);
+      status[i] = ST_OK;
+      done[i] = 1;
+    } else {
+      tol[i] = std::max(o->rtol * bnorm[i], o->atol);
+      active.push_back(i);
+    }
+  }
+  std::vector<int> finalize;
+  while (!active.empty()) {
+    progs.clear();
+    for (int i : active) progs.push_back(ProgRef{&Bt.sys[i].resid, nullptr});
+    rc = run_phase_any(Bt, progs, s);
+    if (!rc) rc = fetch();
+    if (rc) return rc;
+    std::vector<int> cyc;
+    for (int i : active) {
+      const double beta = Bt.host_out[4 * i];
+      true_res[i] = beta;
+      if (!std::isfinite(beta)) {
+        status[i] = ST_EBREAKDOWN;
+        done[i] = 1;
+        continue;
+      }
+      if (beta <= tol[i]) {
+        status[i] = ST_OK;
+        finalize.push_back(i);
+        continue;
+      }
+      if (its[i] >= maxit) {
+        finalize.push_back(i);
+        continue;
+      }
+      if (o->history && its[i] == 0 && o->history_len > 0) o->history[size_t(i) * o->history_len] = beta / bnorm[i];
+      cyc.push_back(i);
+    }
+    active = cyc;
+    if (active.empty()) break;
+    progs.clear();
+    for (int i : cyc) progs.push_back(ProgRef{&Bt.sys[i].head, nullptr});
+    rc = run_phase_any(Bt, progs, s);
+    if (rc) return rc;
+    for (int i : cyc) mused[i] = 0;
+    std::vector<int> inner = cyc;
+    for (int j = 0; j < m && !inner.empty(); ++j) {
+      progs.clear();
+      for (int i : inner) progs.push_back(ProgRef{&Bt.sys[i].pt, &Bt.sys[i].tail[size_t(j)]});
+      rc = run_phase_any(Bt, progs, s);
+      if (!rc) rc = fetch();
+      if (rc) return rc;
+      std::vector<int> next;
+      for (int i : inner) {
+        ++its[i];
+        mused[i] = j + 1;
+        const double hj = Bt.host_out[4 * i + 1], est = Bt.host_out[4 * i + 2];
+        if (o->history && its[i] < o->history_len) o->history[size_t(i) * o->history_len + its[i]] = est / bnorm[i];
+        if (!std::isfinite(est) || !std::isfinite(hj)) {
+          status[i] = ST_EBREAKDOWN;
+          done[i] = 1;
+          continue;
+        }
+        if (est <= tol[i] || its[i] >= maxit) continue;
+        next.push_back(i);
+      }
+      inner = next;
+    }
+    // close the cycle of every system still in it
+    std::vector<int> cont;
+    progs.clear();
+    for (int i : cyc) {
+      if (done[i]) continue;
+      progs.push_back(ProgRef{&Bt.sys[i].end[size_t(mused[i] - 1)], nullptr});
+      restarts[i]++;
+      cont.push_back(i);
+    }
+    rc = run_phase_any(Bt, progs, s);
+    if (rc) return rc;
+    active = cont;
+  }
+  progs.clear();
+  for (int i : finalize) progs.push_back(ProgRef{&Bt.sys[i].fin, nullptr});
+  rc = run_phase_any(Bt, progs, s);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipGetLastError());
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = ST_OK;
+  for (int i = 0; i < ns; ++i) {
+    st_info& in = infos[i];
+    in.iterations = its[i];
+    in.restarts = restarts[i];
+    in.converged = status[i] == ST_OK ? 1 : 0;
+    in.true_rel_residual = bnorm[i] > 0.0 ? true_res[i] / bnorm[i] : 0.0;
+    in.seconds = secs;
+    in.precond_seconds = 0.0;
+    in.jacobian_seconds = 0.0;
+    in.precond_calls = its[i];
+    in.jacobian_calls = its[i] + restarts[i] + (status[i] == ST_OK ? 1 : 0);
+    if (statuses) statuses[i] = status[i];
+    if (status[i] < 0 && worst >= 0) worst = status[i];
+    else if (status[i] == ST_ENOTCONV && worst == ST_OK) worst = ST_ENOTCONV;
+  }
+  return worst;
+}
+
 }  // namespace
 }  // namespace st
+
+struct st_batch {
+  st::Batch b;
+};
+
 
 // ============================================================ C ABI ===
 extern "C" {
@@ -1041,20 +1273,23 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
   H.ca_deg = P.ca_deg;
   H.use_stencil = P.use_stencil;
   H.sFu = P.sFu;
-  H.sMu = P.sMu;
+  H.sAu = P.sAu;
   H.sC0 = P.sC0;
-  H.sC1 = P.sC1;
-  H.sC2 = P.sC2;
+  H.sCP = P.sCP;
+  H.sCQ = P.sCQ;
   H.sFuT = P.sFuT;
   H.sC0T = P.sC0T;
-  H.sC1T = P.sC1T;
-  H.sC2T = P.sC2T;
+  H.sAuT = P.sAuT;
+  H.sCPT = P.sCPT;
+  H.sCQT = P.sCQT;
   H.sMj = P.sMj;
   H.sKjA = P.sKjA;
   // One workgroup covers the C_A grid with at most one row per thread: then the
   // chain kernel (no dispatch per step) beats per-step launches; on larger
   // grids one CU is too slow for it.
-  H.use_chain = H.use_stencil && H.ca_deg > 0 && std::max(H.d.na, H.d.nj) <= kChainBlock ? 1 : 0;
+  H.use_chain = H.use_stencil && H.ca_deg > 0 && std::max(H.d.na, H.d.nj) <= kChainBlock && P.prob.sweep_chain >= 0
+                    ? 1
+                    : 0;
   H.base = static_cast<char*>(ws);
   H.L = workspace_layout(P);
   char* base = H.base;
@@ -1153,33 +1388,38 @@ int st_sizes(const st_handle* h, int64_t* n_total, int* ns, int* nt) {
 
 int st_apply_jacobian(st_handle* h, const double* x, double* y, void* stream) {
   if (!h || !x || !y || x == y) return ST_EINVAL;
-  st::apply_J(h->h, x, y, static_cast<hipStream_t>(stream), false, 1.0, nullptr);
+  st::Ctx c{static_cast<hipStream_t>(stream), nullptr};
+  st::apply_J(h->h, x, y, c, false, 1.0, nullptr);
   return hipGetLastError() == hipSuccess ? ST_OK : ST_EHIP;
 }
 
 int st_apply_jacobian_t(st_handle* h, const double* x, double* y, void* stream) {
   if (!h || !x || !y || x == y || !h->h.adjoint) return ST_EINVAL;
-  st::apply_J(h->h, x, y, static_cast<hipStream_t>(stream), true, 1.0, nullptr);
+  st::Ctx c{static_cast<hipStream_t>(stream), nullptr};
+  st::apply_J(h->h, x, y, c, true, 1.0, nullptr);
   return hipGetLastError() == hipSuccess ? ST_OK : ST_EHIP;
 }
 
 int st_apply_precond(st_handle* h, const double* r, double* z, void* stream) {
   if (!h || !r || !z || r == z) return ST_EINVAL;
-  int rc = st::apply_precond(h->h, r, z, static_cast<hipStream_t>(stream), false);
+  st::Ctx c{static_cast<hipStream_t>(stream), nullptr};
+  int rc = st::apply_precond(h->h, r, z, c, false);
   if (rc) return rc;
   return hipGetLastError() == hipSuccess ? ST_OK : ST_EHIP;
 }
 
 int st_apply_precond_t(st_handle* h, const double* r, double* z, void* stream) {
   if (!h || !r || !z || r == z || !h->h.adjoint) return ST_EINVAL;
-  int rc = st::apply_precond(h->h, r, z, static_cast<hipStream_t>(stream), true);
+  st::Ctx c{static_cast<hipStream_t>(stream), nullptr};
+  int rc = st::apply_precond(h->h, r, z, c, true);
   if (rc) return rc;
   return hipGetLastError() == hipSuccess ? ST_OK : ST_EHIP;
 }
 
 int st_apply_initial_coupling(st_handle* h, const double* a0, double* y, void* stream) {
   if (!h || !a0 || !y || a0 == y) return ST_EINVAL;
-  st::spmv1<double>(static_cast<hipStream_t>(stream), h->h.MA64, 1, 0, 0, a0, 0, 1.0, nullptr, 0.0, y, 0,
+  st::Ctx c{static_cast<hipStream_t>(stream), nullptr};
+  st::spmv1<double>(c, h->h.MA64, 1, 0, 0, a0, 0, 1.0, nullptr, 0.0, y, 0,
                     st::kRoleSlab);
   return hipGetLastError() == hipSuccess ? ST_OK : ST_EHIP;
 }
@@ -1192,6 +1432,114 @@ int st_fgmres_solve(st_handle* h, const double* b, double* x, const st_opts* o, 
 int st_adjoint_solve(st_handle* h, const double* g, double* lam, const st_opts* o, st_info* info, void* stream) {
   if (!h || !g || !lam || !o || !info || g == lam) return ST_EINVAL;
   return st::fgmres(h->h, g, lam, o, info, static_cast<hipStream_t>(stream), true);
+}
+
+int st_batch_create(st_handle* const* hs, int nsys, int restart, st_batch** out) {
+  using namespace st;
+  if (!hs || !out || nsys < 1 || nsys > kMaxMembers) return ST_EINVAL;
+  *out = nullptr;
+  const int m = restart > 0 ? restart : 30;
+  for (int i = 0; i < nsys; ++i) {
+    if (!hs[i]) return ST_EINVAL;
+    if (m > hs[i]->h.max_restart) return ST_EINVAL;
+    if (hs[i]->h.fp32 != hs[0]->h.fp32) return ST_EINVAL;
+    for (int k = 0; k < i; ++k)
+      if (hs[k] == hs[i]) return ST_EINVAL;
+  }
+  st_batch* bb = nullptr;
+  try {
+    bb = new st_batch;
+    Batch& B = bb->b;
+    B.m = m;
+    B.fp32 = hs[0]->h.fp32;
+    B.sys.resize(size_t(nsys));
+    for (int i = 0; i < nsys; ++i) B.sys[size_t(i)].H = &hs[i]->h;
+    // sizes: the programs have the same shape whatever the addresses
+    std::vector<unsigned char> pool;
+    record_static(B, pool, nullptr);
+    B.static_bytes = pool.size();
+    std::vector<double*> fake(size_t(nsys), nullptr);
+    record_dynamic(B, pool, nullptr, fake.data(), fake.data(), true);
+    B.dyn_bytes = pool.size();
+    B.out_off = 0;
+    B.static_off = align_up(sizeof(double) * 4 * size_t(nsys), 256);
+    B.dyn_off = align_up(B.static_off + B.static_bytes, 256);
+    B.ws_bytes = align_up(B.dyn_off + B.dyn_bytes, 256);
+    // launches of one Arnoldi step (preconditioner + J + Gram-Schmidt), lockstep vs separate
+    size_t mx = 0, sum = 0;
+    for (const BatchSys& S : B.sys) {
+      const size_t len = S.pt.size() + S.tail[0].size();
+      mx = std::max(mx, len);
+      sum += len;
+    }
+    B.lock_launches = int64_t(mx);
+    B.sep_launches = int64_t(sum);
+  } catch (...) {
+    delete bb;
+    return ST_ENOMEM;
+  }
+  *out = bb;
+  return ST_OK;
+}
+
+int st_batch_workspace_size(const st_batch* b, size_t* bytes) {
+  if (!b || !bytes) return ST_EINVAL;
+  *bytes = b->b.ws_bytes;
+  return ST_OK;
+}
+
+int st_batch_launch_counts(const st_batch* b, int64_t* lockstep, int64_t* separate) {
+  if (!b) return ST_EINVAL;
+  if (lockstep) *lockstep = b->b.lock_launches;
+  if (separate) *separate = b->b.sep_launches;
+  return ST_OK;
+}
+
+int st_batch_upload(st_batch* b, void* ws, size_t ws_bytes, void* stream) {
+  using namespace st;
+  if (!b || !ws) return ST_EINVAL;
+  Batch& B = b->b;
+  if (ws_bytes < B.ws_bytes) return ST_ENOMEM;
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return ST_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  try {
+    B.base = static_cast<char*>(ws);
+    B.out = reinterpret_cast<double*>(B.base + B.out_off);
+    std::vector<unsigned char> pool;
+    record_static(B, pool, reinterpret_cast<unsigned char*>(B.base + B.static_off));
+    if (pool.size() != B.static_bytes) return ST_EINTERNAL;
+    if (!B.host_out &&
+        hipHostMalloc(reinterpret_cast<void**>(&B.host_out), sizeof(double) * 4 * B.sys.size(),
+                      hipHostMallocDefault) != hipSuccess)
+      return ST_EHIP;
+    if (!B.staging && B.dyn_bytes &&
+        hipHostMalloc(reinterpret_cast<void**>(&B.staging), B.dyn_bytes, hipHostMallocDefault) != hipSuccess)
+      return ST_EHIP;
+    if (hipMemcpyAsync(B.base + B.static_off, pool.data(), pool.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return ST_EHIP;
+  } catch (...) {
+    return ST_ENOMEM;
+  }
+  return ST_OK;
+}
+
+int st_fgmres_solve_batched(st_batch* b, const double* const* bvec, double* const* x, const st_opts* o,
+                            st_info* infos, int* statuses, void* stream) {
+  if (!b || !bvec || !x || !o || !infos || !b->b.base) return ST_EINVAL;
+  try {
+    return st::batch_solve(b->b, bvec, x, o, infos, statuses, static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return ST_ENOMEM;
+  }
+}
+
+int st_batch_destroy(st_batch* b) {
+  if (!b) return ST_OK;
+  if (b->b.host_out) (void)hipHostFree(b->b.host_out);
+  if (b->b.staging) (void)hipHostFree(b->b.staging);
+  delete b;
+  return ST_OK;
 }
 
 }  // extern "C"

@@ -204,7 +204,8 @@ struct Plan {
   SellGroup C1, C2, C1t, C2t;     // sweep couplings of C_A
   SellGroup MA64;                 // M_A / dt in FP64 (initial-condition coupling)
   // Stencil forms of the sweep operators (used with Chebyshev-alone sweeps).
-  StencilOp sFu, sMu, sC0, sC1, sC2, sFuT, sC0T, sC1T, sC2T;
+  // sAu, sCP, sCQ (and the transposes): couplings of the increment-form sweeps.
+  StencilOp sFu, sAu, sC0, sCP, sCQ, sFuT, sAuT, sC0T, sCPT, sCQT;
   StencilOp sMj, sKjA;            // 3x3 stencils of the single-workgroup C_A chain
   int use_stencil = 0;
   Amg amgFu, amgC0, amgKp;        // spatial solvers (per-slab for Fu, C0; shared Kp)
@@ -218,6 +219,7 @@ struct WsLayout {
   size_t V = 0, Z = 0, w = 0, r = 0, hess = 0, small = 0, partial = 0, psum = 0;
   size_t ru = 0, yu = 0, xu = 0, rp = 0, q = 0, t = 0, xp = 0, rj = 0, yj = 0;
   size_t ra = 0, wA = 0, sA = 0, yA = 0, mr = 0, md0 = 0, md1 = 0, chr = 0, chd0 = 0, chd1 = 0;
+  size_t jsel = 0;                              // int: Krylov column of a batched P_T apply
   std::vector<size_t> kp_lev, fu_lev, ca_lev;   // 6 vectors per level each
   size_t end = 0;
 };

@@ -19,7 +19,8 @@ in for them with the sizes of the five benchmark configurations):
   sampled at ``t_k = k dt`` for the slabs ``k = 1..Nt``;
 * shear-layer state: ``A = tanh((y - 1/2) / 0.1) + 0.01 cos(pi x)``, constant
   in time, with the velocity from the Fourier generator;
-* right-hand sides: N(0, 1) on every free unknown, slab-major.
+* right-hand sides: N(0, 1) on every free unknown, slab-major;
+* batch of uneven systems: n and Nt drawn per system (``batch_configs``).
 """
 from __future__ import annotations
 
@@ -61,6 +62,20 @@ CONFIGS = {
     "cfg3_re1000": Config("cfg3_re1000", 64, 128, 0.01, 1000.0, 1000.0, rhs_seeds=(1,)),
     "cfg5": Config("cfg5", 128, 128, 0.005, 500.0, 500.0, rhs_seeds=(1,)),
 }
+
+
+def batch_configs(count: int = 16, seed: int = 0, meshes=(16, 32, 48, 64, 96), max_nt: int = 256,
+                  re: float = 300.0) -> list:
+    """The uneven batch workload: ``count`` systems with n drawn from ``meshes``
+    and Nt from {16, 32, ..., max_nt} (seeded draw), dt = 1/Nt (final time 1),
+    Re = S = ``re``; system i has state seed 100 + i and right-hand-side seed 200 + i."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.choice(np.asarray(meshes)))
+        nt = 16 * int(rng.integers(1, max_nt // 16 + 1))
+        out.append(Config(f"batch{i}", n, nt, 1.0 / nt, re, re, state_seed=100 + i, rhs_seeds=(200 + i,)))
+    return out
 
 
 def slab_sizes(n: int) -> dict:

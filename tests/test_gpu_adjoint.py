@@ -1,7 +1,11 @@
 """Adjoint (transposed, backward-in-time) path on the GPU.
 
 * dot tests: <J x, y> = <x, J^T y> and <P_T^{-1} x, y> = <x, P_T^{-T} y>
-  (zero-sum pressure rows), from the GPU operators themselves;
+  (zero-sum pressure rows), from the GPU operators themselves; the second one
+  with converged sweep solves: the sweeps solve each slab for its increment
+  over a predictor, and with approximate spatial solves the backward sweeps of
+  P_T^{-T} are that same construction for the transposed system, not the
+  exact transpose of the approximate forward operator;
 * the adjoint solve against the oracle's backward substitution (cfg1 in exact
   mode: 1e-10; production mode: residual <= 1e-8);
 * gradients of J = 1/2 |A(T) - A_target|^2 through the autograd Function versus
@@ -30,12 +34,12 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
-def build(n, nt, precision="fp64", inner="amg", **kw):
+def build(n, nt, precision="fp64", inner="amg", solver_degree=0, **kw):
     from paper_2309_00768_amd import binding
     cfg = inputs.Config("a", n, nt, 0.05, 100.0, 100.0, **kw)
     ub, ab = inputs.state(cfg)
     plan = binding.Plan(n, nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision=precision, inner=inner,
-                        adjoint=True)
+                        adjoint=True, fu_solver=solver_degree, ca_solver=2 * solver_degree)
     return cfg, ub, ab, binding.System(plan, "cuda:0")
 
 
@@ -49,7 +53,7 @@ def zero_sum_p(v, sysg):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_gpu_dot_tests(precision):
     say(f"[gpu] dot tests {precision}")
-    cfg, ub, ab, sysg = build(12, 10, precision=precision)
+    cfg, ub, ab, sysg = build(12, 10, precision=precision, solver_degree=40 if precision == "fp64" else 0)
     rng = np.random.default_rng(21)
     x = zero_sum_p(rng.standard_normal(sysg.N), sysg)
     y = zero_sum_p(rng.standard_normal(sysg.N), sysg)

@@ -117,20 +117,42 @@ def test_fgmres_amg_reaches_1e8(precision):
 
 @pytest.mark.parametrize("n,nt", [(8, 8), (3, 5), (6, 1)])
 def test_stencil_and_sell_sweeps_agree(n, nt):
-    """The Chebyshev-alone sweeps on 5x5 stencil operators and on SELL matrices
-    compute the same polynomial (FP64): P_T^{-1} and P_T^{-T} agree to 1e-12."""
+    """Sweeps with converged spatial solves (Chebyshev-Jacobi of degree 40 on
+    F_u,k and 80 on C_A,k, whose estimated interval is wider) agree
+    whatever the form: the stencil sweeps solve for the increment over a
+    predictor with combined coupling stencils, the SELL sweeps for the whole
+    slab from zero with the plain couplings.  P_T^{-1} and P_T^{-T} (FP64) agree
+    to 1e-10, which checks the combined stencils against the plain blocks."""
     say(f"[gpu] stencil vs SELL sweeps n={n} nt={nt}")
     from paper_2309_00768_amd import binding
     cfg, ub, ab, ref = case(n, nt)
     out = []
     for fmt in (0, 1):
-        plan = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, fu_solver=6, ca_solver=8,
+        plan = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, fu_solver=40, ca_solver=80,
                             adjoint=True, sweep_format=fmt)
         sysg = binding.System(plan, "cuda:0")
         r = np.random.default_rng(8).standard_normal(ref.N)
         out.append((sysg.apply_precond(dev(r)).cpu().numpy(), sysg.apply_precond(dev(r), transpose=True).cpu().numpy()))
-    assert rel(out[0][0], out[1][0]) <= 1e-12
-    assert rel(out[0][1], out[1][1]) <= 1e-12
+    assert rel(out[0][0], out[1][0]) <= 1e-10
+    assert rel(out[0][1], out[1][1]) <= 1e-10
+
+
+def test_long_horizon_fp32_sweeps_stay_accurate():
+    """224 slabs of the uneven-batch recipe (n = 16, dt = 1/224, Re = S = 300): with
+    approximate spatial solves a sweep that solves each slab from zero amplifies
+    their error by the recursion (the FP32 solve then stagnates); the increment
+    form keeps P_T usable and FGMRES reaches 1e-8."""
+    say("[gpu] long-horizon FP32 solve n=16 nt=224")
+    from paper_2309_00768_amd import binding
+    cfg = inputs.batch_configs()[4]
+    assert (cfg.n, cfg.nt) == (16, 224)
+    ub, ab = inputs.state(cfg)
+    plan = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp32")
+    sysg = binding.System(plan, "cuda:0")
+    b = dev(inputs.rhs(cfg, cfg.rhs_seeds[0]))
+    x, info, rc, _ = sysg.solve(b, rtol=1e-8, maxit=1500)
+    say(f"    its={info.iterations} res={info.true_rel_residual:.2e}")
+    assert rc == 0 and info.true_rel_residual <= 1e-8
 
 
 @pytest.mark.parametrize("precision,inner", [("fp64", "amg"), ("fp32", "amg"), ("fp64", "exact")])
