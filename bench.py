@@ -95,8 +95,8 @@ def probe_jacobian(cfg, ub, ab, b, dev, launches=5, copy_bytes=1 << 30):
 def bench_batch(args, dev):
     """Uneven batch: 16 systems (n in {16,...,96}, Nt in {16,...,256}, dt = 1/Nt,
     Re = S = 300), FP32 preconditioner, solved together in lockstep; a step is
-    one batched solve of every member to 1e-8.  The same systems solved one at
-    a time (each with its default two-stream preconditioner) are timed beside it."""
+    one batched solve of every member.  The same systems solved one at a time
+    (each with its own recorded preconditioner pipeline) are timed beside it."""
     import torch
     from paper_2309_00768_amd import binding, inputs
     cfgs = inputs.batch_configs()
@@ -104,8 +104,7 @@ def bench_batch(args, dev):
     t0 = time.perf_counter()
     for c in cfgs:
         ub, ab = inputs.state(c)
-        plan = binding.Plan(c.n, c.nt, c.dt, c.mu, c.eta, c.mu0, ub, ab, precision="fp32", single_stream=True,
-                            sweep_chain=False)
+        plan = binding.Plan(c.n, c.nt, c.dt, c.mu, c.eta, c.mu0, ub, ab, precision="fp32")
         si = plan.solver_info()
         systems.append(binding.System(plan, dev))
         plan.close()
@@ -155,7 +154,7 @@ def bench_batch(args, dev):
         "launches_per_arnoldi_step": {"lockstep": lock, "one_at_a_time": sep},
     }
     if not args.no_separate:
-        # the same systems one at a time (same arithmetic, one stream each)
+        # the same systems one at a time (same arithmetic, each its own pipeline)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k, (sg, b) in enumerate(zip(systems, rhs)):

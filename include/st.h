@@ -97,9 +97,13 @@ typedef struct st_problem {
                          is then not amplified by the recursion in time);
                          1 SELL, each step solved from zero (for comparison:
                          the two agree when the spatial solves converge)    */
-  int single_stream;  /* 1: run the whole of P_T^{-1} on the caller's stream
-                         (no overlap of the C_A and F_u sweeps)               */
-  int sweep_chunk;    /* slabs per chunk of the pipelined C_A sweep (0: auto) */
+  int single_stream;  /* 0: P_T^{-1} is recorded at st_create as two programs
+                         (the C_A sweep; the pressure part and the F_u sweep,
+                         each chunk of it waiting for that chunk of the C_A
+                         sweep) and replayed with one launch carrying a step
+                         of each; 1: launched step by step in program order
+                         (same arithmetic)                                    */
+  int sweep_chunk;    /* slabs per chunk of that pipeline (0: max(4, Nt/8))  */
   int sweep_chain;    /* 0: on grids of at most 1024 unknowns the C_A sweep and
                          the M_j solves of a chunk run in one workgroup (no
                          launch per step); -1: never (per-step launches)      */

@@ -15,10 +15,12 @@
 
 namespace st {
 
-// Index of the current Krylov vector for a preconditioner apply whose input
-// and output are columns of V and Z (batched solves); null: use the pointers.
-__device__ inline int64_t jsel_offset(const int* jsel, int64_t jstride) {
-  return jsel ? int64_t(*jsel) * jstride : 0;
+// A recorded preconditioner program reads its input and output vectors from a
+// device slot (set by k_set_ptrs before the program runs); otherwise the
+// pointers in the arguments are used.
+template <class P>
+__device__ inline P slot_or(P const* slot, P direct) {
+  return slot ? *slot : direct;
 }
 
 // Per-slab sums of src[k*ld + off + i], i < len (weights w[i] if w): out[k]; bx = k.
@@ -28,12 +30,11 @@ struct SlabSumsDArgs {
   int off, len;
   const double* w;
   double* out;
-  const int* jsel;
-  int64_t jstride;
+  const double* const* rslot;
 };
 
 __device__ inline void slab_sums_d_body(const SlabSumsDArgs& a, int k) {
-  const double* p = a.src + jsel_offset(a.jsel, a.jstride) + int64_t(k) * a.ld + a.off;
+  const double* p = slot_or(a.rslot, a.src) + int64_t(k) * a.ld + a.off;
   double acc = 0.0;
   for (int i = threadIdx.x; i < a.len; i += blockDim.x) acc += (a.w ? a.w[i] : 1.0) * p[i];
   acc = block_sum(acc);
@@ -66,8 +67,7 @@ struct SplitArgs {
   int ns, nt, o2, o3, o4;
   const double* psum;
   T *ru, *rp, *rj, *ra;
-  const int* jsel;
-  int64_t jstride;
+  const double* const* rslot;
 };
 
 template <class T>
@@ -75,7 +75,7 @@ __device__ inline void split_body(const SplitArgs<T>& a, int bx, int gx) {
   const int64_t N = int64_t(a.ns) * a.nt;
   const int ns = a.ns, o2 = a.o2, o3 = a.o3, o4 = a.o4;
   const int np = o3 - o2, nj = o4 - o3, na = ns - o4;
-  const double* r = a.r + jsel_offset(a.jsel, a.jstride);
+  const double* r = slot_or(a.rslot, a.r);
   for (int64_t i = bx * int64_t(kBlock) + threadIdx.x; i < N; i += int64_t(gx) * kBlock) {
     const int k = int(i / ns), c = int(i % ns);
     const double v = r[i];
@@ -99,8 +99,7 @@ struct JoinArgs {
   double msum;
   const T* yj;
   const T* ya;
-  const int* jsel;
-  int64_t jstride;
+  double* const* zslot;
 };
 
 template <class T>
@@ -108,7 +107,7 @@ __device__ inline void join_body(const JoinArgs<T>& a, int bx, int gx) {
   const int64_t N = int64_t(a.ns) * a.nt;
   const int ns = a.ns, o2 = a.o2, o3 = a.o3, o4 = a.o4;
   const int np = o3 - o2, nj = o4 - o3, na = ns - o4;
-  double* z = a.z + jsel_offset(a.jsel, a.jstride);
+  double* z = slot_or(a.zslot, a.z);
   for (int64_t i = bx * int64_t(kBlock) + threadIdx.x; i < N; i += int64_t(gx) * kBlock) {
     const int k = int(i / ns), c = int(i % ns);
     double v;
@@ -299,18 +298,30 @@ __device__ inline void fill_body(const FillArgs& a, int bx, int gx) {
   for (int64_t i = bx * int64_t(kBlock) + threadIdx.x; i < a.n; i += int64_t(gx) * kBlock) a.x[i] = a.v;
 }
 
-// dst[i] = src[i] for i < n (small gathers), then *iset = ival if iset.
+// dst[i] = src[i] for i < n (small gathers).
 struct CopySmallArgs {
   const double* src;
   double* dst;
   int n;
-  int* iset;
-  int ival;
 };
 
 __device__ inline void copy_small_body(const CopySmallArgs& a) {
   for (int i = threadIdx.x; i < a.n; i += blockDim.x) a.dst[i] = a.src[i];
-  if (a.iset && threadIdx.x == 0) *a.iset = a.ival;
+}
+
+// The input/output slots of a recorded preconditioner program: *rslot = r, *zslot = z.
+struct SetPtrsArgs {
+  const double** rslot;
+  double** zslot;
+  const double* r;
+  double* z;
+};
+
+__device__ inline void set_ptrs_body(const SetPtrsArgs& a) {
+  if (threadIdx.x == 0) {
+    *a.rslot = a.r;
+    *a.zslot = a.z;
+  }
 }
 
 // ------------------------------------------------------------ wrappers ---
@@ -337,5 +348,6 @@ __global__ __launch_bounds__(kBlock) void k_trisolve(TrisolveArgs a) { trisolve_
 __global__ __launch_bounds__(kBlock) void k_init_g(InitGArgs a) { init_g_body(a); }
 __global__ __launch_bounds__(kBlock) void k_fill(FillArgs a) { fill_body(a, blockIdx.x, gridDim.x); }
 __global__ __launch_bounds__(kBlock) void k_copy_small(CopySmallArgs a) { copy_small_body(a); }
+__global__ __launch_bounds__(kBlock) void k_set_ptrs(SetPtrsArgs a) { set_ptrs_body(a); }
 
 }  // namespace st

@@ -17,6 +17,7 @@
 
 #include "kernels.h"
 #include "kernels_vec.h"
+#include "st_internal.h"
 
 namespace st {
 
@@ -45,22 +46,34 @@ enum Kind : int {
   kKInitG,          // InitGArgs
   kKFill,           // FillArgs
   kKCopySmall,      // CopySmallArgs
+  kKSetPtrs,        // SetPtrsArgs
   kKNumKinds
 };
 
-constexpr int kOpArgBytes = 448;
-
-// One recorded launch.
+// One recorded launch: its kernel (for a replay through the same kernel),
+// the body kind (for a batched launch), grid and argument block.
 struct Op {
+  const void* fn = nullptr;
   int kind = 0;
   int gx = 1, gy = 1;
   int size = 0;
   alignas(16) unsigned char args[kOpArgBytes];
 };
 
+// A recorded preconditioner apply is two programs: `a` (the C_A sweep, and
+// the current solves when they balance the two better) and `b` (the rest,
+// then whatever follows the apply).  Op i of b may run only once dep[i] ops
+// of a have completed in earlier launches.
+struct Program {
+  std::vector<Op> a, b;
+  std::vector<int> dep;
+};
+
 struct Ctx {
   hipStream_t s = nullptr;
   std::vector<Op>* rec = nullptr;   // record mode when set
+  std::vector<int>* dep = nullptr;  // b-side: dependency of each recorded op
+  int need = 0;                     // a-ops the next recorded ops depend on
   bool recording() const { return rec != nullptr; }
 };
 
@@ -69,6 +82,7 @@ inline void emit(Ctx& c, int kind, dim3 grid, void (*kern)(A), const A& a) {
   static_assert(sizeof(A) <= kOpArgBytes, "kernel arguments exceed an op record");
   if (c.rec) {
     Op op;
+    op.fn = reinterpret_cast<const void*>(kern);
     op.kind = kind;
     op.gx = int(grid.x);
     op.gy = int(grid.y);
@@ -76,14 +90,62 @@ inline void emit(Ctx& c, int kind, dim3 grid, void (*kern)(A), const A& a) {
     std::memset(op.args, 0, sizeof(op.args));
     std::memcpy(op.args, &a, sizeof(A));
     c.rec->push_back(op);
+    if (c.dep) c.dep->push_back(c.need);
     return;
   }
   void* params[] = {const_cast<A*>(&a)};
   (void)hipLaunchKernel(reinterpret_cast<const void*>(kern), grid, dim3(kBlock), params, 0, c.s);
 }
 
+// ------------------------------------------------------- paired launches ---
+// One op of each of the two preconditioner programs in one launch: workgroups
+// [0, xblocks) run x, the rest run y.  One kernel per pair of bodies, each
+// holding only its two bodies (a kernel with all of them in a switch runs
+// every launch at the occupancy and register budget of the largest).
+template <class T>
+struct BodyStInit {
+  using Args = StInitArgs<T>;
+  static constexpr int kind = kKStInit;
+  __device__ static void run(const Args& a, int b, int) { st_init_body<T>(a, b); }
+};
+
+template <class T>
+struct BodyStCheb {
+  using Args = StChebArgs<T>;
+  static constexpr int kind = kKStCheb;
+  __device__ static void run(const Args& a, int b, int) { st_cheb_body<T>(a, b); }
+};
+
+template <class T>
+struct BodyCheb {
+  using Args = ChebArgs<T>;
+  static constexpr int kind = kKCheb;
+  __device__ static void run(const Args& a, int b, int gx) { cheb_body<T>(a, b % gx, b / gx); }
+};
+
+template <class T>
+struct BodySpmv {
+  using Args = SpmvArgs<T, T>;
+  static constexpr int kind = kKSpmvT;
+  __device__ static void run(const Args& a, int b, int gx) { spmv_body<T, T, T>(a, b % gx, b / gx); }
+};
+
+template <class X, class Y>
+struct TwoArgs {
+  typename X::Args x;
+  typename Y::Args y;
+  int xblocks, xgx, ygx;
+};
+
+template <class X, class Y>
+__global__ ST_LATENCY_KERNEL void k_two(TwoArgs<X, Y> p) {
+  const int b = blockIdx.x;
+  if (b < p.xblocks) X::run(p.x, b, p.xgx);
+  else Y::run(p.y, b - p.xblocks, p.ygx);
+}
+
 // ----------------------------------------------------- batched launches ---
-constexpr int kMaxMembers = 32;
+constexpr int kMaxMembers = 64;   // two programs per system, 32 systems
 
 struct Member {
   const unsigned char* args;   // device copy of the op's argument block
@@ -155,6 +217,7 @@ __global__ ST_LATENCY_KERNEL void k_multi(MultiArgs a) {
     case kKInitG: init_g_body(load_args<T, InitGArgs>(p)); break;
     case kKFill: fill_body(load_args<T, FillArgs>(p), bx, gx); break;
     case kKCopySmall: copy_small_body(load_args<T, CopySmallArgs>(p)); break;
+    case kKSetPtrs: set_ptrs_body(load_args<T, SetPtrsArgs>(p)); break;
     default: break;
   }
 }

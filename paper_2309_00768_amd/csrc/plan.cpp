@@ -156,7 +156,10 @@ WsLayout workspace_layout(const Plan& P) {
   L.chr = take(ts * mm);
   L.chd0 = take(ts * mm);
   L.chd1 = take(ts * mm);
-  L.jsel = take(sizeof(int));
+  L.mr2 = take(ts * nt * mm);
+  L.md02 = take(ts * nt * mm);
+  L.md12 = take(ts * nt * mm);
+  L.io = take(2 * sizeof(void*));
   for (const AmgLevel& lv : P.amgKp.lev)
     for (int i = 0; i < 6; ++i) L.kp_lev.push_back(take(ts * nt * lv.nrows));
   for (const AmgLevel& lv : P.amgFu.lev)
@@ -292,6 +295,7 @@ static int build_plan(Plan& P, std::string& err) {
     P.fu_deg = pick(pr.fu_solver, P.amgFu, red_fu);
     P.ca_deg = pick(pr.ca_solver, P.amgC0, red_ca);
   }
+  P.chunk = pr.sweep_chunk > 0 ? pr.sweep_chunk : std::max(4, (nt + 7) / 8);
   // Stencil forms of the sweep operators (structured grids, 5x5 neighbourhoods).
   P.use_stencil = (P.fu_deg > 0 || P.ca_deg > 0) && pr.sweep_format == 0 ? 1 : 0;
   // Each sweep step solves for the increment over a predictor from the earlier

@@ -55,6 +55,14 @@ struct DAmg {
   std::vector<void*> buf;
 };
 
+// One launch of a replayed program: a recorded op through its own kernel, or
+// one step of each sweep through k_sweep_pair; arguments by value.
+struct ReplayItem {
+  const void* fn = nullptr;
+  dim3 grid;
+  alignas(16) unsigned char args[832];
+};
+
 struct Handle {
   Plan* plan_copy = nullptr;   // scalars only (no big host arrays kept)
   Dims d;
@@ -73,12 +81,15 @@ struct Handle {
   int use_chain = 0;               // C_A sweep + M_j solves in single-workgroup chunk kernels
   double* host_small = nullptr;   // pinned
   double precond_ms = 0.0;
-  // Second stream: the C_A sweep runs on it, chunk by chunk, while the pressure
-  // part and the F_u sweep run on the caller's stream; events order the chunks.
-  hipStream_t s2 = nullptr;
-  hipEvent_t ev_fork = nullptr;
-  std::vector<hipEvent_t> ev_chunk;
   int chunk = 8;
+  // Recorded forward P_T^{-1}: its two programs replayed in lockstep (launch t
+  // runs the next op of each program whose dependency is met) from descriptors
+  // built once; the argument blocks live in the workspace, the input and
+  // output vectors are read from two device slots.
+  int pipeline = 0;
+  std::vector<ReplayItem> pt_items;
+  const double** rslot = nullptr;
+  double** zslot = nullptr;
 };
 
 }  // namespace st
@@ -349,8 +360,8 @@ inline int grid_for(int64_t n) {
 }
 
 inline void slab_sums_d(Ctx& c, const double* src, int64_t ld, int off, int len, const double* w, double* out,
-                        int nt, const int* jsel = nullptr, int64_t jstride = 0) {
-  SlabSumsDArgs a{src, ld, off, len, w, out, jsel, jstride};
+                        int nt, const double* const* rslot = nullptr) {
+  SlabSumsDArgs a{src, ld, off, len, w, out, rslot};
   emit(c, kKSlabSumsD, dim3(nt), &k_slab_sums_d, a);
 }
 
@@ -482,13 +493,17 @@ void sweep_step_stencil(Ctx& c, Handle& H, DAmg& a, const StencilOp& A, const St
 }
 
 // ================================================= P_T^{-1} (forward) ===
-// z = P_T^{-1} r.  With jsel, r and z are the bases of the Krylov blocks V, Z
-// and the column is *jsel (read on the device; batched solves).  Recording
-// (batched) runs everything on one stream in slab order: one chunk, no chain
-// kernel, no second stream.
+// z = P_T^{-1} r.  `c` receives the launches of program b and `ca` those of
+// program a: when not recording both are the caller's stream and everything
+// runs in the order written; when recording (Program: two op lists, the
+// b-ops carrying how many a-ops they wait for) a = the magnetic part up to
+// the C_A sweep (and the current solves when that balances the two better),
+// b = the pressure part, then per chunk of slabs the velocity right-hand side
+// and the F_u sweep, which wait for that chunk of the C_A sweep.  With slots,
+// r and z are read from device slots instead (recorded programs).
 template <class T>
-int precond_forward(Handle& H, const double* r, double* z, Ctx& c, const int* jsel = nullptr,
-                    int64_t jstride = 0) {
+int precond_forward(Handle& H, const double* r, double* z, Ctx& c, Ctx& ca, const double* const* rslot = nullptr,
+                    double* const* zslot = nullptr) {
   const Dims& d = H.d;
   const int nt = d.nt;
   char* B = H.base;
@@ -498,6 +513,7 @@ int precond_forward(Handle& H, const double* r, double* z, Ctx& c, const int* js
   T* rj = at<T>(B, L.rj); T* yj = at<T>(B, L.yj);
   T* ra = at<T>(B, L.ra); T* w = at<T>(B, L.wA); T* sA = at<T>(B, L.sA); T* yA = at<T>(B, L.yA);
   T* mr = at<T>(B, L.mr); T* md0 = at<T>(B, L.md0); T* md1 = at<T>(B, L.md1);
+  T* mr2 = at<T>(B, L.mr2); T* md02 = at<T>(B, L.md02); T* md12 = at<T>(B, L.md12);
   double* psum = at<double>(B, L.psum);
   const int o2 = d.off[2], o3 = d.off[3], o4 = d.off[4], ns = d.ns;
   const int nu = d.nu, np = d.np, nj = d.nj, na = d.na;
@@ -507,31 +523,53 @@ int precond_forward(Handle& H, const double* r, double* z, Ctx& c, const int* js
   // Q1 mass: eigenvalues of D^{-1} M lie in [1/4, 9/4] on squares; widened slightly.
   const double mlo = 0.24, mhi = 2.3, mth = 0.5 * (mhi + mlo), mde = 0.5 * (mhi - mlo);
   const bool rec = c.recording();
+  const bool chain = H.use_chain && !rec;
+  const int C = rec ? std::max(1, std::min(H.chunk, nt)) : nt;
+  const int nch = (nt + C - 1) / C;
+  // The current solves go with the shorter program (estimated launches).
+  const int ca_len = H.ca_deg > 0 ? H.ca_deg : 24, fu_len = H.fu_deg > 0 ? H.fu_deg : 24;
+  const bool mj_in_a = rec && nt * ca_len + nch * (mit + 1) <= nt * fu_len + 40;
+  // The pressure part runs in b-ops that wait only for the split.
+  auto mark = [&](Ctx& cx, int need) { cx.need = need; };
 
-  // 0. split r, projecting the pressure rows to zero sum per slab
-  slab_sums_d(c, r, int64_t(ns), o2, np, nullptr, psum, nt, jsel, jstride);
+  // 0. split r, projecting the pressure rows to zero sum per slab (program a)
+  slab_sums_d(ca, r, int64_t(ns), o2, np, nullptr, psum, nt, rslot);
   {
-    SplitArgs<T> a{r, ns, nt, o2, o3, o4, psum, ru, rp, rj, ra, jsel, jstride};
-    emit(c, kKSplit, dim3(grid_for(int64_t(ns) * nt)), &k_split<T>, a);
+    SplitArgs<T> a{r, ns, nt, o2, o3, o4, psum, ru, rp, rj, ra, rslot};
+    emit(ca, kKSplit, dim3(grid_for(int64_t(ns) * nt)), &k_split<T>, a);
   }
+  const int a_split = rec ? int(ca.rec->size()) : 0;
   // 1. magnetic Schur complement: w = M_A^{-1} r_A; s = F_A w (all slabs at once)
-  cheb_solve<T>(c, H.MA, nt, 0, 0, static_cast<const T*>(H.dMA), 0, nullptr, mth, mde, ra, w, mr, md0, md1, na, mit,
+  cheb_solve<T>(ca, H.MA, nt, 0, 0, static_cast<const T*>(H.dMA), 0, nullptr, mth, mde, ra, w, mr, md0, md1, na, mit,
                 0, false);
   {
     Seg<T> sg[2] = {seg<T>(H.FA, 0, 0, 1, w, na, 0, 0, nt, 1.0), seg<T>(H.FA, 1, 0, 0, w, na, -1, 1, nt, 1.0)};
-    spmv<T, T>(c, H.FA, nt, 2, sg, nullptr, na, 0.0, sA, na);
+    spmv<T, T>(ca, H.FA, nt, 2, sg, nullptr, na, 0.0, sA, na);
   }
-  // y_A = C_A^{-1} s: forward sweep, on the second stream one chunk of slabs at a time
-  const bool two = !rec && H.s2 != nullptr;
-  Ctx ca{two ? H.s2 : c.s, c.rec};
-  if (two) {
-    (void)hipEventRecord(H.ev_fork, c.s);
-    (void)hipStreamWaitEvent(ca.s, H.ev_fork, 0);
+  // 2. pressure (program b, alongside the C_A sweep): q = K_p^{-1} r_p; t = F_p q;
+  //    x_p = -M_p^{-1} t (xp holds M_p^{-1} t; the sign is applied where x_p is used)
+  mark(c, a_split);
+  amg_solve<T>(c, H.amgKp, nt, 0, 0, q, rp, vc);
+  {
+    Seg<T> sg[2] = {seg<T>(H.Fp, 0, 0, 1, q, np, 0, 0, nt, 1.0), seg<T>(H.Fp, 1, 0, 0, q, np, -1, 1, nt, 1.0)};
+    spmv<T, T>(c, H.Fp, nt, 2, sg, nullptr, np, 0.0, t, np);
   }
-  const bool chain = H.use_chain && !rec;
-  const int C = two ? std::max(1, H.chunk) : nt;
-  const int nch = (nt + C - 1) / C;
+  // the b-side mass solves use their own scratch: a-side ones may run alongside
+  cheb_solve<T>(c, H.Mp, nt, 0, 0, static_cast<const T*>(H.dMp), 0, nullptr, mth, mde, t, xp, mr2, md02, md12, np,
+                mit, 0, false);
+  // 3. y_A = C_A^{-1} s: forward sweep (program a), chunk by chunk; then per
+  //    chunk y_j = M_j^{-1}(r_j - K_jA y_A), g_u = r_u - Z_j y_j - Z_A y_A - B^T x_p
+  //    and x_u = F_u^{-1} g_u (forward sweep, program b)
+  std::vector<int> a_end(size_t(nch), 0);
+  auto current_solve = [&](Ctx& cx, int k0, int kc, T* r_, T* d0_, T* d1_) {
+    spmv1<T>(cx, H.KjA, kc, 0, 0, yA + int64_t(k0) * na, na, -1.0, rj + int64_t(k0) * nj, 1.0,
+             rj + int64_t(k0) * nj, nj);
+    cheb_solve<T>(cx, H.Mj, kc, 0, 0, static_cast<const T*>(H.dMj), 0, nullptr, mth, mde, rj + int64_t(k0) * nj,
+                  yj + int64_t(k0) * nj, r_ + int64_t(k0) * nj, d0_ + int64_t(k0) * nj, d1_ + int64_t(k0) * nj, nj,
+                  mit, 0, false);
+  };
   for (int ch = 0; ch < nch; ++ch) {
+    const int k0 = ch * C, k1 = std::min(nt, (ch + 1) * C);
     if (chain) {
       ChainArgs<T> cha;
       cha.C0 = st_op<T>(B, H.sC0);
@@ -539,8 +577,8 @@ int precond_forward(Handle& H, const double* r, double* z, Ctx& c, const int* js
       cha.CQ = st_op<T>(B, H.sCQ);
       cha.Mj = st_op<T>(B, H.sMj);
       cha.KjA = st_op<T>(B, H.sKjA);
-      cha.k0 = ch * C;
-      cha.k1 = std::min(nt, (ch + 1) * C);
+      cha.k0 = k0;
+      cha.k1 = k1;
       cha.deg = H.ca_deg;
       cha.mit = mit;
       cha.na = na;
@@ -560,10 +598,9 @@ int precond_forward(Handle& H, const double* r, double* z, Ctx& c, const int* js
       cha.d0 = at<T>(B, L.chd0);
       cha.d1 = at<T>(B, L.chd1);
       hipLaunchKernelGGL((k_ca_chain<T>), dim3(1), dim3(kChainBlock), 0, ca.s, cha);
-      if (two) (void)hipEventRecord(H.ev_chunk[ch], ca.s);
       continue;
     }
-    for (int k = ch * C; k < std::min(nt, (ch + 1) * C); ++k) {
+    for (int k = k0; k < k1; ++k) {
       if (H.use_stencil && H.ca_deg > 0) {
         // increment over the predictor y^0 (k = 1) or 2 y^{k-1} - y^{k-2} (k >= 2)
         sweep_step_stencil<T>(ca, H, H.amgC0, H.sC0, k >= 1 ? &H.sCP : nullptr, k, 1.0, yA + int64_t(k - 1) * na,
@@ -577,28 +614,13 @@ int precond_forward(Handle& H, const double* r, double* z, Ctx& c, const int* js
         sweep_step<T>(ca, H.amgC0, H.C1, nsg, sg, sA + int64_t(k) * na, yA + int64_t(k) * na, k, H.ca_deg, vc);
       }
     }
-    if (two) (void)hipEventRecord(H.ev_chunk[ch], ca.s);
+    if (mj_in_a) current_solve(ca, k0, k1 - k0, mr, md0, md1);
+    a_end[size_t(ch)] = rec ? int(ca.rec->size()) : 0;
   }
-  // 2. pressure (concurrently with the C_A sweep): q = K_p^{-1} r_p; t = F_p q;
-  //    x_p = -M_p^{-1} t (xp holds M_p^{-1} t; the sign is applied where x_p is used)
-  amg_solve<T>(c, H.amgKp, nt, 0, 0, q, rp, vc);
-  {
-    Seg<T> sg[2] = {seg<T>(H.Fp, 0, 0, 1, q, np, 0, 0, nt, 1.0), seg<T>(H.Fp, 1, 0, 0, q, np, -1, 1, nt, 1.0)};
-    spmv<T, T>(c, H.Fp, nt, 2, sg, nullptr, np, 0.0, t, np);
-  }
-  cheb_solve<T>(c, H.Mp, nt, 0, 0, static_cast<const T*>(H.dMp), 0, nullptr, mth, mde, t, xp, mr, md0, md1, np, mit,
-                0, false);
-  // 3. per chunk, once its y_A is ready: y_j = M_j^{-1}(r_j - K_jA y_A);
-  //    g_u = r_u - Z_j y_j - Z_A y_A - B^T x_p; x_u = F_u^{-1} g_u (forward sweep)
   for (int ch = 0; ch < nch; ++ch) {
     const int k0 = ch * C, kc = std::min(nt, (ch + 1) * C) - k0;
-    if (two) (void)hipStreamWaitEvent(c.s, H.ev_chunk[ch], 0);
-    if (!chain) {
-      spmv1<T>(c, H.KjA, kc, 0, 0, yA + int64_t(k0) * na, na, -1.0, rj + int64_t(k0) * nj, 1.0,
-               rj + int64_t(k0) * nj, nj);
-      cheb_solve<T>(c, H.Mj, kc, 0, 0, static_cast<const T*>(H.dMj), 0, nullptr, mth, mde, rj + int64_t(k0) * nj,
-                    yj + int64_t(k0) * nj, mr, md0, md1, nj, mit, 0, false);
-    }
+    mark(c, a_end[size_t(ch)]);
+    if (!chain && !mj_in_a) current_solve(c, k0, kc, mr2, md02, md12);
     {
       Seg<T> sg[3] = {seg<T>(H.Zj, 0, k0, 1, yj + int64_t(k0) * nj, nj, 0, 0, kc, -1.0),
                       seg<T>(H.Zj, 1, k0, 1, yA + int64_t(k0) * na, na, 0, 0, kc, -1.0),
@@ -619,9 +641,10 @@ int precond_forward(Handle& H, const double* r, double* z, Ctx& c, const int* js
     }
   }
   // 4. join with the pressure normalisation 1^T M_p p = 0
+  mark(c, rec ? int(ca.rec->size()) : 0);
   slab_sums_t<T>(c, xp, int64_t(np), np, H.mp_rowsum, psum + nt, nt);
   {
-    JoinArgs<T> a{z, ns, nt, o2, o3, o4, xu, xp, -1.0, psum + nt, H.msum, yj, yA, jsel, jstride};
+    JoinArgs<T> a{z, ns, nt, o2, o3, o4, xu, xp, -1.0, psum + nt, H.msum, yj, yA, zslot};
     emit(c, kKJoin, dim3(grid_for(int64_t(ns) * nt)), &k_join<T>, a);
   }
   return ST_OK;
@@ -650,7 +673,7 @@ int precond_transpose(Handle& H, const double* r, double* z, Ctx& c) {
 
   slab_sums_d(c, r, int64_t(ns), o2, np, nullptr, psum, nt);
   {
-    SplitArgs<T> a{r, ns, nt, o2, o3, o4, psum, ru, rp, rj, ra, nullptr, 0};
+    SplitArgs<T> a{r, ns, nt, o2, o3, o4, psum, ru, rp, rj, ra, nullptr};
     emit(c, kKSplit, dim3(grid_for(int64_t(ns) * nt)), &k_split<T>, a);
   }
   // x_u = F_u^{-T} r_u, backward in time: F_uk^T x^k = r^k + (1/dt) M_u x^{k+1}
@@ -707,20 +730,36 @@ int precond_transpose(Handle& H, const double* r, double* z, Ctx& c) {
                 0, false);
   slab_sums_t<T>(c, xp, int64_t(np), np, H.mp_rowsum, psum + nt, nt);
   {
-    JoinArgs<T> a{z, ns, nt, o2, o3, o4, xu, xp, -1.0, psum + nt, H.msum, yj, yA, nullptr, 0};
+    JoinArgs<T> a{z, ns, nt, o2, o3, o4, xu, xp, -1.0, psum + nt, H.msum, yj, yA, nullptr};
     emit(c, kKJoin, dim3(grid_for(int64_t(ns) * nt)), &k_join<T>, a);
   }
   return ST_OK;
 }
 
-int apply_precond(Handle& H, const double* r, double* z, Ctx& c, bool transpose, const int* jsel = nullptr,
-                  int64_t jstride = 0) {
-  int rc;
+// Records the forward P_T^{-1} as programs a and b reading r, z from the slots.
+int record_precond(Handle& H, Program& prog, const double* const* rslot, double* const* zslot) {
+  Ctx cb{nullptr, &prog.b, &prog.dep, 0};
+  Ctx ca{nullptr, &prog.a, nullptr, 0};
+  return H.fp32 ? precond_forward<float>(H, nullptr, nullptr, cb, ca, rslot, zslot)
+                : precond_forward<double>(H, nullptr, nullptr, cb, ca, rslot, zslot);
+}
+
+// Replay of the recorded forward P_T^{-1} on stream s.
+int replay_precond(Handle& H, const double* r, double* z, hipStream_t s) {
+  SetPtrsArgs sp{H.rslot, H.zslot, r, z};
+  hipLaunchKernelGGL(k_set_ptrs, dim3(1), dim3(kBlock), 0, s, sp);
+  for (ReplayItem& it : H.pt_items) {
+    void* params[] = {it.args};
+    (void)hipLaunchKernel(it.fn, it.grid, dim3(kBlock), params, 0, s);
+  }
+  return ST_OK;
+}
+
+int apply_precond(Handle& H, const double* r, double* z, Ctx& c, bool transpose) {
+  if (!transpose && H.pipeline && !c.recording()) return replay_precond(H, r, z, c.s);
   if (H.fp32)
-    rc = transpose ? precond_transpose<float>(H, r, z, c) : precond_forward<float>(H, r, z, c, jsel, jstride);
-  else
-    rc = transpose ? precond_transpose<double>(H, r, z, c) : precond_forward<double>(H, r, z, c, jsel, jstride);
-  return rc;
+    return transpose ? precond_transpose<float>(H, r, z, c) : precond_forward<float>(H, r, z, c, c);
+  return transpose ? precond_transpose<double>(H, r, z, c) : precond_forward<double>(H, r, z, c, c);
 }
 
 // y = alpha J x + beta b  (J or J^T), FP64
@@ -741,7 +780,8 @@ struct Krylov {
   int m = 0, ldh = 0;
   double *V = nullptr, *Z = nullptr, *w = nullptr, *bp = nullptr, *Hc = nullptr, *sm = nullptr;
   double *g = nullptr, *cs = nullptr, *sn = nullptr, *y = nullptr, *psum = nullptr, *partial = nullptr;
-  int* jsel = nullptr;
+  const double** rslot = nullptr;   // input/output slots of the recorded preconditioner
+  double** zslot = nullptr;
 };
 
 Krylov krylov(Handle& H, int m) {
@@ -763,7 +803,8 @@ Krylov krylov(Handle& H, int m) {
   K.y = K.sn + (m + 2);
   K.psum = at<double>(B, L.psum);
   K.partial = at<double>(B, L.partial);
-  K.jsel = at<int>(B, L.jsel);
+  K.rslot = at<const double*>(B, L.io);
+  K.zslot = at<double*>(B, L.io + sizeof(void*));
   return K;
 }
 
@@ -951,43 +992,61 @@ int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* 
   return status;
 }
 
-// ============================================================ batches ===
-// Lockstep FGMRES over several systems.  Each system's launches are recorded
-// once (the preconditioner with its Krylov column read from the device, one
-// Arnoldi tail per column j, the cycle head) and again per solve for the
-// launches that name the caller's b and x.  A batched phase runs launch t of
-// every member's program in one k_multi launch.
-struct ProgRef {
+// --------------------------------------------- lockstep scheduling ---
+// One member's launches in a phase: program a, program b (op i waits for
+// dep[i] a-ops), then b2 (after all of a).
+struct LockProg {
   const std::vector<Member>* a = nullptr;
   const std::vector<Member>* b = nullptr;
-  size_t size() const { return (a ? a->size() : 0) + (b ? b->size() : 0); }
-  const Member& at(size_t t) const { return (a && t < a->size()) ? (*a)[t] : (*b)[t - (a ? a->size() : 0)]; }
+  const std::vector<int>* dep = nullptr;
+  const std::vector<Member>* b2 = nullptr;
 };
 
-struct BatchSys {
-  Handle* H = nullptr;
-  Krylov K;
-  std::vector<Member> pt, head;
-  std::vector<std::vector<Member>> tail;   // per Krylov column j
-  std::vector<Member> init, resid, fin;    // per solve (b, x)
-  std::vector<std::vector<Member>> end;    // per solve, index mused - 1
-};
-
-struct Batch {
-  std::vector<BatchSys> sys;
-  int m = 30, fp32 = 0;
-  size_t out_off = 0, static_off = 0, static_bytes = 0, dyn_off = 0, dyn_bytes = 0, ws_bytes = 0;
-  char* base = nullptr;
-  double* out = nullptr;                 // device [nsys][4]: gathered sm[0..2]
-  double* host_out = nullptr;            // pinned
-  unsigned char* staging = nullptr;      // pinned, dyn_bytes
-  int64_t lock_launches = 0, sep_launches = 0;   // one Arnoldi step, lockstep vs one system at a time
-};
-
-inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+// Lockstep schedule: launch t takes, for every member, its next a-op and its
+// next b-op when that op's dependency was met by the a-ops of earlier
+// launches.  fn(args, blocks) receives each launch.
+template <class Fn>
+int lockstep(const std::vector<LockProg>& progs, Fn&& fn) {
+  const size_t n = progs.size();
+  if (2 * n > size_t(kMaxMembers)) return ST_EINVAL;
+  std::vector<size_t> ia(n, 0), ib(n, 0);
+  for (;;) {
+    MultiArgs a;
+    std::memset(&a, 0, sizeof(a));
+    int64_t total = 0;
+    bool left = false;
+    for (size_t i = 0; i < n; ++i) {
+      const LockProg& p = progs[i];
+      const size_t na = p.a ? p.a->size() : 0, nb1 = p.b ? p.b->size() : 0, nb2 = p.b2 ? p.b2->size() : 0;
+      const size_t done = ia[i];
+      if (ia[i] < na) {
+        a.m[a.nmem++] = (*p.a)[ia[i]++];
+        total += a.m[a.nmem - 1].blocks;
+      }
+      if (ib[i] < nb1 + nb2) {
+        const size_t need = ib[i] < nb1 ? (p.dep ? size_t((*p.dep)[ib[i]]) : 0) : na;
+        if (need > na) return ST_EINTERNAL;
+        if (need <= done) {
+          a.m[a.nmem++] = ib[i] < nb1 ? (*p.b)[ib[i]] : (*p.b2)[ib[i] - nb1];
+          total += a.m[a.nmem - 1].blocks;
+          ++ib[i];
+        }
+      }
+      if (ia[i] < na || ib[i] < nb1 + nb2) left = true;
+    }
+    if (a.nmem == 0) {
+      if (!left) return ST_OK;
+      continue;   // only waiting b-ops: the a-op of this member ran in the previous launch
+    }
+    if (total > int64_t(0x7fffffff)) return ST_EINTERNAL;
+    fn(a, unsigned(total));
+  }
+}
 
 // Appends the argument blocks of `ops` to `pool` (the host image of a device
 // region starting at dev) and returns their launch descriptors.
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
 std::vector<Member> place(const std::vector<Op>& ops, std::vector<unsigned char>& pool, const unsigned char* dev) {
   std::vector<Member> out;
   out.reserve(ops.size());
@@ -1006,33 +1065,149 @@ std::vector<Member> place(const std::vector<Op>& ops, std::vector<unsigned char>
   return out;
 }
 
+// Builds the replay of a handle's recorded forward P_T^{-1} (st_create):
+// launch t runs the next op of program a and the next op of program b whose
+// dependency the earlier launches met; two ops with a paired kernel (sweep
+// steps, SELL Chebyshev steps and SELL products) share one k_two launch,
+// anything else runs through its own kernel.
+template <class T, class X, class Y>
+bool try_pair(const Op& x, const Op& y, ReplayItem& it) {
+  if (x.kind != X::kind || y.kind != Y::kind) return false;
+  static_assert(sizeof(TwoArgs<X, Y>) <= sizeof(ReplayItem::args), "paired arguments exceed a replay item");
+  TwoArgs<X, Y> p;
+  std::memset(&p, 0, sizeof(p));
+  std::memcpy(&p.x, x.args, sizeof(p.x));
+  std::memcpy(&p.y, y.args, sizeof(p.y));
+  p.xblocks = x.gx * x.gy;
+  p.xgx = x.gx;
+  p.ygx = y.gx;
+  it.fn = reinterpret_cast<const void*>(&k_two<X, Y>);
+  it.grid = dim3(unsigned(p.xblocks + y.gx * y.gy));
+  std::memset(it.args, 0, sizeof(it.args));
+  std::memcpy(it.args, &p, sizeof(p));
+  return true;
+}
+
+template <class T, class X>
+bool try_pair_x(const Op& x, const Op& y, ReplayItem& it) {
+  return try_pair<T, X, BodyStInit<T>>(x, y, it) || try_pair<T, X, BodyStCheb<T>>(x, y, it) ||
+         try_pair<T, X, BodyCheb<T>>(x, y, it) || try_pair<T, X, BodySpmv<T>>(x, y, it);
+}
+
+template <class T>
+bool pair_ops(const Op& x, const Op& y, ReplayItem& it) {
+  return try_pair_x<T, BodyStInit<T>>(x, y, it) || try_pair_x<T, BodyStCheb<T>>(x, y, it) ||
+         try_pair_x<T, BodyCheb<T>>(x, y, it) || try_pair_x<T, BodySpmv<T>>(x, y, it);
+}
+
+template <class T>
+int build_items(Handle& H, const Program& prog) {
+  auto single = [&](const Op& op) {
+    ReplayItem it;
+    it.fn = op.fn;
+    it.grid = dim3(unsigned(op.gx), unsigned(op.gy));
+    std::memset(it.args, 0, sizeof(it.args));
+    std::memcpy(it.args, op.args, size_t(op.size));
+    H.pt_items.push_back(it);
+  };
+  const size_t na = prog.a.size(), nb = prog.b.size();
+  size_t ia = 0, ib = 0;
+  while (ia < na || ib < nb) {
+    const size_t done = ia;
+    const Op* x = ia < na ? &prog.a[ia++] : nullptr;
+    const Op* y = nullptr;
+    if (ib < nb) {
+      if (size_t(prog.dep[ib]) > na) return ST_EINTERNAL;
+      if (size_t(prog.dep[ib]) <= done) y = &prog.b[ib++];
+    }
+    if (!x && !y) return ST_EINTERNAL;
+    ReplayItem it;
+    if (x && y && pair_ops<T>(*x, *y, it)) {
+      H.pt_items.push_back(it);
+      continue;
+    }
+    if (x) single(*x);
+    if (y) single(*y);
+  }
+  return ST_OK;
+}
+
+int build_pipeline(Handle& H) {
+  H.rslot = at<const double*>(H.base, H.L.io);
+  H.zslot = at<double*>(H.base, H.L.io + sizeof(void*));
+  Program prog;
+  int rc = record_precond(H, prog, H.rslot, H.zslot);
+  if (rc) return rc;
+  H.pt_items.clear();
+  rc = H.fp32 ? build_items<float>(H, prog) : build_items<double>(H, prog);
+  if (rc) return rc;
+  H.pipeline = 1;
+  return ST_OK;
+}
+
+// ============================================================ batches ===
+// Lockstep FGMRES over several systems.  Each system's launches are recorded
+// once (the preconditioner as its two programs reading the Krylov column
+// from the handle's slots, one Arnoldi tail per column j that also points the
+// slots at the next column, the cycle head) and again per solve for the
+// launches that name the caller's b and x.  A batched phase runs the lockstep
+// schedule of every member's programs in k_multi launches.
+struct BatchSys {
+  Handle* H = nullptr;
+  Krylov K;
+  std::vector<Member> pa, pb, head;
+  std::vector<int> pdep;
+  std::vector<std::vector<Member>> tail;   // per Krylov column j
+  std::vector<Member> init, resid, fin;    // per solve (b, x)
+  std::vector<std::vector<Member>> end;    // per solve, index mused - 1
+};
+
+struct Batch {
+  std::vector<BatchSys> sys;
+  int m = 30, fp32 = 0;
+  size_t out_off = 0, static_off = 0, static_bytes = 0, dyn_off = 0, dyn_bytes = 0, ws_bytes = 0;
+  char* base = nullptr;
+  double* out = nullptr;                 // device [nsys][4]: gathered sm[0..2]
+  double* host_out = nullptr;            // pinned
+  unsigned char* staging = nullptr;      // pinned, dyn_bytes
+  int64_t lock_launches = 0, sep_launches = 0;   // one Arnoldi step, lockstep vs one system at a time
+};
+
 // Static programs of every member; dev = device address of the static pool (null: sizing only).
-void record_static(Batch& Bt, std::vector<unsigned char>& pool, const unsigned char* dev) {
+int record_static(Batch& Bt, std::vector<unsigned char>& pool, const unsigned char* dev) {
   pool.clear();
   for (size_t s = 0; s < Bt.sys.size(); ++s) {
     BatchSys& S = Bt.sys[s];
     Handle& H = *S.H;
     S.K = krylov(H, Bt.m);
     const Krylov& K = S.K;
+    Program prog;
+    int rc = record_precond(H, prog, K.rslot, K.zslot);
+    if (rc) return rc;
+    S.pa = place(prog.a, pool, dev);
+    S.pb = place(prog.b, pool, dev);
+    S.pdep = prog.dep;
     std::vector<Op> ops;
     Ctx c{nullptr, &ops};
-    apply_precond(H, K.V, K.Z, c, false, K.jsel, K.N);
-    S.pt = place(ops, pool, dev);
-    ops.clear();
     emit_cycle_head(c, K);
-    CopySmallArgs cs0{K.sm, nullptr, 0, K.jsel, 0};
-    emit(c, kKCopySmall, dim3(1), &k_copy_small, cs0);
+    SetPtrsArgs sp0{K.rslot, K.zslot, K.V, K.Z};
+    emit(c, kKSetPtrs, dim3(1), &k_set_ptrs, sp0);
     S.head = place(ops, pool, dev);
     S.tail.assign(size_t(Bt.m), {});
     for (int j = 0; j < Bt.m; ++j) {
       ops.clear();
       apply_J(H, K.Z + int64_t(j) * K.N, K.w, c, false, 1.0, nullptr);
       emit_arnoldi(c, K, j);
-      CopySmallArgs cs{K.sm, Bt.out + 4 * s, 3, K.jsel, j + 1};
+      CopySmallArgs cs{K.sm, Bt.out + 4 * s, 3};
       emit(c, kKCopySmall, dim3(1), &k_copy_small, cs);
+      if (j + 1 < Bt.m) {
+        SetPtrsArgs sp{K.rslot, K.zslot, K.V + int64_t(j + 1) * K.N, K.Z + int64_t(j + 1) * K.N};
+        emit(c, kKSetPtrs, dim3(1), &k_set_ptrs, sp);
+      }
       S.tail[size_t(j)] = place(ops, pool, dev);
     }
   }
+  return ST_OK;
 }
 
 // Per-solve programs (they name b and x); dev = device address of the dynamic pool.
@@ -1048,7 +1223,7 @@ void record_dynamic(Batch& Bt, std::vector<unsigned char>& pool, const unsigned 
     std::vector<Op> ops;
     Ctx c{nullptr, &ops};
     emit_fgmres_init(c, H, K, bs, xs, zero_x);
-    CopySmallArgs g0{K.sm, Bt.out + 4 * s, 3, nullptr, 0};
+    CopySmallArgs g0{K.sm, Bt.out + 4 * s, 3};
     emit(c, kKCopySmall, dim3(1), &k_copy_small, g0);
     S.init = place(ops, pool, dev);
     ops.clear();
@@ -1070,26 +1245,15 @@ void record_dynamic(Batch& Bt, std::vector<unsigned char>& pool, const unsigned 
 }
 
 template <class T>
-int run_phase(const std::vector<ProgRef>& progs, hipStream_t s) {
-  size_t len = 0;
-  for (const ProgRef& p : progs) len = std::max(len, p.size());
-  for (size_t t = 0; t < len; ++t) {
-    MultiArgs a;
-    std::memset(&a, 0, sizeof(a));
-    int64_t total = 0;
-    for (const ProgRef& p : progs) {
-      if (t >= p.size()) continue;
-      a.m[a.nmem++] = p.at(t);
-      total += p.at(t).blocks;
-    }
-    if (a.nmem == 0 || total <= 0) continue;
-    if (total > int64_t(0x7fffffff)) return ST_EINTERNAL;
-    hipLaunchKernelGGL((k_multi<T>), dim3(unsigned(total)), dim3(kBlock), 0, s, a);
-  }
+int run_phase(const std::vector<LockProg>& progs, hipStream_t s) {
+  const int rc = lockstep(progs, [&](const MultiArgs& a, unsigned blocks) {
+    hipLaunchKernelGGL((k_multi<T>), dim3(blocks), dim3(kBlock), 0, s, a);
+  });
+  if (rc) return rc;
   return hipGetLastError() == hipSuccess ? ST_OK : ST_EHIP;
 }
 
-int run_phase_any(const Batch& Bt, const std::vector<ProgRef>& progs, hipStream_t s) {
+int run_phase_any(const Batch& Bt, const std::vector<LockProg>& progs, hipStream_t s) {
   return Bt.fp32 ? run_phase<float>(progs, s) : run_phase<double>(progs, s);
 }
 
@@ -1115,8 +1279,8 @@ int batch_solve(Batch& Bt, const double* const* b, double* const* x, const st_op
   };
   std::vector<double> bnorm(ns, 0.0), tol(ns, 0.0), true_res(ns, 0.0);
   std::vector<int> its(ns, 0), status(ns, ST_ENOTCONV), restarts(ns, 0), done(ns, 0), mused(ns, 0);
-  std::vector<ProgRef> progs;
-  for (int i = 0; i < ns; ++i) progs.push_back(ProgRef{&Bt.sys[i].init, nullptr});
+  std::vector<LockProg> progs;
+  for (int i = 0; i < ns; ++i) progs.push_back(LockProg{nullptr, &Bt.sys[i].init});
   int rc = run_phase_any(Bt, progs, s);
   if (!rc) rc = fetch();
   if (rc) return rc;
@@ -1140,7 +1304,7 @@ int batch_solve(Batch& Bt, const double* const* b, double* const* x, const st_op
   std::vector<int> finalize;
   while (!active.empty()) {
     progs.clear();
-    for (int i : active) progs.push_back(ProgRef{&Bt.sys[i].resid, nullptr});
+    for (int i : active) progs.push_back(LockProg{nullptr, &Bt.sys[i].resid});
     rc = run_phase_any(Bt, progs, s);
     if (!rc) rc = fetch();
     if (rc) return rc;
@@ -1168,14 +1332,17 @@ int batch_solve(Batch& Bt, const double* const* b, double* const* x, const st_op
     active = cyc;
     if (active.empty()) break;
     progs.clear();
-    for (int i : cyc) progs.push_back(ProgRef{&Bt.sys[i].head, nullptr});
+    for (int i : cyc) progs.push_back(LockProg{nullptr, &Bt.sys[i].head});
     rc = run_phase_any(Bt, progs, s);
     if (rc) return rc;
     for (int i : cyc) mused[i] = 0;
     std::vector<int> inner = cyc;
     for (int j = 0; j < m && !inner.empty(); ++j) {
       progs.clear();
-      for (int i : inner) progs.push_back(ProgRef{&Bt.sys[i].pt, &Bt.sys[i].tail[size_t(j)]});
+      for (int i : inner) {
+        BatchSys& S = Bt.sys[size_t(i)];
+        progs.push_back(LockProg{&S.pa, &S.pb, &S.pdep, &S.tail[size_t(j)]});
+      }
       rc = run_phase_any(Bt, progs, s);
       if (!rc) rc = fetch();
       if (rc) return rc;
@@ -1200,7 +1367,7 @@ int batch_solve(Batch& Bt, const double* const* b, double* const* x, const st_op
     progs.clear();
     for (int i : cyc) {
       if (done[i]) continue;
-      progs.push_back(ProgRef{&Bt.sys[i].end[size_t(mused[i] - 1)], nullptr});
+      progs.push_back(LockProg{nullptr, &Bt.sys[i].end[size_t(mused[i] - 1)]});
       restarts[i]++;
       cont.push_back(i);
     }
@@ -1209,7 +1376,7 @@ int batch_solve(Batch& Bt, const double* const* b, double* const* x, const st_op
     active = cont;
   }
   progs.clear();
-  for (int i : finalize) progs.push_back(ProgRef{&Bt.sys[i].fin, nullptr});
+  for (int i : finalize) progs.push_back(LockProg{nullptr, &Bt.sys[i].fin});
   rc = run_phase_any(Bt, progs, s);
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(s));
@@ -1347,19 +1514,20 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
     delete hh;
     return ST_EHIP;
   }
-  // The second stream (default priority) and the chunk events of the pipelined sweeps.
-  // About 16 chunks: the F_u sweep of a chunk starts as soon as its C_A part is done.
-  H.chunk = P.prob.sweep_chunk > 0 ? P.prob.sweep_chunk : std::max(4, (H.d.nt + 15) / 16);
-  if (H.d.nt > 1 && P.prob.single_stream == 0) {
-    const int nch = (H.d.nt + H.chunk - 1) / H.chunk;
-    bool ok = hipStreamCreateWithFlags(&H.s2, hipStreamNonBlocking) == hipSuccess &&
-              hipEventCreateWithFlags(&H.ev_fork, hipEventDisableTiming) == hipSuccess;
-    H.ev_chunk.assign(nch, nullptr);
-    for (int c = 0; ok && c < nch; ++c)
-      ok = hipEventCreateWithFlags(&H.ev_chunk[c], hipEventDisableTiming) == hipSuccess;
-    if (!ok) {
-      std::fprintf(stderr, "libst: second stream unavailable, sweeps run on one stream\n");
-      H.s2 = nullptr;
+  // About 16 chunks of slabs: the F_u sweep of a chunk starts as soon as its
+  // part of the C_A sweep is done.
+  H.chunk = P.chunk;
+  if (P.prob.single_stream == 0) {
+    int rc = ST_OK;
+    try {
+      rc = build_pipeline(H);
+    } catch (...) {
+      rc = ST_ENOMEM;
+    }
+    if (rc) {
+      (void)hipHostFree(H.host_small);
+      delete hh;
+      return rc;
     }
   }
   *out = hh;
@@ -1369,11 +1537,6 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
 int st_destroy(st_handle* h) {
   if (!h) return ST_OK;
   if (h->h.host_small) (void)hipHostFree(h->h.host_small);
-  if (h->h.s2) (void)hipStreamSynchronize(h->h.s2);
-  for (hipEvent_t e : h->h.ev_chunk)
-    if (e) (void)hipEventDestroy(e);
-  if (h->h.ev_fork) (void)hipEventDestroy(h->h.ev_fork);
-  if (h->h.s2) (void)hipStreamDestroy(h->h.s2);
   delete h;
   return ST_OK;
 }
@@ -1456,7 +1619,11 @@ int st_batch_create(st_handle* const* hs, int nsys, int restart, st_batch** out)
     for (int i = 0; i < nsys; ++i) B.sys[size_t(i)].H = &hs[i]->h;
     // sizes: the programs have the same shape whatever the addresses
     std::vector<unsigned char> pool;
-    record_static(B, pool, nullptr);
+    const int rc = record_static(B, pool, nullptr);
+    if (rc) {
+      delete bb;
+      return rc;
+    }
     B.static_bytes = pool.size();
     std::vector<double*> fake(size_t(nsys), nullptr);
     record_dynamic(B, pool, nullptr, fake.data(), fake.data(), true);
@@ -1465,15 +1632,20 @@ int st_batch_create(st_handle* const* hs, int nsys, int restart, st_batch** out)
     B.static_off = align_up(sizeof(double) * 4 * size_t(nsys), 256);
     B.dyn_off = align_up(B.static_off + B.static_bytes, 256);
     B.ws_bytes = align_up(B.dyn_off + B.dyn_bytes, 256);
-    // launches of one Arnoldi step (preconditioner + J + Gram-Schmidt), lockstep vs separate
-    size_t mx = 0, sum = 0;
-    for (const BatchSys& S : B.sys) {
-      const size_t len = S.pt.size() + S.tail[0].size();
-      mx = std::max(mx, len);
-      sum += len;
+    // launches of one Arnoldi step (preconditioner + J + Gram-Schmidt), all
+    // members in lockstep vs each member alone
+    auto count = [](const std::vector<LockProg>& progs) {
+      int64_t n = 0;
+      (void)lockstep(progs, [&](const MultiArgs&, unsigned) { ++n; });
+      return n;
+    };
+    std::vector<LockProg> all;
+    B.sep_launches = 0;
+    for (BatchSys& S : B.sys) {
+      all.push_back(LockProg{&S.pa, &S.pb, &S.pdep, &S.tail[0]});
+      B.sep_launches += count({all.back()});
     }
-    B.lock_launches = int64_t(mx);
-    B.sep_launches = int64_t(sum);
+    B.lock_launches = count(all);
   } catch (...) {
     delete bb;
     return ST_ENOMEM;
@@ -1506,8 +1678,9 @@ int st_batch_upload(st_batch* b, void* ws, size_t ws_bytes, void* stream) {
     B.base = static_cast<char*>(ws);
     B.out = reinterpret_cast<double*>(B.base + B.out_off);
     std::vector<unsigned char> pool;
-    record_static(B, pool, reinterpret_cast<unsigned char*>(B.base + B.static_off));
-    if (pool.size() != B.static_bytes) return ST_EINTERNAL;
+    if (record_static(B, pool, reinterpret_cast<unsigned char*>(B.base + B.static_off)) != ST_OK ||
+        pool.size() != B.static_bytes)
+      return ST_EINTERNAL;
     if (!B.host_out &&
         hipHostMalloc(reinterpret_cast<void**>(&B.host_out), sizeof(double) * 4 * B.sys.size(),
                       hipHostMallocDefault) != hipSuccess)

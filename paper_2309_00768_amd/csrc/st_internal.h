@@ -192,6 +192,7 @@ struct Plan {
   int fp32 = 0;
   int inner_iters = 40, mass_iters = 12, max_restart = 30, exact = 0;
   int fu_deg = 0, ca_deg = 0;     // > 0: Chebyshev alone of this degree; 0: AMG V-cycle
+  int chunk = 8;                  // slabs per chunk of the C_A / F_u sweep pipeline
   // J and J^T (FP64): segment 0 per-slab values, 1 shared, 2 previous/next slab coupling.
   SellGroup J, JT;
   // P_T pieces (precision per fp32).
@@ -219,11 +220,13 @@ struct WsLayout {
   size_t V = 0, Z = 0, w = 0, r = 0, hess = 0, small = 0, partial = 0, psum = 0;
   size_t ru = 0, yu = 0, xu = 0, rp = 0, q = 0, t = 0, xp = 0, rj = 0, yj = 0;
   size_t ra = 0, wA = 0, sA = 0, yA = 0, mr = 0, md0 = 0, md1 = 0, chr = 0, chd0 = 0, chd1 = 0;
-  size_t jsel = 0;                              // int: Krylov column of a batched P_T apply
+  size_t mr2 = 0, md02 = 0, md12 = 0;           // mass-solve scratch of the second program
+  size_t io = 0;                                // 2 pointers: input/output slots of a recorded P_T
   std::vector<size_t> kp_lev, fu_lev, ca_lev;   // 6 vectors per level each
   size_t end = 0;
 };
 constexpr int kPartialBlocks = 1024;   // blocks of the two-stage reductions
+constexpr int kOpArgBytes = 448;       // largest argument block of a recorded launch
 WsLayout workspace_layout(const Plan& p);
 
 }  // namespace st
