@@ -50,6 +50,9 @@ enum Kind : int {
   kKNumKinds
 };
 
+constexpr int kMaxMembers = 64;   // two programs per system, 32 systems
+constexpr int kMaxMembersG = 64;  // members of one grouped launch
+
 // One recorded launch: its kernel (for a replay through the same kernel),
 // the body kind (for a batched launch), grid and argument block.
 struct Op {
@@ -144,8 +147,179 @@ __global__ ST_LATENCY_KERNEL void k_two(TwoArgs<X, Y> p) {
   else Y::run(p.y, b - p.xblocks, p.ygx);
 }
 
+// -------------------------------------------------------- grouped launches ---
+// Body of kind K in precision T with its argument type; b is the workgroup
+// index within the op's own grid of gx columns.  A grouped launch runs ops of
+// one kind (k_group) or of two pairable kinds (k_group2) for several systems,
+// their argument blocks read from device memory.
+template <int K, class T> struct KB;
+template <class T> struct KB<kKSpmvJ, T> {
+  using Args = SpmvArgs<double, double>;
+  __device__ static void run(const Args& a, int b, int gx) { spmv_body<double, double, double>(a, b % gx, b / gx); }
+};
+template <class T> struct KB<kKSpmvT, T> {
+  using Args = SpmvArgs<T, T>;
+  __device__ static void run(const Args& a, int b, int gx) { spmv_body<T, T, T>(a, b % gx, b / gx); }
+};
+template <class T> struct KB<kKCheb, T> {
+  using Args = ChebArgs<T>;
+  __device__ static void run(const Args& a, int b, int gx) { cheb_body<T>(a, b % gx, b / gx); }
+};
+template <class T> struct KB<kKStInit, T> {
+  using Args = StInitArgs<T>;
+  __device__ static void run(const Args& a, int b, int) { st_init_body<T>(a, b); }
+};
+template <class T> struct KB<kKStCheb, T> {
+  using Args = StChebArgs<T>;
+  __device__ static void run(const Args& a, int b, int) { st_cheb_body<T>(a, b); }
+};
+template <class T> struct KB<kKCoarse, T> {
+  using Args = CoarseArgs<T>;
+  __device__ static void run(const Args& a, int b, int) { coarse_body<T>(a, b); }
+};
+template <class T> struct KB<kKSlabSumsD, T> {
+  using Args = SlabSumsDArgs;
+  __device__ static void run(const Args& a, int b, int) { slab_sums_d_body(a, b); }
+};
+template <class T> struct KB<kKSlabSumsT, T> {
+  using Args = SlabSumsTArgs<T>;
+  __device__ static void run(const Args& a, int b, int) { slab_sums_t_body<T>(a, b); }
+};
+template <class T> struct KB<kKSplit, T> {
+  using Args = SplitArgs<T>;
+  __device__ static void run(const Args& a, int b, int gx) { split_body<T>(a, b, gx); }
+};
+template <class T> struct KB<kKJoin, T> {
+  using Args = JoinArgs<T>;
+  __device__ static void run(const Args& a, int b, int gx) { join_body<T>(a, b, gx); }
+};
+template <class T> struct KB<kKSlabShiftD, T> {
+  using Args = SlabShiftArgs<double>;
+  __device__ static void run(const Args& a, int b, int gx) { slab_shift_body<double>(a, b, gx); }
+};
+template <class T> struct KB<kKSlabShiftT, T> {
+  using Args = SlabShiftArgs<T>;
+  __device__ static void run(const Args& a, int b, int gx) { slab_shift_body<T>(a, b, gx); }
+};
+template <class T> struct KB<kKProjectP, T> {
+  using Args = ProjectPArgs;
+  __device__ static void run(const Args& a, int b, int gx) { project_p_body(a, b, gx); }
+};
+template <class T> struct KB<kKMdot, T> {
+  using Args = MdotArgs;
+  __device__ static void run(const Args& a, int b, int gx) { mdot_body(a, b % gx, b / gx, gx); }
+};
+template <class T> struct KB<kKReduce, T> {
+  using Args = ReduceArgs;
+  __device__ static void run(const Args& a, int b, int) { reduce_body(a, b); }
+};
+template <class T> struct KB<kKCombine, T> {
+  using Args = CombineArgs;
+  __device__ static void run(const Args& a, int b, int gx) { combine_body(a, b, gx); }
+};
+template <class T> struct KB<kKScale, T> {
+  using Args = ScaleArgs;
+  __device__ static void run(const Args& a, int b, int gx) { scale_body(a, b, gx); }
+};
+template <class T> struct KB<kKGivens, T> {
+  using Args = GivensArgs;
+  __device__ static void run(const Args& a, int, int) { givens_body(a); }
+};
+template <class T> struct KB<kKTrisolve, T> {
+  using Args = TrisolveArgs;
+  __device__ static void run(const Args& a, int, int) { trisolve_body(a); }
+};
+template <class T> struct KB<kKInitG, T> {
+  using Args = InitGArgs;
+  __device__ static void run(const Args& a, int, int) { init_g_body(a); }
+};
+template <class T> struct KB<kKFill, T> {
+  using Args = FillArgs;
+  __device__ static void run(const Args& a, int b, int gx) { fill_body(a, b, gx); }
+};
+template <class T> struct KB<kKCopySmall, T> {
+  using Args = CopySmallArgs;
+  __device__ static void run(const Args& a, int, int) { copy_small_body(a); }
+};
+template <class T> struct KB<kKSetPtrs, T> {
+  using Args = SetPtrsArgs;
+  __device__ static void run(const Args& a, int, int) { set_ptrs_body(a); }
+};
+
+struct GroupMember {
+  const unsigned char* args;   // device copy of the op's argument block
+  int blocks;                  // gx * gy
+  int gx;
+  int second;                  // k_group2: 1 = the second body
+  int pad;
+};
+
+struct GroupArgs {
+  int n;
+  int pad;
+  GroupMember m[kMaxMembersG];
+};
+
+// Finds the member of workgroup blockIdx.x: returns its index and the block
+// within it (static member indices only, so the table stays in kernel arguments).
+__device__ inline int group_member(const GroupArgs& g, int& rem) {
+  rem = blockIdx.x;
+  int sel = -1;
+#pragma unroll
+  for (int i = 0; i < kMaxMembersG; ++i) {
+    if (sel < 0 && i < g.n) {
+      if (rem < g.m[i].blocks) sel = i;
+      else rem -= g.m[i].blocks;
+    }
+  }
+  return sel;
+}
+
+template <int K, class T>
+__global__ ST_LATENCY_KERNEL void k_group(GroupArgs g) {
+  int rem = 0;
+  const int sel = group_member(g, rem);
+  if (sel < 0) return;
+  const unsigned char* p = nullptr;
+  int gx = 1;
+#pragma unroll
+  for (int i = 0; i < kMaxMembersG; ++i)
+    if (i == sel) {
+      p = g.m[i].args;
+      gx = g.m[i].gx;
+    }
+  using A = typename KB<K, T>::Args;
+  const A a = *reinterpret_cast<const A* __restrict__>(p);
+  KB<K, T>::run(a, rem, gx);
+}
+
+template <int K1, int K2, class T>
+__global__ ST_LATENCY_KERNEL void k_group2(GroupArgs g) {
+  int rem = 0;
+  const int sel = group_member(g, rem);
+  if (sel < 0) return;
+  const unsigned char* p = nullptr;
+  int gx = 1, second = 0;
+#pragma unroll
+  for (int i = 0; i < kMaxMembersG; ++i)
+    if (i == sel) {
+      p = g.m[i].args;
+      gx = g.m[i].gx;
+      second = g.m[i].second;
+    }
+  if (second) {
+    using A = typename KB<K2, T>::Args;
+    const A a = *reinterpret_cast<const A* __restrict__>(p);
+    KB<K2, T>::run(a, rem, gx);
+  } else {
+    using A = typename KB<K1, T>::Args;
+    const A a = *reinterpret_cast<const A* __restrict__>(p);
+    KB<K1, T>::run(a, rem, gx);
+  }
+}
+
 // ----------------------------------------------------- batched launches ---
-constexpr int kMaxMembers = 64;   // two programs per system, 32 systems
+
 
 struct Member {
   const unsigned char* args;   // device copy of the op's argument block

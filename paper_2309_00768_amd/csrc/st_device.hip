@@ -15,6 +15,7 @@
 #include <cstring>
 #include <new>
 #include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "kernels.h"
@@ -1244,11 +1245,82 @@ void record_dynamic(Batch& Bt, std::vector<unsigned char>& pool, const unsigned 
   }
 }
 
+// Grouped launches of one lockstep step: the ops are grouped by kind; two
+// groups of pairable kinds share one k_group2 launch, every other group runs
+// as one k_group launch of its kind.
+template <class T, int... K>
+void group_kernels(std::vector<const void*>& out, std::integer_sequence<int, K...>) {
+  out = {reinterpret_cast<const void*>(&k_group<K, T>)...};
+}
+
+template <class T>
+const void* group_kernel(int kind) {
+  static std::vector<const void*> table;
+  if (table.empty()) group_kernels<T>(table, std::make_integer_sequence<int, kKNumKinds>{});
+  return table[size_t(kind)];
+}
+
+constexpr int kPairable[4] = {kKStInit, kKStCheb, kKCheb, kKSpmvT};
+
+template <class T, int I, int J>
+const void* group2_entry() {
+  return reinterpret_cast<const void*>(&k_group2<kPairable[I], kPairable[J], T>);
+}
+
+template <class T>
+const void* group2_kernel(int i, int j) {   // i < j: indices into kPairable
+  static const void* table[4][4] = {
+      {nullptr, group2_entry<T, 0, 1>(), group2_entry<T, 0, 2>(), group2_entry<T, 0, 3>()},
+      {nullptr, nullptr, group2_entry<T, 1, 2>(), group2_entry<T, 1, 3>()},
+      {nullptr, nullptr, nullptr, group2_entry<T, 2, 3>()},
+      {nullptr, nullptr, nullptr, nullptr}};
+  return table[i][j];
+}
+
+inline int pairable_index(int kind) {
+  for (int i = 0; i < 4; ++i)
+    if (kPairable[i] == kind) return i;
+  return -1;
+}
+
+template <class T>
+void launch_groups(const MultiArgs& step, hipStream_t s) {
+  int kinds[kKNumKinds];
+  int nk = 0;
+  for (int i = 0; i < step.nmem; ++i) {
+    bool seen = false;
+    for (int k = 0; k < nk; ++k) seen = seen || kinds[k] == step.m[i].kind;
+    if (!seen) kinds[nk++] = step.m[i].kind;
+  }
+  auto launch = [&](const void* fn, int k1, int k2) {
+    GroupArgs g;
+    std::memset(&g, 0, sizeof(g));
+    int64_t total = 0;
+    for (int i = 0; i < step.nmem; ++i) {
+      const Member& m = step.m[i];
+      if (m.kind != k1 && m.kind != k2) continue;
+      GroupMember& gm = g.m[g.n++];
+      gm.args = m.args;
+      gm.blocks = m.blocks;
+      gm.gx = m.gx;
+      gm.second = m.kind == k2 && k2 != k1 ? 1 : 0;
+      total += m.blocks;
+    }
+    void* params[] = {&g};
+    (void)hipLaunchKernel(fn, dim3(unsigned(total)), dim3(kBlock), params, 0, s);
+  };
+  if (nk == 2 && pairable_index(kinds[0]) >= 0 && pairable_index(kinds[1]) >= 0) {
+    int a = pairable_index(kinds[0]), b = pairable_index(kinds[1]);
+    if (a > b) std::swap(a, b);
+    launch(group2_kernel<T>(a, b), kPairable[a], kPairable[b]);
+    return;
+  }
+  for (int k = 0; k < nk; ++k) launch(group_kernel<T>(kinds[k]), kinds[k], kinds[k]);
+}
+
 template <class T>
 int run_phase(const std::vector<LockProg>& progs, hipStream_t s) {
-  const int rc = lockstep(progs, [&](const MultiArgs& a, unsigned blocks) {
-    hipLaunchKernelGGL((k_multi<T>), dim3(blocks), dim3(kBlock), 0, s, a);
-  });
+  const int rc = lockstep(progs, [&](const MultiArgs& a, unsigned) { launch_groups<T>(a, s); });
   if (rc) return rc;
   return hipGetLastError() == hipSuccess ? ST_OK : ST_EHIP;
 }
