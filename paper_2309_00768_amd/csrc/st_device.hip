@@ -1309,13 +1309,23 @@ void launch_groups(const MultiArgs& step, hipStream_t s) {
     void* params[] = {&g};
     (void)hipLaunchKernel(fn, dim3(unsigned(total)), dim3(kBlock), params, 0, s);
   };
-  if (nk == 2 && pairable_index(kinds[0]) >= 0 && pairable_index(kinds[1]) >= 0) {
-    int a = pairable_index(kinds[0]), b = pairable_index(kinds[1]);
-    if (a > b) std::swap(a, b);
+  // pairable kinds two by two, the rest (and an odd one out) alone
+  int pend = -1;
+  for (int k = 0; k < nk; ++k) {
+    const int pi = pairable_index(kinds[k]);
+    if (pi < 0) {
+      launch(group_kernel<T>(kinds[k]), kinds[k], kinds[k]);
+      continue;
+    }
+    if (pend < 0) {
+      pend = pi;
+      continue;
+    }
+    const int a = std::min(pend, pi), b = std::max(pend, pi);
     launch(group2_kernel<T>(a, b), kPairable[a], kPairable[b]);
-    return;
+    pend = -1;
   }
-  for (int k = 0; k < nk; ++k) launch(group_kernel<T>(kinds[k]), kinds[k], kinds[k]);
+  if (pend >= 0) launch(group_kernel<T>(kPairable[pend]), kPairable[pend], kPairable[pend]);
 }
 
 template <class T>
