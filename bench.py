@@ -28,13 +28,13 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of one J apply at the default workload from FETCH_SIZE / WRITE_SIZE
 # counter runs calibrated with a 1 GiB copy (profiles/pmc_cfg3_jacobian_fetch_write.md),
 # valid while the kernel source it measured is unchanged (digest of that source).
-JAC_COUNTERS = {"config": "cfg3", "source_sha256_16": "f1ef34996b299b64", "traffic_bytes": 4.786e9}
+JAC_COUNTERS = {"config": "cfg3", "source_sha256_16": "586580fa0a25caa9", "traffic_bytes": 3.243e9}
 
 
 def jacobian_kernel_digest():
     import hashlib
     src = open(os.path.join(ROOT, "paper_2309_00768_amd", "csrc", "kernels.h")).read()
-    a = src.index("__device__ inline TA sell_row(")
+    a = src.index("struct SpmvSlabsArgs {")
     b = src.index("// Fused Chebyshev-Jacobi step for A x = b")
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
@@ -186,6 +186,75 @@ def bench_batch(args, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_adjoint(args, dev):
+    """Adjoint workload: 128 x 128 mesh, Nt = 128, dt = 0.005, Re = S = 500, FP64.
+    A step is one gradient of J = 1/2 |A(T) - A_target|^2 with respect to the
+    initial potential A0 and the forcing f through the autograd Function: a
+    forward solve and the transposed, backward-in-time adjoint solve, both to
+    1e-12.  The gradient is checked against central differences in 8 seeded
+    directions (J is exactly quadratic, so the differences are exact up to the
+    solve tolerance)."""
+    import torch
+    from paper_2309_00768_amd import autograd as stg
+    from paper_2309_00768_amd import inputs
+    cfg = inputs.CONFIGS["cfg5"]
+    ub, ab = inputs.state(cfg)
+    t0 = time.perf_counter()
+    prob = stg.SpaceTimeProblem(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp64",
+                                rtol=1e-12, checkpoint="auto", device=dev)
+    log(f"setup {time.perf_counter() - t0:.1f} s, N={prob.N}")
+    n, nt = cfg.n, cfg.nt
+    na, nu = (n - 1) ** 2, 2 * (2 * n - 1) ** 2
+    a0 = torch.from_numpy(inputs.free_a_field(cfg, 2)).to(dev).requires_grad_(True)
+    f = torch.from_numpy(inputs.random_vector(nt * nu, 1)).to(dev).requires_grad_(True)
+    target = torch.from_numpy(inputs.free_a_field(cfg, 3)).to(dev)
+
+    def loss(a, ff):
+        return 0.5 * ((stg.terminal_potential(prob, a, ff) - target) ** 2).sum()
+
+    def gradient():
+        a0.grad = None
+        f.grad = None
+        L = loss(a0, f)
+        L.backward()
+        return L
+
+    for i in range(args.warmup):
+        gradient()
+        log(f"warmup {i} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        L = gradient()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ga, gf = a0.grad.detach().clone(), f.grad.detach().clone()
+    worst, checks = 0.0, []
+    if not args.no_fd:
+        for s in range(8):
+            da = torch.from_numpy(inputs.random_vector(na, 10 + s)).to(dev)
+            df = torch.from_numpy(inputs.random_vector(nt * nu, 20 + s) * 0.1).to(dev)
+            eps = 1e-3
+            with torch.no_grad():
+                fd = (loss(a0 + eps * da, f + eps * df) - loss(a0 - eps * da, f - eps * df)).item() / (2 * eps)
+            ad = (ga @ da + gf @ df).item()
+            err = abs(fd - ad) / max(abs(fd), 1e-30)
+            worst = max(worst, err)
+            checks.append(err)
+            log(f"  direction {s}: finite difference {fd:.10e}, adjoint {ad:.10e}, relative {err:.2e}")
+    out = {
+        "metric": METRIC, "value": prob.N * 2 / (elapsed / args.steps), "unit": "DOF-solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"cfg5: {n}x{n} Q2-Q1/Q1/Q1, Nt={nt}, dt={cfg.dt}, Re=S={cfg.re:g}; gradient of "
+                               f"1/2|A(T) - A_target|^2 w.r.t. A0 and f: forward + adjoint FGMRES(30) to 1e-12, "
+                               f"FP64", "N": prob.N},
+        "gradient_s": elapsed / args.steps, "loss": float(L.item()), "rebuilds": prob.rebuilds,
+        "fd_worst_relative": worst if checks else None, "fd_relative": checks,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +267,7 @@ def main():
     ap.add_argument("--cpu-slabs", type=int, default=16)
     ap.add_argument("--no-separate", action="store_true", help="cfg4: skip the one-at-a-time comparison")
     ap.add_argument("--batch-budget", type=int, default=960, help="cfg4: FGMRES iterations per member")
+    ap.add_argument("--no-fd", action="store_true", help="cfg5: skip the finite-difference check")
     ap.add_argument("--probe", choices=["jacobian"], default=None,
                     help="run only a few J applies and a copy of known size (for hardware-counter runs)")
     args = ap.parse_args()
@@ -212,6 +282,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.config == "cfg4":
         bench_batch(args, dev)
+        return
+    if args.config == "cfg5":
+        bench_adjoint(args, dev)
         return
     cfg = inputs.CONFIGS[args.config]
     ub, ab = inputs.state(cfg)
@@ -290,7 +363,7 @@ def main():
         traffic = JAC_COUNTERS["traffic_bytes"]
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                       "kernel": "k_spmv<double,double,double,0> (space-time Jacobian apply)",
+                       "kernel": "k_spmv_slabs<8, 4> (space-time Jacobian apply, 8 slabs per wavefront)",
                        "bytes_per_launch": jbytes, "avg_launch_ms": jac_avg * 1e3, "launches": jac_n,
                        "nnz_state_per_slab": nnz_state, "nnz_shared": nnz_const}
     if not args.no_cpu:

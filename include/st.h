@@ -107,7 +107,10 @@ typedef struct st_problem {
   int sweep_chain;    /* 0: on grids of at most 1024 unknowns the C_A sweep and
                          the M_j solves of a chunk run in one workgroup (no
                          launch per step); -1: never (per-step launches)      */
-  int reserved[2];
+  int j_slabs;        /* slabs per wavefront of the J apply: 0 auto (8), 1 one
+                         slab per workgroup row, 4 or 8 (slab-invariant column
+                         indices and values loaded once for them)           */
+  int reserved[1];
   double inner_reduction; /* auto inner solver of F_u,k: target error reduction
                              per spatial solve (0: 0.1)                        */
   double ca_reduction;    /* auto inner solver of C_A,k: target reduction (0: 0.05) */

@@ -151,6 +151,99 @@ __global__ ST_LATENCY_KERNEL void k_spmv(SpmvArgs<T, TX> a) {
   spmv_body<T, TX, TA>(a, blockIdx.x, blockIdx.y);
 }
 
+// The space-time Jacobian (or its transpose) over NV consecutive slabs per
+// wavefront: each column index and each slab-invariant value of a row is
+// loaded once for the NV slabs, the slab-dependent values and the gathered x
+// once per slab; all loads of a batch of B entries are issued together (at
+// cfg3 the loads in flight per lane pay more than occupancy).  One lane per
+// row.  Per row and slab the products are summed in the same order as k_spmv
+// (segment by segment, entries in order), so the result is the same.
+struct SpmvSlabsArgs {
+  SpmvArgs<double, double> a;
+  int nvec;   // number of slabs
+};
+
+template <int NV, int B = 4>
+__device__ inline void spmv_slabs_body(const SpmvSlabsArgs& sa, int bx, int by) {
+  const SpmvArgs<double, double>& a = sa.a;
+  const int nvec = sa.nvec;
+  const int v0 = by * NV;
+  const int slice = bx * (kBlock / kWave) + (threadIdx.x / kWave);
+  if (slice >= a.nslices) return;          // uniform per wavefront
+  const int lane = threadIdx.x % kWave;
+  const int row = a.perm[slice * kWave + lane];
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    if (s >= a.nseg) break;
+    const Seg<double>& g = a.seg[s];
+    // Slabs outside the segment's range read slab vlo's data (in bounds) and
+    // their sums are dropped, so every load of a batch is issued together.
+    bool on[NV];
+    const double* xs[NV];
+    const double* vals[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      on[v] = v0 + v < nvec && v0 + v >= g.vlo && v0 + v < g.vhi;
+      const int vv = on[v] ? v0 + v : g.vlo;
+      xs[v] = static_cast<const double*>(g.x) + int64_t(vv + g.xshift) * g.xstride;
+      vals[v] = g.val + (g.vstride ? int64_t(g.set_base + vv * g.set_step) * g.vstride : 0);
+    }
+    const int beg = g.sptr[slice];
+    const int w = (g.sptr[slice + 1] - beg) / kWave;
+    const int* __restrict__ col = g.col + beg + lane;
+    double sum[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sum[v] = 0.0;
+    for (int j = 0; j < w; j += B) {
+      const int rem = w - j;
+      int c[B];
+      int o[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        o[u] = beg + lane + (j + (u < rem ? u : 0)) * kWave;
+        c[u] = col[(j + (u < rem ? u : 0)) * kWave];
+      }
+      double vv[NV][B], xv[NV][B];
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int u = 0; u < B; ++u) vv[v][u] = (g.vstride || v == 0) ? vals[v][o[u]] : 0.0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int u = 0; u < B; ++u) xv[v][u] = xs[v][c[u]];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          const double val = g.vstride ? vv[v][u] : vv[0][u];
+          sum[v] += (u < rem ? val : 0.0) * xv[v][u];
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (on[v]) acc[v] += g.alpha * sum[v];
+  }
+  if (row < 0) return;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    if (v0 + v >= nvec) break;
+    double out = acc[v];
+    if (a.b) out += a.beta * a.b[int64_t(v0 + v) * a.bstride + row];
+    a.y[int64_t(v0 + v) * a.ystride + row] = out;
+  }
+}
+
+// Bandwidth-bound: no cap on the waves per SIMD (unlike the latency kernels).
+template <int NV, int B = 4>
+__global__ __launch_bounds__(kBlock) void k_spmv_slabs(SpmvSlabsArgs a) {
+  spmv_slabs_body<NV, B>(a, blockIdx.x, blockIdx.y);
+}
+
 // Fused Chebyshev-Jacobi step for A x = b (A one SELL segment), per vector v.
 //   mode 0: r = b (if b), d_new = Dinv r / theta, x = d_new (or x += d_new)
 //   mode 1: r -= A d_old; d_new = c1 d_old + c2 Dinv r; x += d_new   (step >= 1)

@@ -1,12 +1,11 @@
 // Launch sink of libst.  Every kernel launch of the preconditioner and of
 // FGMRES goes through emit(): it either launches the kernel on a stream
-// (immediate mode) or appends the launch -- kernel kind, grid and argument
-// block -- to a program (record mode).  A batch of systems replays the
-// programs of all its systems in lockstep: launch t of a batched phase runs
-// op t of every member system in one heterogeneous kernel, k_multi, whose
-// workgroups find their system and kernel body from a small descriptor
-// passed as kernel arguments.  Launches per phase then follow the longest
-// member program instead of the sum over members.
+// (immediate mode) or appends the launch -- kernel, body kind, grid and
+// argument block -- to a program (record mode).  Recorded programs are
+// replayed with several ops per launch: two ops of one system through a
+// kernel holding exactly their two bodies (k_two), or the ops of many systems
+// grouped by kind (k_group, k_group2), whose workgroups find their op from a
+// descriptor table passed as kernel arguments.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -47,6 +46,8 @@ enum Kind : int {
   kKFill,           // FillArgs
   kKCopySmall,      // CopySmallArgs
   kKSetPtrs,        // SetPtrsArgs
+  kKSpmvSlabs4,     // SpmvSlabsArgs (J apply, 4 slabs per wavefront)
+  kKSpmvSlabs8,     // SpmvSlabsArgs (J apply, 8 slabs per wavefront)
   kKNumKinds
 };
 
@@ -241,6 +242,14 @@ template <class T> struct KB<kKCopySmall, T> {
   using Args = CopySmallArgs;
   __device__ static void run(const Args& a, int, int) { copy_small_body(a); }
 };
+template <class T> struct KB<kKSpmvSlabs4, T> {
+  using Args = SpmvSlabsArgs;
+  __device__ static void run(const Args& a, int b, int gx) { spmv_slabs_body<4>(a, b % gx, b / gx); }
+};
+template <class T> struct KB<kKSpmvSlabs8, T> {
+  using Args = SpmvSlabsArgs;
+  __device__ static void run(const Args& a, int b, int gx) { spmv_slabs_body<8>(a, b % gx, b / gx); }
+};
 template <class T> struct KB<kKSetPtrs, T> {
   using Args = SetPtrsArgs;
   __device__ static void run(const Args& a, int, int) { set_ptrs_body(a); }
@@ -318,9 +327,8 @@ __global__ ST_LATENCY_KERNEL void k_group2(GroupArgs g) {
   }
 }
 
-// ----------------------------------------------------- batched launches ---
-
-
+// ------------------------------------------------------ batch descriptors ---
+// One op of a member system in a lockstep step, and the ops of one step.
 struct Member {
   const unsigned char* args;   // device copy of the op's argument block
   int kind;
@@ -334,66 +342,5 @@ struct MultiArgs {
   int pad;
   Member m[kMaxMembers];
 };
-
-template <class T, class A>
-__device__ inline A load_args(const unsigned char* p) {
-  return *reinterpret_cast<const A* __restrict__>(p);
-}
-
-// Workgroup b of the launch belongs to member i with prefix(i) <= b <
-// prefix(i+1); it runs that member's body with its own workgroup coordinates.
-template <class T>
-__global__ ST_LATENCY_KERNEL void k_multi(MultiArgs a) {
-  int rem = blockIdx.x, sel = 0;
-  bool found = false;
-#pragma unroll
-  for (int i = 0; i < kMaxMembers; ++i) {
-    if (!found && i < a.nmem) {
-      if (rem < a.m[i].blocks) {
-        sel = i;
-        found = true;
-      } else {
-        rem -= a.m[i].blocks;
-      }
-    }
-  }
-  if (!found) return;
-  int kind = 0, gx = 1;
-  const unsigned char* p = nullptr;
-#pragma unroll
-  for (int i = 0; i < kMaxMembers; ++i)
-    if (i == sel) {
-      kind = a.m[i].kind;
-      gx = a.m[i].gx;
-      p = a.m[i].args;
-    }
-  const int bx = rem % gx, by = rem / gx;
-  switch (kind) {
-    case kKSpmvJ: spmv_body<double, double, double>(load_args<T, SpmvArgs<double, double>>(p), bx, by); break;
-    case kKSpmvT: spmv_body<T, T, T>(load_args<T, SpmvArgs<T, T>>(p), bx, by); break;
-    case kKCheb: cheb_body<T>(load_args<T, ChebArgs<T>>(p), bx, by); break;
-    case kKStInit: st_init_body<T>(load_args<T, StInitArgs<T>>(p), bx); break;
-    case kKStCheb: st_cheb_body<T>(load_args<T, StChebArgs<T>>(p), bx); break;
-    case kKCoarse: coarse_body<T>(load_args<T, CoarseArgs<T>>(p), bx); break;
-    case kKSlabSumsD: slab_sums_d_body(load_args<T, SlabSumsDArgs>(p), bx); break;
-    case kKSlabSumsT: slab_sums_t_body<T>(load_args<T, SlabSumsTArgs<T>>(p), bx); break;
-    case kKSplit: split_body<T>(load_args<T, SplitArgs<T>>(p), bx, gx); break;
-    case kKJoin: join_body<T>(load_args<T, JoinArgs<T>>(p), bx, gx); break;
-    case kKSlabShiftD: slab_shift_body<double>(load_args<T, SlabShiftArgs<double>>(p), bx, gx); break;
-    case kKSlabShiftT: slab_shift_body<T>(load_args<T, SlabShiftArgs<T>>(p), bx, gx); break;
-    case kKProjectP: project_p_body(load_args<T, ProjectPArgs>(p), bx, gx); break;
-    case kKMdot: mdot_body(load_args<T, MdotArgs>(p), bx, by, gx); break;
-    case kKReduce: reduce_body(load_args<T, ReduceArgs>(p), bx); break;
-    case kKCombine: combine_body(load_args<T, CombineArgs>(p), bx, gx); break;
-    case kKScale: scale_body(load_args<T, ScaleArgs>(p), bx, gx); break;
-    case kKGivens: givens_body(load_args<T, GivensArgs>(p)); break;
-    case kKTrisolve: trisolve_body(load_args<T, TrisolveArgs>(p)); break;
-    case kKInitG: init_g_body(load_args<T, InitGArgs>(p)); break;
-    case kKFill: fill_body(load_args<T, FillArgs>(p), bx, gx); break;
-    case kKCopySmall: copy_small_body(load_args<T, CopySmallArgs>(p)); break;
-    case kKSetPtrs: set_ptrs_body(load_args<T, SetPtrsArgs>(p)); break;
-    default: break;
-  }
-}
 
 }  // namespace st

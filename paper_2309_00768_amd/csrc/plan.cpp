@@ -172,6 +172,10 @@ WsLayout workspace_layout(const Plan& P) {
 
 static int build_plan(Plan& P, std::string& err) {
   const st_problem& pr = P.prob;
+  if (pr.j_slabs != 0 && pr.j_slabs != 1 && pr.j_slabs != 4 && pr.j_slabs != 8) {
+    err = "j_slabs must be 0, 1, 4 or 8";
+    return ST_EINVAL;
+  }
   int rc = assemble_blocks(pr, P.blk, err);
   if (rc) return rc;
   form_wave_operator(P.blk);

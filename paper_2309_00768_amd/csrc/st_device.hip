@@ -87,6 +87,7 @@ struct Handle {
   // runs the next op of each program whose dependency is met) from descriptors
   // built once; the argument blocks live in the workspace, the input and
   // output vectors are read from two device slots.
+  int j_slabs = 0;                 // slabs per wavefront of the J apply (0: 8)
   int pipeline = 0;
   std::vector<ReplayItem> pt_items;
   const double** rslot = nullptr;
@@ -763,7 +764,9 @@ int apply_precond(Handle& H, const double* r, double* z, Ctx& c, bool transpose)
   return transpose ? precond_transpose<double>(H, r, z, c) : precond_forward<double>(H, r, z, c, c);
 }
 
-// y = alpha J x + beta b  (J or J^T), FP64
+// y = alpha J x + beta b  (J or J^T), FP64.  With one lane per row the
+// multi-slab kernel loads the slab-invariant indices and values once for
+// several slabs.
 void apply_J(Handle& H, const double* x, double* y, Ctx& c, bool transpose, double alpha, const double* b) {
   const DGroup& g = transpose ? H.JT : H.J;
   const int nt = H.d.nt, ns = H.d.ns;
@@ -771,7 +774,27 @@ void apply_J(Handle& H, const double* x, double* y, Ctx& c, bool transpose, doub
       seg<double>(g, 0, 0, 1, x, ns, 0, 0, nt, alpha),
       seg<double>(g, 1, 0, 0, x, ns, 0, 0, nt, alpha),
       transpose ? seg<double>(g, 2, 0, 0, x, ns, 1, 0, nt - 1, alpha) : seg<double>(g, 2, 0, 0, x, ns, -1, 1, nt, alpha)};
-  spmv<double, double>(c, g, nt, 3, sg, b, ns, b ? 1.0 : 0.0, y, ns, kRoleJ);
+  const int nv = H.j_slabs == 0 ? 8 : H.j_slabs;
+  if (g.lanes != 1 || nv == 1) {
+    spmv<double, double>(c, g, nt, 3, sg, b, ns, b ? 1.0 : 0.0, y, ns, kRoleJ);
+    return;
+  }
+  SpmvSlabsArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.a.perm = g.perm;
+  a.a.nslices = g.nslices;
+  a.a.lanes = 1;
+  a.a.nseg = 3;
+  for (int i = 0; i < 3; ++i) a.a.seg[i] = sg[i];
+  a.a.b = b;
+  a.a.bstride = ns;
+  a.a.beta = b ? 1.0 : 0.0;
+  a.a.y = y;
+  a.a.ystride = ns;
+  a.nvec = nt;
+  const dim3 grid((g.nslices + 3) / 4, (nt + nv - 1) / nv);
+  if (nv == 8) emit(c, kKSpmvSlabs8, grid, &k_spmv_slabs<8>, a);
+  else emit(c, kKSpmvSlabs4, grid, &k_spmv_slabs<4>, a);
 }
 
 // ============================================================ FGMRES ===
@@ -1521,6 +1544,7 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
   H.fu_deg = P.fu_deg;
   H.ca_deg = P.ca_deg;
   H.use_stencil = P.use_stencil;
+  H.j_slabs = P.prob.j_slabs;
   H.sFu = P.sFu;
   H.sAu = P.sAu;
   H.sC0 = P.sC0;
