@@ -80,7 +80,7 @@ typedef struct st_problem {
   int precond_precision; /* st_precision of everything inside P_T           */
   int inner_mode;     /* st_inner_mode                                        */
   int inner_iters;    /* V-cycles per spatial solve in EXACT mode (0: 40)      */
-  int mass_iters;     /* Chebyshev steps per mass-matrix solve (0: 12 AMG mode,
+  int mass_iters;     /* Chebyshev steps per mass-matrix solve (0: 6 AMG mode,
                          60 EXACT mode)                                        */
   int cheb_degree;    /* Chebyshev-Jacobi smoother degree (0: 3)              */
   int fu_solver;      /* inner solver of F_u,k in AMG mode: 0 auto (from the
@@ -112,8 +112,9 @@ typedef struct st_problem {
                          indices and values loaded once for them)           */
   int reserved[1];
   double inner_reduction; /* auto inner solver of F_u,k: target error reduction
-                             per spatial solve (0: 0.1)                        */
-  double ca_reduction;    /* auto inner solver of C_A,k: target reduction (0: 0.05) */
+                             per spatial solve (0: 0.3; degree at least 4)    */
+  double ca_reduction;    /* auto inner solver of C_A,k: target reduction (0: 0.3;
+                             degree at least 4)                                */
 } st_problem;
 
 typedef struct st_opts {

@@ -21,7 +21,7 @@
 namespace st {
 
 // Kernel bodies a batched launch can run.  Ids of precision-dependent bodies
-// refer to the preconditioner precision T of the k_multi<T> instance.
+// refer to the preconditioner precision T of the k_group<K, T> instance.
 enum Kind : int {
   kKSpmvJ = 0,      // SpmvArgs<double, double>, FP64 (J apply)
   kKSpmvT,          // SpmvArgs<T, T> (every P_T product, all roles)

@@ -186,7 +186,7 @@ static int build_plan(Plan& P, std::string& err) {
   P.fp32 = pr.precond_precision == ST_FP32 ? 1 : 0;
   P.exact = pr.inner_mode == ST_INNER_EXACT ? 1 : 0;
   P.inner_iters = pr.inner_iters > 0 ? pr.inner_iters : 40;
-  P.mass_iters = pr.mass_iters > 0 ? pr.mass_iters : (P.exact ? 60 : 12);
+  P.mass_iters = pr.mass_iters > 0 ? pr.mass_iters : (P.exact ? 60 : 6);
   P.max_restart = pr.max_restart > 0 ? pr.max_restart : 30;
   const int cheb = pr.cheb_degree > 0 ? pr.cheb_degree : 3;
   const int fp = P.fp32;
@@ -282,19 +282,21 @@ static int build_plan(Plan& P, std::string& err) {
   estimate_interval(img, b.Fu, nt, P.amgFu);
   estimate_interval(img, b.C0, nt, P.amgC0);
   {
-    const double red_fu = pr.inner_reduction > 0 ? pr.inner_reduction : 0.1;
-    const double red_ca = pr.ca_reduction > 0 ? pr.ca_reduction : 0.05;
-    // The degree meets the reduction target on the estimated interval (the
-    // sweeps solve for increments, so the error of a step is not amplified by
-    // the recursion in time).  Beyond kMaxAlone steps one V-cycle is cheaper
-    // per slab.
-    constexpr int kMaxAlone = 48;
+    const double red_fu = pr.inner_reduction > 0 ? pr.inner_reduction : 0.3;
+    const double red_ca = pr.ca_reduction > 0 ? pr.ca_reduction : 0.3;
+    // The degree meets the reduction target on the estimated interval, and is
+    // at least kMinAlone (the sweeps solve for increments, so the error of a
+    // step is not amplified by the recursion in time; measured at the cfg3 and
+    // uneven-batch sizes, tighter solves do not lower the FGMRES iteration
+    // count, and C_A below degree 4 raises it).  Beyond kMaxAlone steps one
+    // V-cycle is cheaper per slab.
+    constexpr int kMinAlone = 4, kMaxAlone = 48;
     auto pick = [&](int opt, const Amg& a, double red) -> int {
       if (P.exact || opt < 0) return 0;
       if (opt > 0) return opt;
       const double sk = std::sqrt(a.kappa), r = (sk - 1.0) / (sk + 1.0);
       const int deg = int(std::ceil(std::log(red / 2.0) / std::log(r)));
-      return deg > kMaxAlone ? 0 : std::max(2, deg);
+      return deg > kMaxAlone ? 0 : std::max(kMinAlone, deg);
     };
     P.fu_deg = pick(pr.fu_solver, P.amgFu, red_fu);
     P.ca_deg = pick(pr.ca_solver, P.amgC0, red_ca);

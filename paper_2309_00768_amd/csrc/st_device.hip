@@ -1175,7 +1175,8 @@ int build_pipeline(Handle& H) {
 // from the handle's slots, one Arnoldi tail per column j that also points the
 // slots at the next column, the cycle head) and again per solve for the
 // launches that name the caller's b and x.  A batched phase runs the lockstep
-// schedule of every member's programs in k_multi launches.
+// schedule of every member's programs, one k_group (or, for two pairable
+// kinds, one k_group2) launch per op kind of a step.
 struct BatchSys {
   Handle* H = nullptr;
   Krylov K;
