@@ -110,7 +110,11 @@ typedef struct st_problem {
   int j_slabs;        /* slabs per wavefront of the J apply: 0 auto (8), 1 one
                          slab per workgroup row, 4 or 8 (slab-invariant column
                          indices and values loaded once for them)           */
-  int reserved[1];
+  int sweep_fuse;     /* stencil sweep solves: 0 one launch per Chebyshev step;
+                         1 several steps per launch on 8 x 8 node tiles grown
+                         by halos held in LDS (up to 4 steps in the first
+                         launch of a solve, 3 in each later one; bitwise the
+                         same result, slower on the measured workloads)     */
   double inner_reduction; /* auto inner solver of F_u,k: target error reduction
                              per spatial solve (0: 0.3; degree at least 4)    */
   double ca_reduction;    /* auto inner solver of C_A,k: target reduction (0: 0.3;

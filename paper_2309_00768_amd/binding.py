@@ -34,7 +34,7 @@ class StProblem(ctypes.Structure):
         ("ca_solver", ctypes.c_int), ("max_restart", ctypes.c_int), ("sell_sigma", ctypes.c_int),
         ("adjoint", ctypes.c_int), ("j_lanes", ctypes.c_int), ("sweep_format", ctypes.c_int),
         ("single_stream", ctypes.c_int), ("sweep_chunk", ctypes.c_int), ("sweep_chain", ctypes.c_int),
-        ("j_slabs", ctypes.c_int), ("reserved", ctypes.c_int * 1),
+        ("j_slabs", ctypes.c_int), ("sweep_fuse", ctypes.c_int),
         ("inner_reduction", ctypes.c_double), ("ca_reduction", ctypes.c_double),
     ]
 
@@ -139,7 +139,7 @@ class Plan:
     def __init__(self, n, nt, dt, mu, eta, mu0, ubar, abar, jbar=None, precision="fp64", inner="amg",
                  inner_iters=0, mass_iters=0, cheb_degree=0, max_restart=0, sell_sigma=0, adjoint=False,
                  fu_solver=0, ca_solver=0, inner_reduction=0.0, j_lanes=0, ca_reduction=0.0, sweep_format=0,
-                 single_stream=False, sweep_chunk=0, sweep_chain=True, j_slabs=0):
+                 single_stream=False, sweep_chunk=0, sweep_chain=True, j_slabs=0, sweep_fuse=False):
         self._ub = np.ascontiguousarray(ubar, dtype=np.float64)
         self._ab = np.ascontiguousarray(abar, dtype=np.float64)
         assert self._ub.shape == (nt, 2, (2 * n + 1) ** 2) and self._ab.shape == (nt, (n + 1) ** 2)
@@ -157,6 +157,7 @@ class Plan:
         p.sweep_chunk = sweep_chunk
         p.sweep_chain = 0 if sweep_chain else -1
         p.j_slabs = j_slabs
+        p.sweep_fuse = 1 if sweep_fuse else 0
         self.problem = p
         self.n, self.nt = n, nt
         h = ctypes.c_void_p()

@@ -338,12 +338,13 @@ struct StOp {
   int64_t rows;
 };
 
-// (A x)[row] for a stencil operator of radius RAD; every coefficient and
+// (A x)[row] for a stencil operator of radius RAD with NCC column components
+// summed (1, or 2 for the coupled velocity components); every coefficient and
 // neighbour load is independent of the others (one memory round trip).
 // Neighbours outside the column grid have zero coefficients; their (clamped)
 // addresses stay inside x.
-template <int RAD, class T, class TA>
-__device__ inline TA stencil_row(const StOp<T>& A, int set, int64_t row, const T* __restrict__ x) {
+template <int RAD, int NCC, class T, class TA>
+__device__ inline TA stencil_row_n(const StOp<T>& A, int set, int64_t row, const T* __restrict__ x) {
   constexpr int W = 2 * RAD + 1, NS = W * W;
   const int64_t per = int64_t(A.gx) * A.gy, cper = int64_t(A.cgx) * A.cgy;
   const int c = int(row / per);
@@ -357,21 +358,31 @@ __device__ inline TA stencil_row(const StOp<T>& A, int set, int64_t row, const T
 #pragma unroll
     for (int dx = -RAD; dx <= RAD; ++dx) off[(dy + RAD) * W + dx + RAD] = jj * A.cgx + min(max(i + dx, 0), A.cgx - 1);
   }
-  TA acc = TA(0);
-  const int ncc = A.diag_comp ? 1 : A.ncomp;
-  for (int q = 0; q < ncc; ++q) {
-    const T* __restrict__ xc = x + int64_t(A.diag_comp ? c : q) * cper;
+  T cv[NCC][NS], xv[NCC][NS];
+#pragma unroll
+  for (int q = 0; q < NCC; ++q) {
+    const T* __restrict__ xc = x + int64_t(NCC == 1 && A.diag_comp ? c : q) * cper;
     const T* __restrict__ cq = cf + int64_t(q) * NS * A.rows;
-    T cv[NS], xv[NS];
 #pragma unroll
     for (int o = 0; o < NS; ++o) {
-      cv[o] = cq[int64_t(o) * A.rows];
-      xv[o] = xc[off[o]];
+      cv[q][o] = cq[int64_t(o) * A.rows];
+      xv[q][o] = xc[off[o]];
     }
-#pragma unroll
-    for (int o = 0; o < NS; ++o) acc += TA(cv[o]) * TA(xv[o]);
   }
+  TA acc = TA(0);
+#pragma unroll
+  for (int q = 0; q < NCC; ++q)
+#pragma unroll
+    for (int o = 0; o < NS; ++o) acc += TA(cv[q][o]) * TA(xv[q][o]);
   return acc;
+}
+
+// The same for any operator: one column component (diagonal-component
+// operators included) or two.
+template <int RAD, class T, class TA>
+__device__ inline TA stencil_row(const StOp<T>& A, int set, int64_t row, const T* __restrict__ x) {
+  if (A.diag_comp || A.ncomp == 1) return stencil_row_n<RAD, 1, T, TA>(A, set, row, x);
+  return stencil_row_n<RAD, 2, T, TA>(A, set, row, x);
 }
 
 // First step of a sweep solve with Chebyshev-Jacobi alone, fused with the
@@ -395,11 +406,13 @@ struct StInitArgs {
   int64_t rows;
   int guess;
   double g1, g2;
+  int rpb;              // rows per workgroup (<= kBlock; fewer spread a small grid over more CUs)
 };
 
 template <class T>
 __device__ inline void st_init_body(const StInitArgs<T>& a, int bx) {
-  const int64_t row = int64_t(bx) * kBlock + threadIdx.x;
+  if (int(threadIdx.x) >= a.rpb) return;
+  const int64_t row = int64_t(bx) * a.rpb + threadIdx.x;
   if (row >= a.rows) return;
   T acc = a.q[row];
   if (a.n1) acc += T(a.a1) * stencil_row<2, T, T>(a.S1, a.set1, row, a.y1);
@@ -432,11 +445,13 @@ struct StChebArgs {
   T* r;
   T* x;
   int64_t rows;
+  int rpb;              // rows per workgroup (<= kBlock)
 };
 
 template <class T>
 __device__ inline void st_cheb_body(const StChebArgs<T>& a, int bx) {
-  const int64_t row = int64_t(bx) * kBlock + threadIdx.x;
+  if (int(threadIdx.x) >= a.rpb) return;
+  const int64_t row = int64_t(bx) * a.rpb + threadIdx.x;
   if (row >= a.rows) return;
   const T od = a.dold[row];
   const T dg = a.dinv[row];
@@ -452,6 +467,189 @@ __device__ inline void st_cheb_body(const StChebArgs<T>& a, int bx) {
 template <class T, int Role>
 __global__ ST_LATENCY_KERNEL void k_st_cheb(StChebArgs<T> a) {
   st_cheb_body<T>(a, blockIdx.x);
+}
+
+// A Chebyshev-Jacobi sweep solve (or a run of its steps) on a stencil
+// operator in one launch, with no memory round trip between steps.  Each
+// workgroup owns a tx x ty tile of nodes (every component) and works on the
+// tile grown by a halo: a step's r and d are valid on a region one stencil
+// radius smaller than the d it reads, so with h = radius x (stencil
+// applications still to come) the last step of the launch is exact on the
+// tile.  The grown tile's r and the two d iterates live in LDS; only x (and r
+// with the last d when a later launch continues the solve) are written back.
+// A continuing launch reads r and d from other buffers than those it writes,
+// since its grown tile overlaps the tiles of other workgroups.
+// Overlapping tiles repeat the halo work of their neighbours: with 8 x 8
+// tiles and a radius-2 stencil, four steps compute 20 x 20, 16 x 16, 12 x 12
+// and 8 x 8 nodes per tile.  Step 0 is st_init_body's arithmetic (residual of
+// the predictor) and step i >= 1 st_cheb_body's, in the same order, so the
+// result is that of the step-by-step launches.
+constexpr int kSolveBlock = 512;   // threads per workgroup of the tiled solve
+// Two such workgroups per CU (4 waves per SIMD, at most 128 VGPRs): a forward
+// sweep's F_u and C_A solves together take 256 + 64 workgroups at 64 x 64.
+#define ST_SOLVE_KERNEL __launch_bounds__(kSolveBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
+constexpr int kTileExt = 400;   // nodes of a grown tile per component (LDS capacity)
+constexpr int kTileOut = 64;    // nodes of a tile per component
+constexpr int kTileComp = 2;
+
+template <class T>
+struct StSolveArgs {
+  StInitArgs<T> in;   // step 0; x, dinv, theta, rows; r and d receive r and the
+                      // last d when a later launch continues the solve
+  StOp<T> A;          // the diagonal block (row grid = column grid)
+  int set;
+  double delta;
+  const T* r_in;      // s0 > 0: r and d_{s0-1} written by the previous launch
+  const T* d_in;
+  int s0, ns;         // steps [s0, s0 + ns) of the solve
+  int tx, ty, ntx;    // tile size and tiles per grid row
+  int more;           // 1: a later launch continues (write r and the last d)
+};
+
+// (A d)[row] for a radius-2 stencil with d held in LDS over the grown tile
+// whose corner is grid node (ex0, ey0); neighbour addresses clamp to the grid
+// exactly as stencil_row's do (the clamped node lies in the grown tile).
+template <int NCC, class T>
+__device__ inline T stencil_row_lds_n(const StOp<T>& A, int set, int64_t row, int c, int i, int j, const T* sdv,
+                                      int ew, int ea, int ex0, int ey0) {
+  constexpr int RAD = 2, W = 2 * RAD + 1, NS = W * W;
+  const T* __restrict__ cf = A.coef + (A.set_stride ? int64_t(set) * A.set_stride : 0) + row;
+  int off[NS];
+#pragma unroll
+  for (int dy = -RAD; dy <= RAD; ++dy) {
+    const int jj = min(max(j + dy, 0), A.gy - 1) - ey0;
+#pragma unroll
+    for (int dx = -RAD; dx <= RAD; ++dx)
+      off[(dy + RAD) * W + dx + RAD] = jj * ew + min(max(i + dx, 0), A.gx - 1) - ex0;
+  }
+  T cv[NCC][NS], xv[NCC][NS];
+#pragma unroll
+  for (int q = 0; q < NCC; ++q) {
+    const T* xc = sdv + (NCC == 1 && A.diag_comp ? c : q) * ea;
+    const T* __restrict__ cq = cf + int64_t(q) * NS * A.rows;
+#pragma unroll
+    for (int o = 0; o < NS; ++o) {
+      cv[q][o] = cq[int64_t(o) * A.rows];
+      xv[q][o] = xc[off[o]];
+    }
+  }
+  T acc = T(0);
+#pragma unroll
+  for (int q = 0; q < NCC; ++q)
+#pragma unroll
+    for (int o = 0; o < NS; ++o) acc += cv[q][o] * xv[q][o];
+  return acc;
+}
+
+template <class T>
+__device__ inline T stencil_row_lds(const StOp<T>& A, int set, int64_t row, int c, int i, int j, const T* sdv,
+                                    int ew, int ea, int ex0, int ey0) {
+  if (A.diag_comp || A.ncomp == 1) return stencil_row_lds_n<1, T>(A, set, row, c, i, j, sdv, ew, ea, ex0, ey0);
+  return stencil_row_lds_n<2, T>(A, set, row, c, i, j, sdv, ew, ea, ex0, ey0);
+}
+
+template <class T>
+__device__ inline void st_solve_body(const StSolveArgs<T>& a, int bx) {
+  constexpr int RAD = 2;
+  __shared__ T sr[kTileComp * kTileExt];
+  __shared__ T sd[2][kTileComp * kTileExt];
+  __shared__ T sx[kTileComp * kTileOut];
+  const StInitArgs<T>& in = a.in;
+  const int gx = a.A.gx, gy = a.A.gy, nc = a.A.ncomp;
+  const int per = gx * gy;
+  const int tyi = bx / a.ntx, txi = bx - tyi * a.ntx;
+  const int X0 = txi * a.tx, Y0 = tyi * a.ty;
+  const int s0 = a.s0, s1 = a.s0 + a.ns;       // steps [s0, s1)
+  const int H = RAD * (a.ns - (s0 == 0 ? 1 : 0));
+  const int ew = a.tx + 2 * H, ea = ew * (a.ty + 2 * H);
+  const int ex0 = X0 - H, ey0 = Y0 - H;
+  const int ta = a.tx * a.ty;
+  const double sigma = in.theta / a.delta;
+  double rho_prev = 1.0 / sigma, rho = rho_prev;
+  for (int i = 1; i < s0; ++i) {
+    rho_prev = rho;
+    rho = 1.0 / (2.0 * sigma - rho_prev);
+  }
+  // A continued solve reads d_{s0-1} on the whole grown tile, r and x where
+  // its first step computes.
+  if (s0 > 0) {
+    const int xa = max(ex0, 0), xb = min(ex0 + ew, gx), ya = max(ey0, 0), yb = min(ey0 + ea / ew, gy);
+    const int w = xb - xa, n = nc * w * (yb - ya);
+    for (int e = threadIdx.x; e < n; e += kSolveBlock) {
+      const int c = e / (w * (yb - ya)), rem = e - c * w * (yb - ya);
+      const int j = ya + rem / w, i = xa + rem % w;
+      const int64_t row = int64_t(c) * per + int64_t(j) * gx + i;
+      const int l = c * ea + (j - ey0) * ew + (i - ex0);
+      sd[(s0 - 1) & 1][l] = a.d_in[row];
+      sr[l] = a.r_in[row];
+      if (i >= X0 && i < X0 + a.tx && j >= Y0 && j < Y0 + a.ty)
+        sx[c * ta + (j - Y0) * a.tx + (i - X0)] = in.x[row];
+    }
+    __syncthreads();
+  }
+  for (int s = s0; s < s1; ++s) {
+    const int h = RAD * (s1 - 1 - s);
+    const int xa = max(X0 - h, 0), xb = min(X0 + a.tx + h, gx), ya = max(Y0 - h, 0), yb = min(Y0 + a.ty + h, gy);
+    const int w = xb - xa, wh = w * (yb - ya), n = nc * wh;
+    const bool last = s == s1 - 1;
+    T c1 = T(0), c2 = T(0);
+    if (s >= 1) {
+      rho_prev = rho;
+      rho = 1.0 / (2.0 * sigma - rho_prev);
+      c1 = T(rho * rho_prev);
+      c2 = T(2.0 * rho / a.delta);
+    }
+    for (int e = threadIdx.x; e < n; e += kSolveBlock) {
+      const int c = e / wh, rem = e - c * wh;
+      const int j = ya + rem / w, i = xa + rem % w;
+      const int64_t row = int64_t(c) * per + int64_t(j) * gx + i;
+      const int l = c * ea + (j - ey0) * ew + (i - ex0);
+      const bool tile = i >= X0 && i < X0 + a.tx && j >= Y0 && j < Y0 + a.ty;
+      const int tl = c * ta + (j - Y0) * a.tx + (i - X0);
+      T rn, d, xn = T(0);
+      if (s == 0) {
+        T acc = in.q[row];
+        if (in.n1) acc += T(in.a1) * stencil_row<2, T, T>(in.S1, in.set1, row, in.y1);
+        if (in.n2) acc += T(in.a2) * stencil_row<2, T, T>(in.S2, in.set2, row, in.y2);
+        d = in.dinv[row] * acc / T(in.theta);
+        rn = acc;
+        if (tile) {
+          T x0 = T(0);
+          if (in.guess) {
+            x0 = T(in.g1) * in.y1[row];
+            if (in.g2 != 0.0) x0 += T(in.g2) * in.y2[row];
+          }
+          xn = x0 + d;
+        }
+      } else {
+        const T* sdo = sd[(s - 1) & 1];
+        const T od = sdo[l];
+        const T dg = in.dinv[row];
+        const T t = stencil_row_lds<T>(a.A, a.set, row, c, i, j, sdo, ew, ea, ex0, ey0);
+        rn = sr[l] - t;
+        d = c1 * od + c2 * dg * rn;
+        if (tile) xn = sx[tl] + d;
+      }
+      if (last) {
+        // the last step runs on the tile only
+        in.x[row] = xn;
+        if (a.more) {
+          in.r[row] = rn;
+          in.d[row] = d;
+        }
+      } else {
+        sr[l] = rn;
+        sd[s & 1][l] = d;
+        if (tile) sx[tl] = xn;
+      }
+    }
+    if (!last) __syncthreads();
+  }
+}
+
+template <class T, int Role>
+__global__ ST_SOLVE_KERNEL void k_st_solve(StSolveArgs<T> a) {
+  st_solve_body<T>(a, blockIdx.x);
 }
 
 // The C_A sweep for slabs [k0, k1) in one workgroup, each slab followed by

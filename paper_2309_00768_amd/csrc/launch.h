@@ -48,6 +48,7 @@ enum Kind : int {
   kKSetPtrs,        // SetPtrsArgs
   kKSpmvSlabs4,     // SpmvSlabsArgs (J apply, 4 slabs per wavefront)
   kKSpmvSlabs8,     // SpmvSlabsArgs (J apply, 8 slabs per wavefront)
+  kKStSolve,        // StSolveArgs<T>
   kKNumKinds
 };
 
@@ -81,6 +82,10 @@ struct Ctx {
   bool recording() const { return rec != nullptr; }
 };
 
+// Workgroup size of a kind's kernels: the tiled sweep solve runs wider
+// workgroups (one grown tile each), everything else kBlock.
+inline int block_of(int kind) { return kind == kKStSolve ? kSolveBlock : kBlock; }
+
 template <class A>
 inline void emit(Ctx& c, int kind, dim3 grid, void (*kern)(A), const A& a) {
   static_assert(sizeof(A) <= kOpArgBytes, "kernel arguments exceed an op record");
@@ -98,7 +103,7 @@ inline void emit(Ctx& c, int kind, dim3 grid, void (*kern)(A), const A& a) {
     return;
   }
   void* params[] = {const_cast<A*>(&a)};
-  (void)hipLaunchKernel(reinterpret_cast<const void*>(kern), grid, dim3(kBlock), params, 0, c.s);
+  (void)hipLaunchKernel(reinterpret_cast<const void*>(kern), grid, dim3(block_of(kind)), params, 0, c.s);
 }
 
 // ------------------------------------------------------- paired launches ---
@@ -118,6 +123,13 @@ struct BodyStCheb {
   using Args = StChebArgs<T>;
   static constexpr int kind = kKStCheb;
   __device__ static void run(const Args& a, int b, int) { st_cheb_body<T>(a, b); }
+};
+
+template <class T>
+struct BodyStSolve {
+  using Args = StSolveArgs<T>;
+  static constexpr int kind = kKStSolve;
+  __device__ static void run(const Args& a, int b, int) { st_solve_body<T>(a, b); }
 };
 
 template <class T>
@@ -148,6 +160,15 @@ __global__ ST_LATENCY_KERNEL void k_two(TwoArgs<X, Y> p) {
   else Y::run(p.y, b - p.xblocks, p.ygx);
 }
 
+// Two tiled sweep solves (one of each program) in one launch of kSolveBlock
+// workgroups.
+template <class T>
+__global__ ST_SOLVE_KERNEL void k_two_solve(TwoArgs<BodyStSolve<T>, BodyStSolve<T>> p) {
+  const int b = blockIdx.x;
+  if (b < p.xblocks) st_solve_body<T>(p.x, b);
+  else st_solve_body<T>(p.y, b - p.xblocks);
+}
+
 // -------------------------------------------------------- grouped launches ---
 // Body of kind K in precision T with its argument type; b is the workgroup
 // index within the op's own grid of gx columns.  A grouped launch runs ops of
@@ -173,6 +194,10 @@ template <class T> struct KB<kKStInit, T> {
 template <class T> struct KB<kKStCheb, T> {
   using Args = StChebArgs<T>;
   __device__ static void run(const Args& a, int b, int) { st_cheb_body<T>(a, b); }
+};
+template <class T> struct KB<kKStSolve, T> {   // launched through k_group_solve
+  using Args = StSolveArgs<T>;
+  __device__ static void run(const Args&, int, int) {}
 };
 template <class T> struct KB<kKCoarse, T> {
   using Args = CoarseArgs<T>;
@@ -300,6 +325,20 @@ __global__ ST_LATENCY_KERNEL void k_group(GroupArgs g) {
   using A = typename KB<K, T>::Args;
   const A a = *reinterpret_cast<const A* __restrict__>(p);
   KB<K, T>::run(a, rem, gx);
+}
+
+// Tiled sweep solves of several systems (both sweeps of each) in one launch.
+template <class T>
+__global__ ST_SOLVE_KERNEL void k_group_solve(GroupArgs g) {
+  int rem = 0;
+  const int sel = group_member(g, rem);
+  if (sel < 0) return;
+  const unsigned char* p = nullptr;
+#pragma unroll
+  for (int i = 0; i < kMaxMembersG; ++i)
+    if (i == sel) p = g.m[i].args;
+  const StSolveArgs<T> a = *reinterpret_cast<const StSolveArgs<T>* __restrict__>(p);
+  st_solve_body<T>(a, rem);
 }
 
 template <int K1, int K2, class T>

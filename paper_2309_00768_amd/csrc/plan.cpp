@@ -176,6 +176,10 @@ static int build_plan(Plan& P, std::string& err) {
     err = "j_slabs must be 0, 1, 4 or 8";
     return ST_EINVAL;
   }
+  if (pr.sweep_fuse != 0 && pr.sweep_fuse != 1) {
+    err = "sweep_fuse must be 0 or 1";
+    return ST_EINVAL;
+  }
   int rc = assemble_blocks(pr, P.blk, err);
   if (rc) return rc;
   form_wave_operator(P.blk);

@@ -191,6 +191,7 @@ SellGroup pack_sell(Image& img, const std::vector<const Csr*>& mats, int fp32, i
 bool pack_stencil(Image& img, const Csr& m, int nsets, int gx, int gy, int ncomp, bool diag_comp, int fp32,
                   StencilOp& out, int rad, int cgx, int cgy, int shift) {
   out = StencilOp();
+  if (ncomp < 1 || ncomp > 2) return false;   // the kernels sum one or two column components
   out.gx = gx;
   out.gy = gy;
   out.ncomp = ncomp;

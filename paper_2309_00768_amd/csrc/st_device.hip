@@ -61,6 +61,7 @@ struct DAmg {
 struct ReplayItem {
   const void* fn = nullptr;
   dim3 grid;
+  int block = kBlock;
   alignas(16) unsigned char args[832];
 };
 
@@ -70,6 +71,7 @@ struct Handle {
   double dt = 0;
   int fp32 = 0, exact = 0, inner_iters = 1, mass_iters = 12, max_restart = 30, adjoint = 0;
   int fu_deg = 0, ca_deg = 0, use_stencil = 0;
+  int sweep_fuse = 0;              // stencil sweep solves in tiled launches of several steps
   char* base = nullptr;
   WsLayout L;
   DGroup J, JT, MA, Mj, Mp, FA, FAt, Fp, Fpt, KjA, KjAt, Bt, B, Zj, Zjt, ZAt, Mu, C1, C1t, MA64;
@@ -431,9 +433,38 @@ StOp<T> st_op(char* base, const StencilOp& o) {
   return a;
 }
 
-// One sweep step with Chebyshev-Jacobi alone on stencil operators, `deg`
-// kernels: x = x0 + p(D^{-1} A_k) D^{-1} r0 with r0 = q + a1 S1 y1 + a2 S2 y2
-// the residual of the predictor x0 = g1 y1 + g2 y2 (x0 = 0 when !guess).
+// Tiles of the fused sweep solve and the steps one launch may take: the grown
+// tile (tile + 2 x radius x stencil applications) must fit the LDS arrays.
+// Rows per workgroup of a sweep step kernel: a slab's grid has few rows
+// (32,258 velocity rows at 64 x 64), so smaller workgroups spread a step over
+// more CUs; measured at 64 x 64, FP64 steps gain from 64 rows (the P_T apply
+// drops from 5.1 to 4.5 ms) and FP32 steps are latency-bound at any size.
+template <class T>
+constexpr int st_rows() { return sizeof(T) == 8 ? 64 : 128; }
+constexpr int kSolveTile = 8;
+constexpr int kSolveFirst = 4;   // steps 0..3: three applications of A
+constexpr int kSolveNext = 3;    // a continuing launch also applies A to the d it reads
+
+// Whether the fused solve handles operator A (one radius-2 stencil on a grid
+// that is its own column grid, at most two components).
+inline bool solve_fusable(const StencilOp& A) {
+  const int hmax = 2 * std::max(kSolveFirst - 1, kSolveNext);
+  return A.rad == 2 && A.ncomp <= kTileComp && A.cgx == A.gx && A.cgy == A.gy && A.shift == 0 &&
+         (kSolveTile + 2 * hmax) * (kSolveTile + 2 * hmax) <= kTileExt && kSolveTile * kSolveTile <= kTileOut &&
+         int64_t(A.gx) * A.gy * A.ncomp == A.rows;
+}
+
+// Launches per sweep solve of degree deg.
+inline int sweep_launches(const Handle& H, int deg) {
+  if (!H.sweep_fuse) return deg;
+  return deg <= kSolveFirst ? 1 : 1 + (deg - kSolveFirst + kSolveNext - 1) / kSolveNext;
+}
+
+// One sweep step with Chebyshev-Jacobi alone on stencil operators:
+// x = x0 + p(D^{-1} A_k) D^{-1} r0 with r0 = q + a1 S1 y1 + a2 S2 y2 the
+// residual of the predictor x0 = g1 y1 + g2 y2 (x0 = 0 when !guess).  Fused:
+// the tiled solve kernel, up to kSolveFirst steps in its first launch and
+// kSolveNext in each later one; otherwise one kernel per step.
 template <class T>
 void sweep_step_stencil(Ctx& c, Handle& H, DAmg& a, const StencilOp& A, const StencilOp* S1, int set1, double a1,
                         const T* y1, const StencilOp* S2, int set2, double a2, const T* y2, const T* q, T* x, int k,
@@ -468,7 +499,35 @@ void sweep_step_stencil(Ctx& c, Handle& H, DAmg& a, const StencilOp& A, const St
   ia.guess = guess ? 1 : 0;
   ia.g1 = g1;
   ia.g2 = g2;
-  const dim3 grid(unsigned((rows + kBlock - 1) / kBlock));
+  ia.rpb = st_rows<T>();
+  if (H.sweep_fuse && solve_fusable(A)) {
+    StSolveArgs<T> sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.in = ia;
+    sa.A = st_op<T>(H.base, A);
+    sa.set = iset;
+    sa.delta = delta;
+    sa.tx = sa.ty = kSolveTile;
+    sa.ntx = (A.gx + kSolveTile - 1) / kSolveTile;
+    const dim3 grid(unsigned(sa.ntx * ((A.gy + kSolveTile - 1) / kSolveTile)));
+    // a continuing launch reads the previous launch's r and d from the other pair of buffers
+    T* rb[2] = {r, static_cast<T*>(a.buf[1])};
+    T* db[2] = {d0, d1};
+    for (int s0 = 0, l = 0; s0 < deg; ++l) {
+      sa.s0 = s0;
+      sa.ns = std::min(deg - s0, s0 == 0 ? kSolveFirst : kSolveNext);
+      sa.more = s0 + sa.ns < deg ? 1 : 0;
+      sa.r_in = rb[(l + 1) % 2];
+      sa.d_in = db[(l + 1) % 2];
+      sa.in.r = rb[l % 2];
+      sa.in.d = db[l % 2];
+      if (role == 1) emit(c, kKStSolve, grid, &k_st_solve<T, 1>, sa);
+      else emit(c, kKStSolve, grid, &k_st_solve<T, 2>, sa);
+      s0 += sa.ns;
+    }
+    return;
+  }
+  const dim3 grid(unsigned((rows + st_rows<T>() - 1) / st_rows<T>()));
   if (role == 1) emit(c, kKStInit, grid, &k_st_init<T, 1>, ia);
   else emit(c, kKStInit, grid, &k_st_init<T, 2>, ia);
   StChebArgs<T> ca;
@@ -479,6 +538,7 @@ void sweep_step_stencil(Ctx& c, Handle& H, DAmg& a, const StencilOp& A, const St
   ca.rows = rows;
   ca.r = r;
   ca.x = x;
+  ca.rpb = st_rows<T>();
   T* d[2] = {d0, d1};
   const double sigma = theta / delta;
   double rho_prev = 1.0 / sigma, rho = rho_prev;
@@ -529,7 +589,8 @@ int precond_forward(Handle& H, const double* r, double* z, Ctx& c, Ctx& ca, cons
   const int C = rec ? std::max(1, std::min(H.chunk, nt)) : nt;
   const int nch = (nt + C - 1) / C;
   // The current solves go with the shorter program (estimated launches).
-  const int ca_len = H.ca_deg > 0 ? H.ca_deg : 24, fu_len = H.fu_deg > 0 ? H.fu_deg : 24;
+  const int ca_len = H.ca_deg > 0 ? sweep_launches(H, H.ca_deg) : 24;
+  const int fu_len = H.fu_deg > 0 ? sweep_launches(H, H.fu_deg) : 24;
   const bool mj_in_a = rec && nt * ca_len + nch * (mit + 1) <= nt * fu_len + 40;
   // The pressure part runs in b-ops that wait only for the split.
   auto mark = [&](Ctx& cx, int need) { cx.need = need; };
@@ -752,7 +813,7 @@ int replay_precond(Handle& H, const double* r, double* z, hipStream_t s) {
   hipLaunchKernelGGL(k_set_ptrs, dim3(1), dim3(kBlock), 0, s, sp);
   for (ReplayItem& it : H.pt_items) {
     void* params[] = {it.args};
-    (void)hipLaunchKernel(it.fn, it.grid, dim3(kBlock), params, 0, s);
+    (void)hipLaunchKernel(it.fn, it.grid, dim3(unsigned(it.block)), params, 0, s);
   }
   return ST_OK;
 }
@@ -1120,6 +1181,13 @@ bool try_pair_x(const Op& x, const Op& y, ReplayItem& it) {
 
 template <class T>
 bool pair_ops(const Op& x, const Op& y, ReplayItem& it) {
+  if (x.kind == kKStSolve && y.kind == kKStSolve) {
+    // two tiled solves: their own kernel, with its wider workgroups
+    if (!try_pair<T, BodyStSolve<T>, BodyStSolve<T>>(x, y, it)) return false;
+    it.fn = reinterpret_cast<const void*>(&k_two_solve<T>);
+    it.block = kSolveBlock;
+    return true;
+  }
   return try_pair_x<T, BodyStInit<T>>(x, y, it) || try_pair_x<T, BodyStCheb<T>>(x, y, it) ||
          try_pair_x<T, BodyCheb<T>>(x, y, it) || try_pair_x<T, BodySpmv<T>>(x, y, it);
 }
@@ -1130,6 +1198,7 @@ int build_items(Handle& H, const Program& prog) {
     ReplayItem it;
     it.fn = op.fn;
     it.grid = dim3(unsigned(op.gx), unsigned(op.gy));
+    it.block = block_of(op.kind);
     std::memset(it.args, 0, sizeof(it.args));
     std::memcpy(it.args, op.args, size_t(op.size));
     H.pt_items.push_back(it);
@@ -1280,11 +1349,15 @@ void group_kernels(std::vector<const void*>& out, std::integer_sequence<int, K..
 template <class T>
 const void* group_kernel(int kind) {
   static std::vector<const void*> table;
-  if (table.empty()) group_kernels<T>(table, std::make_integer_sequence<int, kKNumKinds>{});
+  if (table.empty()) {
+    group_kernels<T>(table, std::make_integer_sequence<int, kKNumKinds>{});
+    table[size_t(kKStSolve)] = reinterpret_cast<const void*>(&k_group_solve<T>);
+  }
   return table[size_t(kind)];
 }
 
-constexpr int kPairable[4] = {kKStInit, kKStCheb, kKCheb, kKSpmvT};
+constexpr int kNumPairable = 4;
+constexpr int kPairable[kNumPairable] = {kKStInit, kKStCheb, kKCheb, kKSpmvT};
 
 template <class T, int I, int J>
 const void* group2_entry() {
@@ -1293,7 +1366,7 @@ const void* group2_entry() {
 
 template <class T>
 const void* group2_kernel(int i, int j) {   // i < j: indices into kPairable
-  static const void* table[4][4] = {
+  static const void* table[kNumPairable][kNumPairable] = {
       {nullptr, group2_entry<T, 0, 1>(), group2_entry<T, 0, 2>(), group2_entry<T, 0, 3>()},
       {nullptr, nullptr, group2_entry<T, 1, 2>(), group2_entry<T, 1, 3>()},
       {nullptr, nullptr, nullptr, group2_entry<T, 2, 3>()},
@@ -1302,7 +1375,7 @@ const void* group2_kernel(int i, int j) {   // i < j: indices into kPairable
 }
 
 inline int pairable_index(int kind) {
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < kNumPairable; ++i)
     if (kPairable[i] == kind) return i;
   return -1;
 }
@@ -1331,7 +1404,7 @@ void launch_groups(const MultiArgs& step, hipStream_t s) {
       total += m.blocks;
     }
     void* params[] = {&g};
-    (void)hipLaunchKernel(fn, dim3(unsigned(total)), dim3(kBlock), params, 0, s);
+    (void)hipLaunchKernel(fn, dim3(unsigned(total)), dim3(unsigned(block_of(k1))), params, 0, s);
   };
   // pairable kinds two by two, the rest (and an odd one out) alone
   int pend = -1;
@@ -1545,6 +1618,7 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
   H.fu_deg = P.fu_deg;
   H.ca_deg = P.ca_deg;
   H.use_stencil = P.use_stencil;
+  H.sweep_fuse = P.prob.sweep_fuse == 1 ? 1 : 0;
   H.j_slabs = P.prob.j_slabs;
   H.sFu = P.sFu;
   H.sAu = P.sAu;

@@ -175,3 +175,31 @@ def test_pipelined_sweeps_match_single_stream(precision, inner):
         assert torch.equal(z, z2)
         out.append(z.cpu().numpy())
     assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,nt,fu,ca", [(12, 6, 4, 4), (12, 6, 7, 11), (20, 3, 5, 2), (3, 4, 1, 6)])
+def test_fused_sweep_solves_match_per_step(precision, n, nt, fu, ca):
+    """The tiled sweep solve (8 x 8 node tiles grown by halos in LDS, up to 4
+    Chebyshev steps in the first launch of a solve and 3 in each later one)
+    computes what one launch per step computes.  The meshes give ragged tiles
+    (F_u grids of 23 x 23, 39 x 39 and 5 x 5 nodes; C_A grids of 11 x 11,
+    19 x 19 and 2 x 2), the degrees one and several launches per solve; both
+    P_T^{-1} (recorded pipeline) and P_T^{-T} are compared."""
+    say(f"[gpu] fused vs per-step sweep solves {precision} n={n} nt={nt} fu={fu} ca={ca}")
+    from paper_2309_00768_amd import binding
+    cfg, ub, ab, ref = case(n, nt)
+    out = []
+    for fuse in (True, False):
+        plan = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision=precision,
+                            fu_solver=fu, ca_solver=ca, adjoint=True, sweep_fuse=fuse, sweep_chain=False)
+        sysg = binding.System(plan, "cuda:0")
+        r = np.random.default_rng(10).standard_normal(ref.N)
+        z = sysg.apply_precond(dev(r)).cpu().numpy()
+        zt = sysg.apply_precond(dev(r), transpose=True).cpu().numpy()
+        out.append((z, zt))
+    tol = 1e-13 if precision == "fp64" else 1e-6
+    say(f"    bitwise equal: {np.array_equal(out[0][0], out[1][0])}, {np.array_equal(out[0][1], out[1][1])}; "
+        f"rel {rel(out[0][0], out[1][0]):.1e}, {rel(out[0][1], out[1][1]):.1e}")
+    assert rel(out[0][0], out[1][0]) <= tol
+    assert rel(out[0][1], out[1][1]) <= tol

@@ -39,6 +39,21 @@ def test_plan_rejects_invalid_problem():
     assert binding.lib().st_plan_create(ctypes.byref(p), ctypes.byref(h)) == -1
 
 
+@pytest.mark.parametrize("field,value", [("j_slabs", 3), ("sweep_fuse", -1)])
+def test_plan_rejects_invalid_tuning(field, value):
+    n, nt = 2, 1
+    ub = np.zeros((nt, 2, (2 * n + 1) ** 2))
+    ab = np.zeros((nt, (n + 1) ** 2))
+    p = binding.StProblem()
+    p.n, p.nt, p.dt, p.mu, p.eta, p.mu0 = n, nt, 0.1, 0.01, 0.01, 1.0
+    p.ubar, p.abar = binding._dptr(ub), binding._dptr(ab)
+    h = ctypes.c_void_p()
+    assert binding.lib().st_plan_create(ctypes.byref(p), ctypes.byref(h)) == 0
+    binding.lib().st_plan_destroy(h)
+    setattr(p, field, value)
+    assert binding.lib().st_plan_create(ctypes.byref(p), ctypes.byref(h)) == -1
+
+
 def _compare(plan, ref, tol=1e-13):
     worst = 0.0
     for k in sorted({0, ref.nt // 2, ref.nt - 1}):
