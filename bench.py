@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of one J apply at the default workload from FETCH_SIZE / WRITE_SIZE
 # counter runs calibrated with a 1 GiB copy (profiles/pmc_cfg3_jacobian_fetch_write.md),
 # valid while the kernel source it measured is unchanged (digest of that source).
-JAC_COUNTERS = {"config": "cfg3", "source_sha256_16": "586580fa0a25caa9", "traffic_bytes": 3.243e9}
+JAC_COUNTERS = {"config": "cfg3", "j_slabs": 8, "source_sha256_16": "586580fa0a25caa9", "traffic_bytes": 3.243e9}
 
 
 def jacobian_kernel_digest():
@@ -104,14 +104,15 @@ def bench_batch(args, dev):
     t0 = time.perf_counter()
     for c in cfgs:
         ub, ab = inputs.state(c)
-        plan = binding.Plan(c.n, c.nt, c.dt, c.mu, c.eta, c.mu0, ub, ab, precision="fp32")
+        plan = binding.Plan(c.n, c.nt, c.dt, c.mu, c.eta, c.mu0, ub, ab, precision="fp32",
+                            autotune=not args.no_autotune)
         si = plan.solver_info()
         systems.append(binding.System(plan, dev))
         plan.close()
         rhs.append(torch.from_numpy(inputs.rhs(c, c.rhs_seeds[0])).to(dev))
         ntot += systems[-1].N
         log(f"setup {c.name}: n={c.n} Nt={c.nt} N={systems[-1].N}, inner degrees F_u {si[0]} C_A {si[1]} "
-            f"(kappa {si[2]:.1f}, {si[3]:.1f})")
+            f"(kappa {si[2]:.1f}, {si[3]:.1f}), launches {systems[-1].tuning()}")
     log(f"setup {time.perf_counter() - t0:.1f} s, {len(cfgs)} systems, N total {ntot}")
     batch = binding.Batch(systems, restart=30)
     lock, sep = batch.launch_counts()
@@ -268,6 +269,8 @@ def main():
     ap.add_argument("--no-separate", action="store_true", help="cfg4: skip the one-at-a-time comparison")
     ap.add_argument("--batch-budget", type=int, default=960, help="cfg4: FGMRES iterations per member")
     ap.add_argument("--no-fd", action="store_true", help="cfg5: skip the finite-difference check")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="default launch choices instead of timing them at st_create")
     ap.add_argument("--probe", choices=["jacobian"], default=None,
                     help="run only a few J applies and a copy of known size (for hardware-counter runs)")
     args = ap.parse_args()
@@ -293,7 +296,8 @@ def main():
         probe_jacobian(cfg, ub, ab, b, dev)
         return
     t0 = time.perf_counter()
-    plan32 = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp32")
+    tune = not args.no_autotune
+    plan32 = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp32", autotune=tune)
     N = plan32.ns * cfg.nt
     jbytes, nnz_state, nnz_const = jacobian_bytes(plan32, cfg.nt, N)
     fu_deg, ca_deg, _, _ = plan32.solver_info()
@@ -301,14 +305,15 @@ def main():
              f"(0 = SA-AMG V(1,1)), SA-AMG V(1,1) on K_p")
     sys32 = binding.System(plan32, dev)
     plan32.close()
-    log(f"setup fp32 {time.perf_counter() - t0:.1f} s, N={N}")
+    log(f"setup fp32 {time.perf_counter() - t0:.1f} s, N={N}, launches {sys32.tuning()}")
     sys64 = None
     if not args.no_fp64:
         t0 = time.perf_counter()
-        plan64 = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp64")
+        plan64 = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp64",
+                              autotune=tune)
         sys64 = binding.System(plan64, dev)
         plan64.close()
-        log(f"setup fp64 {time.perf_counter() - t0:.1f} s")
+        log(f"setup fp64 {time.perf_counter() - t0:.1f} s, launches {sys64.tuning()}")
     bt = torch.from_numpy(b).to(dev)
     x = torch.zeros_like(bt)
 
@@ -345,6 +350,7 @@ def main():
         "fgmres_iters": its / args.steps,
         "true_rel_residual": res,
         "precond_share": sum(i.precond_seconds for i in infos) / elapsed,
+        "launch_choices": {"fp32": sys32.tuning(), "autotuned": tune},
     }
     if sys64 is not None:
         info64 = solve(sys64)
@@ -356,14 +362,19 @@ def main():
         out["fp64_time_to_1e8_s"] = t64
         out["fp64_fgmres_iters"] = info64.iterations
         out["fp32_vs_fp64_speedup"] = t64 / (elapsed / args.steps)
+        out["launch_choices"]["fp64"] = sys64.tuning()
         log(f"fp64 precond: {info64.iterations} its, {t64:.3f} s")
     achieved = jbytes / jac_avg / 1e9
+    nv = sys32.tuning()["j_slabs"]
+    kernel = (f"k_spmv_slabs<{nv}, 4> (space-time Jacobian apply, {nv} slabs per wavefront)" if nv > 1 else
+              "k_spmv<double, double, double, 1> (space-time Jacobian apply, one slab per workgroup row)")
     traffic = None
-    if args.config == JAC_COUNTERS["config"] and jacobian_kernel_digest() == JAC_COUNTERS["source_sha256_16"]:
+    if (args.config == JAC_COUNTERS["config"] and nv == JAC_COUNTERS["j_slabs"]
+            and jacobian_kernel_digest() == JAC_COUNTERS["source_sha256_16"]):
         traffic = JAC_COUNTERS["traffic_bytes"]
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                       "kernel": "k_spmv_slabs<8, 4> (space-time Jacobian apply, 8 slabs per wavefront)",
+                       "kernel": kernel,
                        "bytes_per_launch": jbytes, "avg_launch_ms": jac_avg * 1e3, "launches": jac_n,
                        "nnz_state_per_slab": nnz_state, "nnz_shared": nnz_const}
     if not args.no_cpu:

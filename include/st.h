@@ -115,6 +115,14 @@ typedef struct st_problem {
                          by halos held in LDS (up to 4 steps in the first
                          launch of a solve, 3 in each later one; bitwise the
                          same result, slower on the measured workloads)     */
+  int autotune;       /* 1: st_create times, on this system's operators, the
+                         launch choices that leave every result bitwise the
+                         same (slabs per wavefront of the J apply when j_slabs
+                         is 0; rows per workgroup of the sweep step kernels;
+                         one launch per sweep step or the tiled solve) and
+                         keeps the fastest (st_tuning reports them); 0: the
+                         given or default choices                          */
+  int reserved[1];
   double inner_reduction; /* auto inner solver of F_u,k: target error reduction
                              per spatial solve (0: 0.3; degree at least 4)    */
   double ca_reduction;    /* auto inner solver of C_A,k: target reduction (0: 0.3;
@@ -257,6 +265,12 @@ int st_batch_destroy(st_batch* b);
 
 /* Sizes of a created system: N, Ns, Nt. */
 int st_sizes(const st_handle* h, int64_t* n_total, int* ns, int* nt);
+
+/* Launch choices in effect for a created system (tuned when
+   st_problem.autotune = 1): slabs per wavefront of the J apply, rows per
+   workgroup of the sweep step kernels, and 1 if the sweep solves run as tiled
+   multi-step launches.  Any pointer may be NULL. */
+int st_tuning(const st_handle* h, int* j_slabs, int* step_rows, int* sweep_fuse);
 
 const char* st_error_string(int code);
 

@@ -35,6 +35,7 @@ class StProblem(ctypes.Structure):
         ("adjoint", ctypes.c_int), ("j_lanes", ctypes.c_int), ("sweep_format", ctypes.c_int),
         ("single_stream", ctypes.c_int), ("sweep_chunk", ctypes.c_int), ("sweep_chain", ctypes.c_int),
         ("j_slabs", ctypes.c_int), ("sweep_fuse", ctypes.c_int),
+        ("autotune", ctypes.c_int), ("reserved", ctypes.c_int * 1),
         ("inner_reduction", ctypes.c_double), ("ca_reduction", ctypes.c_double),
     ]
 
@@ -59,7 +60,7 @@ EXPORTED = [
     "st_plan_solver_info",
     "st_plan_destroy", "st_create", "st_destroy", "st_apply_jacobian", "st_apply_jacobian_t",
     "st_apply_precond", "st_apply_precond_t", "st_apply_initial_coupling", "st_fgmres_solve", "st_adjoint_solve",
-    "st_sizes", "st_batch_create", "st_batch_workspace_size", "st_batch_upload", "st_batch_launch_counts",
+    "st_sizes", "st_tuning", "st_batch_create", "st_batch_workspace_size", "st_batch_upload", "st_batch_launch_counts",
     "st_fgmres_solve_batched", "st_batch_destroy",
     "st_error_string",
 ]
@@ -90,6 +91,7 @@ def _load(path=LIB_PATH):
         "st_fgmres_solve": ([vp, vp, vp, ctypes.POINTER(StOpts), ctypes.POINTER(StInfo), vp], ctypes.c_int),
         "st_adjoint_solve": ([vp, vp, vp, ctypes.POINTER(StOpts), ctypes.POINTER(StInfo), vp], ctypes.c_int),
         "st_sizes": ([vp, i64p, ip, ip], ctypes.c_int),
+        "st_tuning": ([vp, ip, ip, ip], ctypes.c_int),
         "st_batch_create": ([ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
         "st_batch_workspace_size": ([vp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "st_batch_upload": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
@@ -139,7 +141,8 @@ class Plan:
     def __init__(self, n, nt, dt, mu, eta, mu0, ubar, abar, jbar=None, precision="fp64", inner="amg",
                  inner_iters=0, mass_iters=0, cheb_degree=0, max_restart=0, sell_sigma=0, adjoint=False,
                  fu_solver=0, ca_solver=0, inner_reduction=0.0, j_lanes=0, ca_reduction=0.0, sweep_format=0,
-                 single_stream=False, sweep_chunk=0, sweep_chain=True, j_slabs=0, sweep_fuse=False):
+                 single_stream=False, sweep_chunk=0, sweep_chain=True, j_slabs=0, sweep_fuse=False,
+                 autotune=False):
         self._ub = np.ascontiguousarray(ubar, dtype=np.float64)
         self._ab = np.ascontiguousarray(abar, dtype=np.float64)
         assert self._ub.shape == (nt, 2, (2 * n + 1) ** 2) and self._ab.shape == (nt, (n + 1) ** 2)
@@ -158,6 +161,7 @@ class Plan:
         p.sweep_chain = 0 if sweep_chain else -1
         p.j_slabs = j_slabs
         p.sweep_fuse = 1 if sweep_fuse else 0
+        p.autotune = int(autotune)
         self.problem = p
         self.n, self.nt = n, nt
         h = ctypes.c_void_p()
@@ -287,6 +291,13 @@ class System:
         rc = _check(fn(self.ptr, self._vec(b), self._vec(x), ctypes.byref(o), ctypes.byref(info),
                        _stream_ptr(stream)), "solve")
         return x, info, rc, hist[:min(info.iterations + 1, hist.size)]
+
+    def tuning(self):
+        """Launch choices in effect (``st_tuning``): J slabs per wavefront, sweep
+        step rows per workgroup, tiled sweep solves."""
+        js, rows, fuse = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().st_tuning(self.ptr, ctypes.byref(js), ctypes.byref(rows), ctypes.byref(fuse)), "st_tuning")
+        return {"j_slabs": js.value, "step_rows": rows.value, "sweep_fuse": bool(fuse.value)}
 
     def close(self):
         if getattr(self, "ptr", None):

@@ -180,6 +180,10 @@ static int build_plan(Plan& P, std::string& err) {
     err = "sweep_fuse must be 0 or 1";
     return ST_EINVAL;
   }
+  if (pr.autotune != 0 && pr.autotune != 1) {
+    err = "autotune must be 0 or 1";
+    return ST_EINVAL;
+  }
   int rc = assemble_blocks(pr, P.blk, err);
   if (rc) return rc;
   form_wave_operator(P.blk);

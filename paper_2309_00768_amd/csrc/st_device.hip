@@ -72,6 +72,7 @@ struct Handle {
   int fp32 = 0, exact = 0, inner_iters = 1, mass_iters = 12, max_restart = 30, adjoint = 0;
   int fu_deg = 0, ca_deg = 0, use_stencil = 0;
   int sweep_fuse = 0;              // stencil sweep solves in tiled launches of several steps
+  int step_rows = 0;               // rows per workgroup of the sweep step kernels (0: by precision)
   char* base = nullptr;
   WsLayout L;
   DGroup J, JT, MA, Mj, Mp, FA, FAt, Fp, Fpt, KjA, KjAt, Bt, B, Zj, Zjt, ZAt, Mu, C1, C1t, MA64;
@@ -499,7 +500,8 @@ void sweep_step_stencil(Ctx& c, Handle& H, DAmg& a, const StencilOp& A, const St
   ia.guess = guess ? 1 : 0;
   ia.g1 = g1;
   ia.g2 = g2;
-  ia.rpb = st_rows<T>();
+  const int rpb = H.step_rows > 0 ? H.step_rows : st_rows<T>();
+  ia.rpb = rpb;
   if (H.sweep_fuse && solve_fusable(A)) {
     StSolveArgs<T> sa;
     std::memset(&sa, 0, sizeof(sa));
@@ -527,7 +529,7 @@ void sweep_step_stencil(Ctx& c, Handle& H, DAmg& a, const StencilOp& A, const St
     }
     return;
   }
-  const dim3 grid(unsigned((rows + st_rows<T>() - 1) / st_rows<T>()));
+  const dim3 grid(unsigned((rows + rpb - 1) / rpb));
   if (role == 1) emit(c, kKStInit, grid, &k_st_init<T, 1>, ia);
   else emit(c, kKStInit, grid, &k_st_init<T, 2>, ia);
   StChebArgs<T> ca;
@@ -538,7 +540,7 @@ void sweep_step_stencil(Ctx& c, Handle& H, DAmg& a, const StencilOp& A, const St
   ca.rows = rows;
   ca.r = r;
   ca.x = x;
-  ca.rpb = st_rows<T>();
+  ca.rpb = rpb;
   T* d[2] = {d0, d1};
   const double sigma = theta / delta;
   double rho_prev = 1.0 / sigma, rho = rho_prev;
@@ -1238,6 +1240,71 @@ int build_pipeline(Handle& H) {
   return ST_OK;
 }
 
+// =========================================================== autotune ===
+// Times, on this system's own operators, the launch choices that leave every
+// result bitwise the same, and keeps the fastest: slabs per wavefront of the
+// J apply (when not given), rows per workgroup of the sweep step kernels, and
+// one launch per sweep step against the tiled multi-step solve.  The inputs
+// are two zeroed Krylov columns (the kernels' timing does not depend on the
+// values).
+int autotune(Handle& H, hipStream_t s, bool pipeline) {
+  const int64_t N = int64_t(H.d.ns) * H.d.nt;
+  double* x = at<double>(H.base, H.L.V);
+  double* y = x + N;
+  if (hipMemsetAsync(x, 0, size_t(N) * sizeof(double), s) != hipSuccess) return ST_EHIP;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return ST_EHIP;
+  Ctx c{s, nullptr};
+  int rc = ST_OK;
+  auto timed = [&](auto&& fn, int reps) -> float {
+    fn();
+    fn();
+    (void)hipEventRecord(e0, s);
+    for (int i = 0; i < reps; ++i) fn();
+    (void)hipEventRecord(e1, s);
+    float ms = 0.0f;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = ST_EHIP;
+    return ms / float(reps);
+  };
+  if (H.j_slabs == 0 && H.J.lanes == 1) {
+    int best = 8;
+    float tbest = 1e30f;
+    for (int nv : {1, 4, 8}) {
+      H.j_slabs = nv;
+      const float t = timed([&] { apply_J(H, x, y, c, false, 1.0, nullptr); }, 5);
+      if (t < tbest) {
+        tbest = t;
+        best = nv;
+      }
+    }
+    H.j_slabs = best;
+  }
+  if (rc == ST_OK && H.use_stencil) {
+    struct Cand { int fuse, rows; };
+    const Cand cands[] = {{0, 64}, {0, 128}, {0, 256}, {1, 0}};
+    Cand best = cands[0];
+    float tbest = 1e30f;
+    for (const Cand& cd : cands) {
+      H.sweep_fuse = cd.fuse;
+      H.step_rows = cd.rows;
+      if (pipeline && (rc = build_pipeline(H)) != ST_OK) break;
+      const float t = timed([&] { (void)apply_precond(H, x, y, c, false); }, 4);
+      if (rc != ST_OK) break;
+      if (t < tbest) {
+        tbest = t;
+        best = cd;
+      }
+    }
+    H.sweep_fuse = best.fuse;
+    H.step_rows = best.rows;
+    if (rc == ST_OK && pipeline) rc = build_pipeline(H);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == ST_OK && hipGetLastError() != hipSuccess) rc = ST_EHIP;
+  return rc;
+}
+
 // ============================================================ batches ===
 // Lockstep FGMRES over several systems.  Each system's launches are recorded
 // once (the preconditioner as its two programs reading the Krylov column
@@ -1698,10 +1765,11 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
   // About 16 chunks of slabs: the F_u sweep of a chunk starts as soon as its
   // part of the C_A sweep is done.
   H.chunk = P.chunk;
-  if (P.prob.single_stream == 0) {
+  {
     int rc = ST_OK;
     try {
-      rc = build_pipeline(H);
+      if (P.prob.single_stream == 0) rc = build_pipeline(H);
+      if (rc == ST_OK && P.prob.autotune == 1) rc = autotune(H, s, P.prob.single_stream == 0);
     } catch (...) {
       rc = ST_ENOMEM;
     }
@@ -1727,6 +1795,15 @@ int st_sizes(const st_handle* h, int64_t* n_total, int* ns, int* nt) {
   if (n_total) *n_total = int64_t(h->h.d.ns) * h->h.d.nt;
   if (ns) *ns = h->h.d.ns;
   if (nt) *nt = h->h.d.nt;
+  return ST_OK;
+}
+
+int st_tuning(const st_handle* h, int* j_slabs, int* step_rows, int* sweep_fuse) {
+  if (!h) return ST_EINVAL;
+  const st::Handle& H = h->h;
+  if (j_slabs) *j_slabs = H.J.lanes != 1 ? 1 : (H.j_slabs == 0 ? 8 : H.j_slabs);
+  if (step_rows) *step_rows = H.step_rows > 0 ? H.step_rows : (H.fp32 ? st::st_rows<float>() : st::st_rows<double>());
+  if (sweep_fuse) *sweep_fuse = H.sweep_fuse;
   return ST_OK;
 }
 

@@ -203,3 +203,27 @@ def test_fused_sweep_solves_match_per_step(precision, n, nt, fu, ca):
         f"rel {rel(out[0][0], out[1][0]):.1e}, {rel(out[0][1], out[1][1]):.1e}")
     assert rel(out[0][0], out[1][0]) <= tol
     assert rel(out[0][1], out[1][1]) <= tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_autotuned_launches_give_the_same_results(precision):
+    """st_create with autotune = 1 times the J slabs per wavefront, the sweep
+    step rows per workgroup and the tiled solve on the system itself; whatever
+    it picks, J x, P_T^{-1} r and P_T^{-T} r are bitwise those of the default
+    launches."""
+    say(f"[gpu] autotuned launches {precision}")
+    from paper_2309_00768_amd import binding
+    cfg, ub, ab, ref = case(12, 6)
+    out = []
+    for tune in (False, True):
+        plan = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision=precision,
+                            adjoint=True, autotune=tune)
+        sysg = binding.System(plan, "cuda:0")
+        t = sysg.tuning()
+        say(f"    autotune={tune}: {t}")
+        assert t["j_slabs"] in (1, 4, 8) and t["step_rows"] in (64, 128, 256)
+        r = np.random.default_rng(11).standard_normal(ref.N)
+        out.append([sysg.apply_jacobian(dev(r)).cpu().numpy(), sysg.apply_precond(dev(r)).cpu().numpy(),
+                    sysg.apply_precond(dev(r), transpose=True).cpu().numpy()])
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)

@@ -39,7 +39,7 @@ def test_plan_rejects_invalid_problem():
     assert binding.lib().st_plan_create(ctypes.byref(p), ctypes.byref(h)) == -1
 
 
-@pytest.mark.parametrize("field,value", [("j_slabs", 3), ("sweep_fuse", -1)])
+@pytest.mark.parametrize("field,value", [("j_slabs", 3), ("sweep_fuse", -1), ("autotune", 2)])
 def test_plan_rejects_invalid_tuning(field, value):
     n, nt = 2, 1
     ub = np.zeros((nt, 2, (2 * n + 1) ** 2))
