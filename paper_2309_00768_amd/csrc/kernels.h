@@ -161,7 +161,23 @@ __global__ ST_LATENCY_KERNEL void k_spmv(SpmvArgs<T, TX> a) {
 struct SpmvSlabsArgs {
   SpmvArgs<double, double> a;
   int nvec;   // number of slabs
+  int nbx;    // workgroups along the slices (4 slices each)
+  int nblk;   // nbx x slab groups; the grid is nblk rounded up to a multiple of 8
 };
+
+// Workgroup b of the (1-D) grid -> (slice block, slab group), so that each of
+// the 8 XCDs (which take workgroups round robin) runs one contiguous range of
+// blocks, slab group by slab group: the x lines a slice gathers are then
+// fetched into that XCD's L2 once for the neighbouring slices too, instead of
+// once per XCD.  A bijection of [0, round_up(nblk, 8)); false for padding.
+__device__ inline bool slabs_block(const SpmvSlabsArgs& sa, int b, int& bx, int& by) {
+  const int per = (sa.nblk + 7) / 8;
+  const int logical = (b % 8) * per + b / 8;
+  if (logical >= sa.nblk) return false;
+  bx = logical % sa.nbx;
+  by = logical / sa.nbx;
+  return true;
+}
 
 template <int NV, int B = 4>
 __device__ inline void spmv_slabs_body(const SpmvSlabsArgs& sa, int bx, int by) {
@@ -241,7 +257,8 @@ __device__ inline void spmv_slabs_body(const SpmvSlabsArgs& sa, int bx, int by) 
 // Bandwidth-bound: no cap on the waves per SIMD (unlike the latency kernels).
 template <int NV, int B = 4>
 __global__ __launch_bounds__(kBlock) void k_spmv_slabs(SpmvSlabsArgs a) {
-  spmv_slabs_body<NV, B>(a, blockIdx.x, blockIdx.y);
+  int bx, by;
+  if (slabs_block(a, blockIdx.x, bx, by)) spmv_slabs_body<NV, B>(a, bx, by);
 }
 
 // Fused Chebyshev-Jacobi step for A x = b (A one SELL segment), per vector v.

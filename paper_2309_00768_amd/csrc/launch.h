@@ -269,11 +269,17 @@ template <class T> struct KB<kKCopySmall, T> {
 };
 template <class T> struct KB<kKSpmvSlabs4, T> {
   using Args = SpmvSlabsArgs;
-  __device__ static void run(const Args& a, int b, int gx) { spmv_slabs_body<4>(a, b % gx, b / gx); }
+  __device__ static void run(const Args& a, int b, int) {
+    int bx, by;
+    if (slabs_block(a, b, bx, by)) spmv_slabs_body<4>(a, bx, by);
+  }
 };
 template <class T> struct KB<kKSpmvSlabs8, T> {
   using Args = SpmvSlabsArgs;
-  __device__ static void run(const Args& a, int b, int gx) { spmv_slabs_body<8>(a, b % gx, b / gx); }
+  __device__ static void run(const Args& a, int b, int) {
+    int bx, by;
+    if (slabs_block(a, b, bx, by)) spmv_slabs_body<8>(a, bx, by);
+  }
 };
 template <class T> struct KB<kKSetPtrs, T> {
   using Args = SetPtrsArgs;

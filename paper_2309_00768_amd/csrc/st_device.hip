@@ -855,7 +855,9 @@ void apply_J(Handle& H, const double* x, double* y, Ctx& c, bool transpose, doub
   a.a.y = y;
   a.a.ystride = ns;
   a.nvec = nt;
-  const dim3 grid((g.nslices + 3) / 4, (nt + nv - 1) / nv);
+  a.nbx = (g.nslices + 3) / 4;
+  a.nblk = a.nbx * ((nt + nv - 1) / nv);
+  const dim3 grid(unsigned((a.nblk + 7) / 8 * 8));
   if (nv == 8) emit(c, kKSpmvSlabs8, grid, &k_spmv_slabs<8>, a);
   else emit(c, kKSpmvSlabs4, grid, &k_spmv_slabs<4>, a);
 }
