@@ -91,8 +91,8 @@ struct Handle {
   // built once; the argument blocks live in the workspace, the input and
   // output vectors are read from two device slots.
   int j_slabs = 0;                 // slabs per wavefront of the J apply (0: 8)
-  int pipeline = 0;
-  std::vector<ReplayItem> pt_items;
+  int pipeline = 0, pipeline_t = 0;
+  std::vector<ReplayItem> pt_items, pt_items_t;   // forward and transposed applies
   const double** rslot = nullptr;
   double** zslot = nullptr;
 };
@@ -716,8 +716,16 @@ int precond_forward(Handle& H, const double* r, double* z, Ctx& c, Ctx& ca, cons
 }
 
 // ================================================ P_T^{-T} (adjoint) ====
+// z = P_T^{-T} r: the backward F_u^T sweep first, then the pressure part and,
+// slab by slab, the current and the backward C_A^T sweep.  As for the forward
+// apply, `ca` receives program a (split, the F_u^T sweep chunk by chunk from
+// the last slab, then the pressure part) and `c` program b (per chunk, once
+// that chunk of x_u is done: y_j = M_j^{-1}(r_j - Z_j^T x_u), the right-hand
+// side h = r_A - Z_A^T x_u - K_jA^T y_j and the C_A^T sweep; then F_A^T, M_A^{-1}
+// and, after all of a, the join).  Not recording, both are the caller's stream.
 template <class T>
-int precond_transpose(Handle& H, const double* r, double* z, Ctx& c) {
+int precond_transpose(Handle& H, const double* r, double* z, Ctx& c, Ctx& ca, const double* const* rslot = nullptr,
+                      double* const* zslot = nullptr) {
   if (!H.adjoint) return ST_EINVAL;
   const Dims& d = H.d;
   const int nt = d.nt;
@@ -728,6 +736,7 @@ int precond_transpose(Handle& H, const double* r, double* z, Ctx& c) {
   T* rj = at<T>(B, L.rj); T* yj = at<T>(B, L.yj);
   T* ra = at<T>(B, L.ra); T* cA = at<T>(B, L.wA); T* f = at<T>(B, L.sA); T* yA = at<T>(B, L.yA);
   T* mr = at<T>(B, L.mr); T* md0 = at<T>(B, L.md0); T* md1 = at<T>(B, L.md1);
+  T* mr2 = at<T>(B, L.mr2); T* md02 = at<T>(B, L.md02); T* md12 = at<T>(B, L.md12);
   double* psum = at<double>(B, L.psum);
   const int o2 = d.off[2], o3 = d.off[3], o4 = d.off[4], ns = d.ns;
   const int nu = d.nu, np = d.np, nj = d.nj, na = d.na;
@@ -735,85 +744,117 @@ int precond_transpose(Handle& H, const double* r, double* z, Ctx& c) {
   const int vc = H.exact ? H.inner_iters : 1;
   const int mit = H.mass_iters;
   const double mlo = 0.24, mhi = 2.3, mth = 0.5 * (mhi + mlo), mde = 0.5 * (mhi - mlo);
+  const bool rec = c.recording();
+  const int C = rec ? std::max(1, std::min(H.chunk, nt)) : nt;
+  const int nch = (nt + C - 1) / C;
+  auto mark = [&](Ctx& cx, int need) { cx.need = need; };
 
-  slab_sums_d(c, r, int64_t(ns), o2, np, nullptr, psum, nt);
+  slab_sums_d(ca, r, int64_t(ns), o2, np, nullptr, psum, nt, rslot);
   {
-    SplitArgs<T> a{r, ns, nt, o2, o3, o4, psum, ru, rp, rj, ra, nullptr};
-    emit(c, kKSplit, dim3(grid_for(int64_t(ns) * nt)), &k_split<T>, a);
+    SplitArgs<T> a{r, ns, nt, o2, o3, o4, psum, ru, rp, rj, ra, rslot};
+    emit(ca, kKSplit, dim3(grid_for(int64_t(ns) * nt)), &k_split<T>, a);
   }
-  // x_u = F_u^{-T} r_u, backward in time: F_uk^T x^k = r^k + (1/dt) M_u x^{k+1}
-  for (int k = nt - 1; k >= 0; --k) {
-    Seg<T> sg = seg<T>(H.Mu, 0, 0, 0, xu + int64_t(k + 1) * nu, 0, 0, 0, 1, 1.0 / dt);
-    if (H.use_stencil && H.fu_deg > 0)
-      sweep_step_stencil<T>(c, H, H.amgFuT, H.sFuT, k + 1 < nt ? &H.sAuT : nullptr, k, -1.0,
-                            xu + int64_t(k + 1) * nu, nullptr, 0, 0.0, nullptr, ru + int64_t(k) * nu,
-                            xu + int64_t(k) * nu, k, H.fu_deg, 1, k + 1 < nt, 1.0, 0.0);
-    else
-      sweep_step<T>(c, H.amgFuT, H.Mu, k + 1 < nt ? 1 : 0, &sg, ru + int64_t(k) * nu, xu + int64_t(k) * nu, k,
-                    H.fu_deg, vc);
+  // x_u = F_u^{-T} r_u, backward in time: F_uk^T x^k = r^k + (1/dt) M_u x^{k+1};
+  // chunk ch holds slabs [k0, k1) counted from the last one.
+  std::vector<int> a_end(size_t(nch), 0);
+  auto chunk = [&](int ch, int& k0, int& k1) {
+    k1 = nt - ch * C;
+    k0 = std::max(0, k1 - C);
+  };
+  for (int ch = 0; ch < nch; ++ch) {
+    int k0, k1;
+    chunk(ch, k0, k1);
+    for (int k = k1 - 1; k >= k0; --k) {
+      Seg<T> sg = seg<T>(H.Mu, 0, 0, 0, xu + int64_t(k + 1) * nu, 0, 0, 0, 1, 1.0 / dt);
+      if (H.use_stencil && H.fu_deg > 0)
+        sweep_step_stencil<T>(ca, H, H.amgFuT, H.sFuT, k + 1 < nt ? &H.sAuT : nullptr, k, -1.0,
+                              xu + int64_t(k + 1) * nu, nullptr, 0, 0.0, nullptr, ru + int64_t(k) * nu,
+                              xu + int64_t(k) * nu, k, H.fu_deg, 1, k + 1 < nt, 1.0, 0.0);
+      else
+        sweep_step<T>(ca, H.amgFuT, H.Mu, k + 1 < nt ? 1 : 0, &sg, ru + int64_t(k) * nu, xu + int64_t(k) * nu, k,
+                      H.fu_deg, vc);
+    }
+    a_end[size_t(ch)] = rec ? int(ca.rec->size()) : 0;
   }
-  // x_p = S_p^{-T}(r_p - B x_u),  S_p^{-T} = -K_p^{-1} F_p^T M_p^{-1}
-  spmv1<T>(c, H.B, nt, 0, 0, xu, nu, -1.0, rp, 1.0, rp, np);
-  slab_sums_t<T>(c, rp, int64_t(np), np, nullptr, psum, nt);
-  slab_shift<T>(c, rp, int64_t(np), np, nt, psum, 1.0 / np);
-  cheb_solve<T>(c, H.Mp, nt, 0, 0, static_cast<const T*>(H.dMp), 0, nullptr, mth, mde, rp, q, mr, md0, md1, np, mit,
-                0, false);
+  // x_p = S_p^{-T}(r_p - B x_u),  S_p^{-T} = -K_p^{-1} F_p^T M_p^{-1}  (program a)
+  spmv1<T>(ca, H.B, nt, 0, 0, xu, nu, -1.0, rp, 1.0, rp, np);
+  slab_sums_t<T>(ca, rp, int64_t(np), np, nullptr, psum, nt);
+  slab_shift<T>(ca, rp, int64_t(np), np, nt, psum, 1.0 / np);
+  cheb_solve<T>(ca, H.Mp, nt, 0, 0, static_cast<const T*>(H.dMp), 0, nullptr, mth, mde, rp, q, mr, md0, md1, np,
+                mit, 0, false);
   {
     Seg<T> sg[2] = {seg<T>(H.Fpt, 0, 0, 1, q, np, 0, 0, nt, 1.0), seg<T>(H.Fpt, 1, 0, 0, q, np, 1, 0, nt - 1, 1.0)};
-    spmv<T, T>(c, H.Fpt, nt, 2, sg, nullptr, np, 0.0, t, np);
+    spmv<T, T>(ca, H.Fpt, nt, 2, sg, nullptr, np, 0.0, t, np);
   }
-  slab_sums_t<T>(c, t, int64_t(np), np, nullptr, psum, nt);
-  slab_shift<T>(c, t, int64_t(np), np, nt, psum, 1.0 / np);
-  amg_solve<T>(c, H.amgKp, nt, 0, 0, xp, t, vc);
-  // y_j = M_j^{-1}(r_j - Z_j^T x_u)
-  spmv1<T>(c, H.Zjt, nt, 0, 1, xu, nu, -1.0, rj, 1.0, rj, nj);
-  cheb_solve<T>(c, H.Mj, nt, 0, 0, static_cast<const T*>(H.dMj), 0, nullptr, mth, mde, rj, yj, mr, md0, md1, nj, mit,
-                0, false);
-  // h = r_A - Z_A^T x_u - K_jA^T y_j  (in ra)
-  spmv1<T>(c, H.ZAt, nt, 0, 1, xu, nu, -1.0, ra, 1.0, ra, na);
-  spmv1<T>(c, H.KjAt, nt, 0, 0, yj, nj, -1.0, ra, 1.0, ra, na);
-  // c = C_A^{-T} h backward: C0_k^T c^k = h^k + (1/dt) C1_k^T c^{k+1} - (1/dt^2) C2^T c^{k+2}
-  for (int k = nt - 1; k >= 0; --k) {
-    Seg<T> sg[2];
-    int nsg = 0;
-    if (k + 1 < nt) sg[nsg++] = seg<T>(H.C1t, 0, k, 0, cA + int64_t(k + 1) * na, 0, 0, 0, 1, 1.0 / dt);
-    if (k + 2 < nt) sg[nsg++] = seg<T>(H.C1t, 1, 0, 0, cA + int64_t(k + 2) * na, 0, 0, 0, 1, -1.0 / (dt * dt));
-    if (H.use_stencil && H.ca_deg > 0)
-      sweep_step_stencil<T>(c, H, H.amgC0T, H.sC0T, k + 1 < nt ? &H.sCPT : nullptr, k, 1.0, cA + int64_t(k + 1) * na,
-                            k + 2 < nt ? &H.sCQT : nullptr, k, 1.0, cA + int64_t(k + 2) * na, ra + int64_t(k) * na,
-                            cA + int64_t(k) * na, k, H.ca_deg, 2, k + 1 < nt, k + 2 < nt ? 2.0 : 1.0,
-                            k + 2 < nt ? -1.0 : 0.0);
-    else
-      sweep_step<T>(c, H.amgC0T, H.C1t, nsg, sg, ra + int64_t(k) * na, cA + int64_t(k) * na, k, H.ca_deg, vc);
+  slab_sums_t<T>(ca, t, int64_t(np), np, nullptr, psum, nt);
+  slab_shift<T>(ca, t, int64_t(np), np, nt, psum, 1.0 / np);
+  amg_solve<T>(ca, H.amgKp, nt, 0, 0, xp, t, vc);
+  const int a_all = rec ? int(ca.rec->size()) : 0;
+  // per chunk (program b): y_j = M_j^{-1}(r_j - Z_j^T x_u); h = r_A - Z_A^T x_u -
+  // K_jA^T y_j (in ra); c = C_A^{-T} h backward:
+  // C0_k^T c^k = h^k + (1/dt) C1_k^T c^{k+1} - (1/dt^2) C2^T c^{k+2}
+  for (int ch = 0; ch < nch; ++ch) {
+    int k0, k1;
+    chunk(ch, k0, k1);
+    const int kc = k1 - k0;
+    mark(c, a_end[size_t(ch)]);
+    spmv1<T>(c, H.Zjt, kc, k0, 1, xu + int64_t(k0) * nu, nu, -1.0, rj + int64_t(k0) * nj, 1.0,
+             rj + int64_t(k0) * nj, nj);
+    cheb_solve<T>(c, H.Mj, kc, 0, 0, static_cast<const T*>(H.dMj), 0, nullptr, mth, mde, rj + int64_t(k0) * nj,
+                  yj + int64_t(k0) * nj, mr2 + int64_t(k0) * nj, md02 + int64_t(k0) * nj, md12 + int64_t(k0) * nj, nj,
+                  mit, 0, false);
+    spmv1<T>(c, H.ZAt, kc, k0, 1, xu + int64_t(k0) * nu, nu, -1.0, ra + int64_t(k0) * na, 1.0,
+             ra + int64_t(k0) * na, na);
+    spmv1<T>(c, H.KjAt, kc, 0, 0, yj + int64_t(k0) * nj, nj, -1.0, ra + int64_t(k0) * na, 1.0,
+             ra + int64_t(k0) * na, na);
+    for (int k = k1 - 1; k >= k0; --k) {
+      Seg<T> sg[2];
+      int nsg = 0;
+      if (k + 1 < nt) sg[nsg++] = seg<T>(H.C1t, 0, k, 0, cA + int64_t(k + 1) * na, 0, 0, 0, 1, 1.0 / dt);
+      if (k + 2 < nt) sg[nsg++] = seg<T>(H.C1t, 1, 0, 0, cA + int64_t(k + 2) * na, 0, 0, 0, 1, -1.0 / (dt * dt));
+      if (H.use_stencil && H.ca_deg > 0)
+        sweep_step_stencil<T>(c, H, H.amgC0T, H.sC0T, k + 1 < nt ? &H.sCPT : nullptr, k, 1.0,
+                              cA + int64_t(k + 1) * na, k + 2 < nt ? &H.sCQT : nullptr, k, 1.0,
+                              cA + int64_t(k + 2) * na, ra + int64_t(k) * na, cA + int64_t(k) * na, k, H.ca_deg, 2,
+                              k + 1 < nt, k + 2 < nt ? 2.0 : 1.0, k + 2 < nt ? -1.0 : 0.0);
+      else
+        sweep_step<T>(c, H.amgC0T, H.C1t, nsg, sg, ra + int64_t(k) * na, cA + int64_t(k) * na, k, H.ca_deg, vc);
+    }
   }
   // f = F_A^T c; y_A = M_A^{-1} f
   {
     Seg<T> sg[2] = {seg<T>(H.FAt, 0, 0, 1, cA, na, 0, 0, nt, 1.0), seg<T>(H.FAt, 1, 0, 0, cA, na, 1, 0, nt - 1, 1.0)};
     spmv<T, T>(c, H.FAt, nt, 2, sg, nullptr, na, 0.0, f, na);
   }
-  cheb_solve<T>(c, H.MA, nt, 0, 0, static_cast<const T*>(H.dMA), 0, nullptr, mth, mde, f, yA, mr, md0, md1, na, mit,
-                0, false);
+  cheb_solve<T>(c, H.MA, nt, 0, 0, static_cast<const T*>(H.dMA), 0, nullptr, mth, mde, f, yA, mr2, md02, md12, na,
+                mit, 0, false);
+  // join with the pressure normalisation, once program a is done
+  mark(c, a_all);
   slab_sums_t<T>(c, xp, int64_t(np), np, H.mp_rowsum, psum + nt, nt);
   {
-    JoinArgs<T> a{z, ns, nt, o2, o3, o4, xu, xp, -1.0, psum + nt, H.msum, yj, yA, nullptr};
+    JoinArgs<T> a{z, ns, nt, o2, o3, o4, xu, xp, -1.0, psum + nt, H.msum, yj, yA, zslot};
     emit(c, kKJoin, dim3(grid_for(int64_t(ns) * nt)), &k_join<T>, a);
   }
   return ST_OK;
 }
 
-// Records the forward P_T^{-1} as programs a and b reading r, z from the slots.
-int record_precond(Handle& H, Program& prog, const double* const* rslot, double* const* zslot) {
+// Records P_T^{-1} (or P_T^{-T}) as programs a and b reading r, z from the slots.
+int record_precond(Handle& H, Program& prog, const double* const* rslot, double* const* zslot,
+                   bool transpose = false) {
   Ctx cb{nullptr, &prog.b, &prog.dep, 0};
   Ctx ca{nullptr, &prog.a, nullptr, 0};
+  if (transpose)
+    return H.fp32 ? precond_transpose<float>(H, nullptr, nullptr, cb, ca, rslot, zslot)
+                  : precond_transpose<double>(H, nullptr, nullptr, cb, ca, rslot, zslot);
   return H.fp32 ? precond_forward<float>(H, nullptr, nullptr, cb, ca, rslot, zslot)
                 : precond_forward<double>(H, nullptr, nullptr, cb, ca, rslot, zslot);
 }
 
 // Replay of the recorded forward P_T^{-1} on stream s.
-int replay_precond(Handle& H, const double* r, double* z, hipStream_t s) {
+int replay_precond(Handle& H, const double* r, double* z, hipStream_t s, bool transpose = false) {
   SetPtrsArgs sp{H.rslot, H.zslot, r, z};
   hipLaunchKernelGGL(k_set_ptrs, dim3(1), dim3(kBlock), 0, s, sp);
-  for (ReplayItem& it : H.pt_items) {
+  for (ReplayItem& it : transpose ? H.pt_items_t : H.pt_items) {
     void* params[] = {it.args};
     (void)hipLaunchKernel(it.fn, it.grid, dim3(unsigned(it.block)), params, 0, s);
   }
@@ -821,10 +862,10 @@ int replay_precond(Handle& H, const double* r, double* z, hipStream_t s) {
 }
 
 int apply_precond(Handle& H, const double* r, double* z, Ctx& c, bool transpose) {
-  if (!transpose && H.pipeline && !c.recording()) return replay_precond(H, r, z, c.s);
+  if (!c.recording() && (transpose ? H.pipeline_t : H.pipeline)) return replay_precond(H, r, z, c.s, transpose);
   if (H.fp32)
-    return transpose ? precond_transpose<float>(H, r, z, c) : precond_forward<float>(H, r, z, c, c);
-  return transpose ? precond_transpose<double>(H, r, z, c) : precond_forward<double>(H, r, z, c, c);
+    return transpose ? precond_transpose<float>(H, r, z, c, c) : precond_forward<float>(H, r, z, c, c);
+  return transpose ? precond_transpose<double>(H, r, z, c, c) : precond_forward<double>(H, r, z, c, c);
 }
 
 // y = alpha J x + beta b  (J or J^T), FP64.  With one lane per row the
@@ -1197,7 +1238,7 @@ bool pair_ops(const Op& x, const Op& y, ReplayItem& it) {
 }
 
 template <class T>
-int build_items(Handle& H, const Program& prog) {
+int build_items(std::vector<ReplayItem>& items, const Program& prog) {
   auto single = [&](const Op& op) {
     ReplayItem it;
     it.fn = op.fn;
@@ -1205,7 +1246,7 @@ int build_items(Handle& H, const Program& prog) {
     it.block = block_of(op.kind);
     std::memset(it.args, 0, sizeof(it.args));
     std::memcpy(it.args, op.args, size_t(op.size));
-    H.pt_items.push_back(it);
+    items.push_back(it);
   };
   const size_t na = prog.a.size(), nb = prog.b.size();
   size_t ia = 0, ib = 0;
@@ -1220,7 +1261,7 @@ int build_items(Handle& H, const Program& prog) {
     if (!x && !y) return ST_EINTERNAL;
     ReplayItem it;
     if (x && y && pair_ops<T>(*x, *y, it)) {
-      H.pt_items.push_back(it);
+      items.push_back(it);
       continue;
     }
     if (x) single(*x);
@@ -1232,13 +1273,16 @@ int build_items(Handle& H, const Program& prog) {
 int build_pipeline(Handle& H) {
   H.rslot = at<const double*>(H.base, H.L.io);
   H.zslot = at<double*>(H.base, H.L.io + sizeof(void*));
-  Program prog;
-  int rc = record_precond(H, prog, H.rslot, H.zslot);
-  if (rc) return rc;
-  H.pt_items.clear();
-  rc = H.fp32 ? build_items<float>(H, prog) : build_items<double>(H, prog);
-  if (rc) return rc;
-  H.pipeline = 1;
+  for (int tr = 0; tr < (H.adjoint ? 2 : 1); ++tr) {
+    Program prog;
+    int rc = record_precond(H, prog, H.rslot, H.zslot, tr == 1);
+    if (rc) return rc;
+    std::vector<ReplayItem>& items = tr ? H.pt_items_t : H.pt_items;
+    items.clear();
+    rc = H.fp32 ? build_items<float>(items, prog) : build_items<double>(items, prog);
+    if (rc) return rc;
+    (tr ? H.pipeline_t : H.pipeline) = 1;
+  }
   return ST_OK;
 }
 

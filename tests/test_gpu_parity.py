@@ -157,24 +157,30 @@ def test_long_horizon_fp32_sweeps_stay_accurate():
 
 @pytest.mark.parametrize("precision,inner", [("fp64", "amg"), ("fp32", "amg"), ("fp64", "exact")])
 def test_pipelined_sweeps_match_single_stream(precision, inner):
-    """The recorded two-program pipeline (a C_A sweep step and an F_u sweep step in
-    one launch, chunk by chunk) computes exactly what the step-by-step order
-    computes, and repeated applies give identical results."""
+    """The recorded two-program pipelines (for P_T^{-1}: a C_A sweep step and an
+    F_u sweep step in one launch, chunk by chunk; for P_T^{-T}: the backward F_u^T
+    sweep beside the backward C_A^T sweep of the chunks already done) compute
+    exactly what the step-by-step order computes, and repeated applies give
+    identical results.  20 slabs in chunks of 6 leave a ragged last chunk."""
     say(f"[gpu] recorded pipeline vs step-by-step {precision} {inner}")
     from paper_2309_00768_amd import binding
     cfg, ub, ab, ref = case(8, 20)
     out = []
     for single in (False, True):
         plan = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision=precision,
-                            inner=inner, single_stream=single, sweep_chunk=6, sweep_chain=False)
+                            inner=inner, single_stream=single, sweep_chunk=6, sweep_chain=False, adjoint=True)
         sysg = binding.System(plan, "cuda:0")
         r = np.random.default_rng(9).standard_normal(ref.N)
-        z = sysg.apply_precond(dev(r))
-        z2 = sysg.apply_precond(dev(r))
-        torch.cuda.synchronize()
-        assert torch.equal(z, z2)
-        out.append(z.cpu().numpy())
-    assert np.array_equal(out[0], out[1])
+        res = []
+        for tr in (False, True):
+            z = sysg.apply_precond(dev(r), transpose=tr)
+            z2 = sysg.apply_precond(dev(r), transpose=tr)
+            torch.cuda.synchronize()
+            assert torch.equal(z, z2)
+            res.append(z.cpu().numpy())
+        out.append(res)
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
