@@ -268,9 +268,11 @@ int st_sizes(const st_handle* h, int64_t* n_total, int* ns, int* nt);
 
 /* Launch choices in effect for a created system (tuned when
    st_problem.autotune = 1): slabs per wavefront of the J apply, rows per
-   workgroup of the sweep step kernels, and 1 if the sweep solves run as tiled
-   multi-step launches.  Any pointer may be NULL. */
-int st_tuning(const st_handle* h, int* j_slabs, int* step_rows, int* sweep_fuse);
+   workgroup of the sweep step kernels, 1 if the sweep solves run as tiled
+   multi-step launches, and the number of launches of one recorded
+   P_T^{-1} apply (0 when it is launched step by step).  Any pointer may be
+   NULL. */
+int st_tuning(const st_handle* h, int* j_slabs, int* step_rows, int* sweep_fuse, int* precond_launches);
 
 const char* st_error_string(int code);
 

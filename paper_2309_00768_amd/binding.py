@@ -91,7 +91,7 @@ def _load(path=LIB_PATH):
         "st_fgmres_solve": ([vp, vp, vp, ctypes.POINTER(StOpts), ctypes.POINTER(StInfo), vp], ctypes.c_int),
         "st_adjoint_solve": ([vp, vp, vp, ctypes.POINTER(StOpts), ctypes.POINTER(StInfo), vp], ctypes.c_int),
         "st_sizes": ([vp, i64p, ip, ip], ctypes.c_int),
-        "st_tuning": ([vp, ip, ip, ip], ctypes.c_int),
+        "st_tuning": ([vp, ip, ip, ip, ip], ctypes.c_int),
         "st_batch_create": ([ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
         "st_batch_workspace_size": ([vp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "st_batch_upload": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
@@ -294,10 +294,12 @@ class System:
 
     def tuning(self):
         """Launch choices in effect (``st_tuning``): J slabs per wavefront, sweep
-        step rows per workgroup, tiled sweep solves."""
-        js, rows, fuse = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _check(lib().st_tuning(self.ptr, ctypes.byref(js), ctypes.byref(rows), ctypes.byref(fuse)), "st_tuning")
-        return {"j_slabs": js.value, "step_rows": rows.value, "sweep_fuse": bool(fuse.value)}
+        step rows per workgroup, tiled sweep solves, launches per P_T apply."""
+        js, rows, fuse, pl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().st_tuning(self.ptr, ctypes.byref(js), ctypes.byref(rows), ctypes.byref(fuse), ctypes.byref(pl)),
+               "st_tuning")
+        return {"j_slabs": js.value, "step_rows": rows.value, "sweep_fuse": bool(fuse.value),
+                "precond_launches": pl.value}
 
     def close(self):
         if getattr(self, "ptr", None):

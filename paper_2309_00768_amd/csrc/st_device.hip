@@ -72,6 +72,8 @@ struct Handle {
   int fp32 = 0, exact = 0, inner_iters = 1, mass_iters = 12, max_restart = 30, adjoint = 0;
   int fu_deg = 0, ca_deg = 0, use_stencil = 0;
   int sweep_fuse = 0;              // stencil sweep solves in tiled launches of several steps
+  int first_chunk = 0;             // slabs in the first chunk of the recorded forward apply (0: chunk)
+  int mj_place = 1;                // current solves: 0 the program that finishes b first, 1 b, 2 a
   int step_rows = 0;               // rows per workgroup of the sweep step kernels (0: by precision)
   char* base = nullptr;
   WsLayout L;
@@ -588,12 +590,12 @@ int precond_forward(Handle& H, const double* r, double* z, Ctx& c, Ctx& ca, cons
   const double mlo = 0.24, mhi = 2.3, mth = 0.5 * (mhi + mlo), mde = 0.5 * (mhi - mlo);
   const bool rec = c.recording();
   const bool chain = H.use_chain && !rec;
+  // Chunk boundaries: a first chunk of H.first_chunk slabs (0: C), then C each.
   const int C = rec ? std::max(1, std::min(H.chunk, nt)) : nt;
-  const int nch = (nt + C - 1) / C;
-  // The current solves go with the shorter program (estimated launches).
-  const int ca_len = H.ca_deg > 0 ? sweep_launches(H, H.ca_deg) : 24;
-  const int fu_len = H.fu_deg > 0 ? sweep_launches(H, H.fu_deg) : 24;
-  const bool mj_in_a = rec && nt * ca_len + nch * (mit + 1) <= nt * fu_len + 40;
+  std::vector<int> cb{0};
+  for (int k = rec && H.first_chunk > 0 ? std::min(H.first_chunk, C) : C; k < nt; k += C) cb.push_back(k);
+  cb.push_back(nt);
+  const int nch = int(cb.size()) - 1;
   // The pressure part runs in b-ops that wait only for the split.
   auto mark = [&](Ctx& cx, int need) { cx.need = need; };
 
@@ -622,10 +624,10 @@ int precond_forward(Handle& H, const double* r, double* z, Ctx& c, Ctx& ca, cons
   // the b-side mass solves use their own scratch: a-side ones may run alongside
   cheb_solve<T>(c, H.Mp, nt, 0, 0, static_cast<const T*>(H.dMp), 0, nullptr, mth, mde, t, xp, mr2, md02, md12, np,
                 mit, 0, false);
-  // 3. y_A = C_A^{-1} s: forward sweep (program a), chunk by chunk; then per
-  //    chunk y_j = M_j^{-1}(r_j - K_jA y_A), g_u = r_u - Z_j y_j - Z_A y_A - B^T x_p
-  //    and x_u = F_u^{-1} g_u (forward sweep, program b)
-  std::vector<int> a_end(size_t(nch), 0);
+  // 3. y_A = C_A^{-1} s: forward sweep (program a), chunk by chunk; per chunk
+  //    y_j = M_j^{-1}(r_j - K_jA y_A) (the current solve, in either program),
+  //    g_u = r_u - Z_j y_j - Z_A y_A - B^T x_p and x_u = F_u^{-1} g_u (forward
+  //    sweep, program b, once that chunk of the C_A sweep is done)
   auto current_solve = [&](Ctx& cx, int k0, int kc, T* r_, T* d0_, T* d1_) {
     spmv1<T>(cx, H.KjA, kc, 0, 0, yA + int64_t(k0) * na, na, -1.0, rj + int64_t(k0) * nj, 1.0,
              rj + int64_t(k0) * nj, nj);
@@ -633,8 +635,50 @@ int precond_forward(Handle& H, const double* r, double* z, Ctx& c, Ctx& ca, cons
                   yj + int64_t(k0) * nj, r_ + int64_t(k0) * nj, d0_ + int64_t(k0) * nj, d1_ + int64_t(k0) * nj, nj,
                   mit, 0, false);
   };
+  auto ca_step = [&](Ctx& cx, int k) {
+    if (H.use_stencil && H.ca_deg > 0) {
+      // increment over the predictor y^0 (k = 1) or 2 y^{k-1} - y^{k-2} (k >= 2)
+      sweep_step_stencil<T>(cx, H, H.amgC0, H.sC0, k >= 1 ? &H.sCP : nullptr, k, 1.0, yA + int64_t(k - 1) * na,
+                            k >= 2 ? &H.sCQ : nullptr, k, 1.0, yA + int64_t(k - 2) * na, sA + int64_t(k) * na,
+                            yA + int64_t(k) * na, k, H.ca_deg, 2, k >= 1, k >= 2 ? 2.0 : 1.0, k >= 2 ? -1.0 : 0.0);
+    } else {
+      Seg<T> sg[2];
+      int nsg = 0;
+      if (k >= 1) sg[nsg++] = seg<T>(H.C1, 0, k - 1, 0, yA + int64_t(k - 1) * na, 0, 0, 0, 1, 1.0 / dt);
+      if (k >= 2) sg[nsg++] = seg<T>(H.C1, 1, 0, 0, yA + int64_t(k - 2) * na, 0, 0, 0, 1, -1.0 / (dt * dt));
+      sweep_step<T>(cx, H.amgC0, H.C1, nsg, sg, sA + int64_t(k) * na, yA + int64_t(k) * na, k, H.ca_deg, vc);
+    }
+  };
+  auto fu_step = [&](Ctx& cx, int k) {
+    if (H.use_stencil && H.fu_deg > 0) {
+      // increment over the predictor x^{k-1}: r0 = g^k - (F_u,k - M_u/dt) x^{k-1}
+      sweep_step_stencil<T>(cx, H, H.amgFu, H.sFu, k >= 1 ? &H.sAu : nullptr, k, -1.0, xu + int64_t(k - 1) * nu,
+                            nullptr, 0, 0.0, nullptr, yu + int64_t(k) * nu, xu + int64_t(k) * nu, k, H.fu_deg, 1,
+                            k >= 1, 1.0, 0.0);
+    } else {
+      Seg<T> sg = seg<T>(H.Mu, 0, 0, 0, xu + int64_t(k - 1) * nu, 0, 0, 0, 1, 1.0 / dt);
+      sweep_step<T>(cx, H.amgFu, H.Mu, k >= 1 ? 1 : 0, &sg, yu + int64_t(k) * nu, xu + int64_t(k) * nu, k,
+                    H.fu_deg, vc);
+    }
+  };
+  // Lockstep estimate (one op of each program per launch; a never waits): b's
+  // work on a chunk starts once a has finished that chunk and b its earlier
+  // work.  The current solve goes to the program that lets b finish the chunk
+  // first (H.mj_place 0), or always to b (1) or to a (2).  The op counts come
+  // from recording into a scratch list.
+  int cs_ops = 0, fu_ops = 0;
+  if (rec) {
+    std::vector<Op> tmp;
+    Ctx ct{nullptr, &tmp, nullptr, 0};
+    current_solve(ct, 0, 1, mr2, md02, md12);
+    cs_ops = int(tmp.size());
+    tmp.clear();
+    fu_step(ct, std::min(1, nt - 1));
+    fu_ops = int(tmp.size());
+  }
+  int tb = rec ? a_split + int(c.rec->size()) : 0;
   for (int ch = 0; ch < nch; ++ch) {
-    const int k0 = ch * C, k1 = std::min(nt, (ch + 1) * C);
+    const int k0 = cb[size_t(ch)], k1 = cb[size_t(ch) + 1], kc = k1 - k0;
     if (chain) {
       ChainArgs<T> cha;
       cha.C0 = st_op<T>(B, H.sC0);
@@ -663,47 +707,27 @@ int precond_forward(Handle& H, const double* r, double* z, Ctx& c, Ctx& ca, cons
       cha.d0 = at<T>(B, L.chd0);
       cha.d1 = at<T>(B, L.chd1);
       hipLaunchKernelGGL((k_ca_chain<T>), dim3(1), dim3(kChainBlock), 0, ca.s, cha);
-      continue;
+    } else {
+      for (int k = k0; k < k1; ++k) ca_step(ca, k);
     }
-    for (int k = k0; k < k1; ++k) {
-      if (H.use_stencil && H.ca_deg > 0) {
-        // increment over the predictor y^0 (k = 1) or 2 y^{k-1} - y^{k-2} (k >= 2)
-        sweep_step_stencil<T>(ca, H, H.amgC0, H.sC0, k >= 1 ? &H.sCP : nullptr, k, 1.0, yA + int64_t(k - 1) * na,
-                              k >= 2 ? &H.sCQ : nullptr, k, 1.0, yA + int64_t(k - 2) * na, sA + int64_t(k) * na,
-                              yA + int64_t(k) * na, k, H.ca_deg, 2, k >= 1, k >= 2 ? 2.0 : 1.0, k >= 2 ? -1.0 : 0.0);
-      } else {
-        Seg<T> sg[2];
-        int nsg = 0;
-        if (k >= 1) sg[nsg++] = seg<T>(H.C1, 0, k - 1, 0, yA + int64_t(k - 1) * na, 0, 0, 0, 1, 1.0 / dt);
-        if (k >= 2) sg[nsg++] = seg<T>(H.C1, 1, 0, 0, yA + int64_t(k - 2) * na, 0, 0, 0, 1, -1.0 / (dt * dt));
-        sweep_step<T>(ca, H.amgC0, H.C1, nsg, sg, sA + int64_t(k) * na, yA + int64_t(k) * na, k, H.ca_deg, vc);
-      }
+    bool in_a = false;
+    if (rec && !chain) {
+      const int la = int(ca.rec->size());
+      const int fin_a = std::max(tb, la + cs_ops) + 1 + kc * fu_ops;
+      const int fin_b = std::max(tb, la) + cs_ops + 1 + kc * fu_ops;
+      in_a = H.mj_place == 2 || (H.mj_place == 0 && fin_a < fin_b);
+      tb = in_a ? fin_a : fin_b;
     }
-    if (mj_in_a) current_solve(ca, k0, k1 - k0, mr, md0, md1);
-    a_end[size_t(ch)] = rec ? int(ca.rec->size()) : 0;
-  }
-  for (int ch = 0; ch < nch; ++ch) {
-    const int k0 = ch * C, kc = std::min(nt, (ch + 1) * C) - k0;
-    mark(c, a_end[size_t(ch)]);
-    if (!chain && !mj_in_a) current_solve(c, k0, kc, mr2, md02, md12);
+    if (in_a) current_solve(ca, k0, kc, mr, md0, md1);
+    mark(c, rec ? int(ca.rec->size()) : 0);
+    if (!chain && !in_a) current_solve(c, k0, kc, mr2, md02, md12);
     {
       Seg<T> sg[3] = {seg<T>(H.Zj, 0, k0, 1, yj + int64_t(k0) * nj, nj, 0, 0, kc, -1.0),
                       seg<T>(H.Zj, 1, k0, 1, yA + int64_t(k0) * na, na, 0, 0, kc, -1.0),
                       seg<T>(H.Zj, 2, 0, 0, xp + int64_t(k0) * np, np, 0, 0, kc, 1.0)};
       spmv<T, T>(c, H.Zj, kc, 3, sg, ru + int64_t(k0) * nu, nu, 1.0, yu + int64_t(k0) * nu, nu);
     }
-    for (int k = k0; k < k0 + kc; ++k) {
-      if (H.use_stencil && H.fu_deg > 0) {
-        // increment over the predictor x^{k-1}: r0 = g^k - (F_u,k - M_u/dt) x^{k-1}
-        sweep_step_stencil<T>(c, H, H.amgFu, H.sFu, k >= 1 ? &H.sAu : nullptr, k, -1.0, xu + int64_t(k - 1) * nu,
-                              nullptr, 0, 0.0, nullptr, yu + int64_t(k) * nu, xu + int64_t(k) * nu, k, H.fu_deg, 1,
-                              k >= 1, 1.0, 0.0);
-      } else {
-        Seg<T> sg = seg<T>(H.Mu, 0, 0, 0, xu + int64_t(k - 1) * nu, 0, 0, 0, 1, 1.0 / dt);
-        sweep_step<T>(c, H.amgFu, H.Mu, k >= 1 ? 1 : 0, &sg, yu + int64_t(k) * nu, xu + int64_t(k) * nu, k,
-                      H.fu_deg, vc);
-      }
-    }
+    for (int k = k0; k < k1; ++k) fu_step(c, k);
   }
   // 4. join with the pressure normalisation 1^T M_p p = 0
   mark(c, rec ? int(ca.rec->size()) : 0);
@@ -1289,8 +1313,10 @@ int build_pipeline(Handle& H) {
 // =========================================================== autotune ===
 // Times, on this system's own operators, the launch choices that leave every
 // result bitwise the same, and keeps the fastest: slabs per wavefront of the
-// J apply (when not given), rows per workgroup of the sweep step kernels, and
-// one launch per sweep step against the tiled multi-step solve.  The inputs
+// J apply (when not given), rows per workgroup of the sweep step kernels, one
+// launch per sweep step against the tiled multi-step solve, and the schedule
+// of the recorded forward apply (first chunk, placement of the current
+// solves).  The inputs
 // are two zeroed Krylov columns (the kernels' timing does not depend on the
 // values).
 int autotune(Handle& H, hipStream_t s, bool pipeline) {
@@ -1344,6 +1370,31 @@ int autotune(Handle& H, hipStream_t s, bool pipeline) {
     H.sweep_fuse = best.fuse;
     H.step_rows = best.rows;
     if (rc == ST_OK && pipeline) rc = build_pipeline(H);
+  }
+  // the recorded forward apply's schedule: size of the first chunk (how long
+  // program b waits for the C_A sweep at the start) and where the current
+  // solves go
+  if (rc == ST_OK && pipeline) {
+    const int C = std::max(1, std::min(H.chunk, H.d.nt));
+    struct Sched { int first, place; };
+    const Sched cands[] = {{0, 1}, {0, 0}, {C / 2, 1}, {C / 2, 0}, {C / 4, 1}, {C / 4, 0}};
+    Sched best = cands[0];
+    float tbest = 1e30f;
+    for (const Sched& sc : cands) {
+      if (sc.first < 0 || (sc.first > 0 && sc.first >= C)) continue;
+      H.first_chunk = sc.first;
+      H.mj_place = sc.place;
+      if ((rc = build_pipeline(H)) != ST_OK) break;
+      const float t = timed([&] { (void)apply_precond(H, x, y, c, false); }, 4);
+      if (rc != ST_OK) break;
+      if (t < tbest) {
+        tbest = t;
+        best = sc;
+      }
+    }
+    H.first_chunk = best.first;
+    H.mj_place = best.place;
+    if (rc == ST_OK) rc = build_pipeline(H);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1844,12 +1895,13 @@ int st_sizes(const st_handle* h, int64_t* n_total, int* ns, int* nt) {
   return ST_OK;
 }
 
-int st_tuning(const st_handle* h, int* j_slabs, int* step_rows, int* sweep_fuse) {
+int st_tuning(const st_handle* h, int* j_slabs, int* step_rows, int* sweep_fuse, int* precond_launches) {
   if (!h) return ST_EINVAL;
   const st::Handle& H = h->h;
   if (j_slabs) *j_slabs = H.J.lanes != 1 ? 1 : (H.j_slabs == 0 ? 8 : H.j_slabs);
   if (step_rows) *step_rows = H.step_rows > 0 ? H.step_rows : (H.fp32 ? st::st_rows<float>() : st::st_rows<double>());
   if (sweep_fuse) *sweep_fuse = H.sweep_fuse;
+  if (precond_launches) *precond_launches = H.pipeline ? int(H.pt_items.size()) + 1 : 0;
   return ST_OK;
 }
 
