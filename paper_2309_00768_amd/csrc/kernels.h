@@ -502,9 +502,9 @@ __global__ ST_LATENCY_KERNEL void k_st_cheb(StChebArgs<T> a) {
 // the predictor) and step i >= 1 st_cheb_body's, in the same order, so the
 // result is that of the step-by-step launches.
 constexpr int kSolveBlock = 512;   // threads per workgroup of the tiled solve
-// Two such workgroups per CU (4 waves per SIMD, at most 128 VGPRs): a forward
-// sweep's F_u and C_A solves together take 256 + 64 workgroups at 64 x 64.
-#define ST_SOLVE_KERNEL __launch_bounds__(kSolveBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
+// No cap on the registers: capped at 128 VGPRs (two workgroups per CU) the
+// kernel spills and is no faster (measured).
+#define ST_SOLVE_KERNEL __launch_bounds__(kSolveBlock)
 constexpr int kTileExt = 400;   // nodes of a grown tile per component (LDS capacity)
 constexpr int kTileOut = 64;    // nodes of a tile per component
 constexpr int kTileComp = 2;
@@ -674,7 +674,9 @@ __global__ ST_SOLVE_KERNEL void k_st_solve(StSolveArgs<T> a) {
 // `deg` on C_A,k for the increment over the predictor (y^0 for slab 1,
 // 2 y^{k-1} - y^{k-2} after; first step fused with the residual
 // s^k + P_k y^{k-1} + Q_k y^{k-2} of the predictor) and of degree `mit` on
-// M_j.  Only workgroup barriers: no inter-workgroup synchronisation.
+// M_j.  Only workgroup barriers: no inter-workgroup synchronisation.  Every
+// operator here is a one-component stencil (checked where the kernel is
+// chosen).
 template <class T>
 struct ChainArgs {
   StOp<T> C0, CP, CQ, Mj, KjA;
@@ -710,12 +712,12 @@ __global__ __launch_bounds__(kChainBlock) void k_ca_chain(ChainArgs<T> a) {
       T x0 = T(0);
       if (k >= 1) {
         const T* y1 = a.yA + int64_t(k - 1) * na;
-        acc += stencil_row<2, T, T>(a.CP, k, row, y1);
+        acc += stencil_row_n<2, 1, T, T>(a.CP, k, row, y1);
         x0 = y1[row];
       }
       if (k >= 2) {
         const T* y2 = a.yA + int64_t(k - 2) * na;
-        acc += stencil_row<2, T, T>(a.CQ, k, row, y2);
+        acc += stencil_row_n<2, 1, T, T>(a.CQ, k, row, y2);
         x0 = T(2) * x0 - y2[row];
       }
       const T dd = dinv[row] * acc / T(theta);
@@ -735,7 +737,7 @@ __global__ __launch_bounds__(kChainBlock) void k_ca_chain(ChainArgs<T> a) {
         T* dnew = i % 2 ? a.d1 : a.d0;
         for (int row = tid; row < na; row += kChainBlock) {
           const T od = dold[row], dg = dinv[row], rr = a.r[row];
-          const T rn = rr - stencil_row<2, T, T>(a.C0, k, row, dold);
+          const T rn = rr - stencil_row_n<2, 1, T, T>(a.C0, k, row, dold);
           const T dn = c1 * od + c2 * dg * rn;
           a.r[row] = rn;
           dnew[row] = dn;
@@ -748,7 +750,7 @@ __global__ __launch_bounds__(kChainBlock) void k_ca_chain(ChainArgs<T> a) {
     T* jk = a.yj + int64_t(k) * nj;
     const T* rjk = a.rj + int64_t(k) * nj;
     for (int row = tid; row < nj; row += kChainBlock) {
-      const T acc = rjk[row] - stencil_row<1, T, T>(a.KjA, 0, row, yk);
+      const T acc = rjk[row] - stencil_row_n<1, 1, T, T>(a.KjA, 0, row, yk);
       const T dd = a.dinvM[row] * acc / T(a.mth);
       a.r[row] = acc;
       a.d0[row] = dd;
@@ -766,7 +768,7 @@ __global__ __launch_bounds__(kChainBlock) void k_ca_chain(ChainArgs<T> a) {
         T* dnew = i % 2 ? a.d1 : a.d0;
         for (int row = tid; row < nj; row += kChainBlock) {
           const T od = dold[row], dg = a.dinvM[row], rr = a.r[row];
-          const T rn = rr - stencil_row<1, T, T>(a.Mj, 0, row, dold);
+          const T rn = rr - stencil_row_n<1, 1, T, T>(a.Mj, 0, row, dold);
           const T dn = c1 * od + c2 * dg * rn;
           a.r[row] = rn;
           dnew[row] = dn;

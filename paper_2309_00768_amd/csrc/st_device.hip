@@ -1799,7 +1799,9 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
   // One workgroup covers the C_A grid with at most one row per thread: then the
   // chain kernel (no dispatch per step) beats per-step launches; on larger
   // grids one CU is too slow for it.
-  H.use_chain = H.use_stencil && H.ca_deg > 0 && std::max(H.d.na, H.d.nj) <= kChainBlock && P.prob.sweep_chain >= 0
+  H.use_chain = H.use_stencil && H.ca_deg > 0 && std::max(H.d.na, H.d.nj) <= kChainBlock && P.prob.sweep_chain >= 0 &&
+                        H.sC0.ncomp == 1 && H.sCP.ncomp == 1 && H.sCQ.ncomp == 1 && H.sMj.ncomp == 1 &&
+                        H.sKjA.ncomp == 1
                     ? 1
                     : 0;
   H.base = static_cast<char*>(ws);

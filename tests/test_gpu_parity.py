@@ -233,3 +233,23 @@ def test_autotuned_launches_give_the_same_results(precision):
                     sysg.apply_precond(dev(r), transpose=True).cpu().numpy()])
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-4)])
+def test_chain_kernel_matches_per_step_launches(precision, tol):
+    """Launched step by step on grids of at most 1024 rows, the C_A sweep and the
+    current solves of a chunk run in one workgroup (k_ca_chain).  They agree with
+    the per-step launches up to the summation order of the stencil and SELL forms
+    of K_jA and M_j."""
+    say(f"[gpu] chain kernel vs per-step launches {precision}")
+    from paper_2309_00768_amd import binding
+    cfg, ub, ab, ref = case(8, 20)
+    out = []
+    for chain in (True, False):
+        plan = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision=precision,
+                            single_stream=True, sweep_chain=chain)
+        sysg = binding.System(plan, "cuda:0")
+        r = np.random.default_rng(12).standard_normal(ref.N)
+        out.append(sysg.apply_precond(dev(r)).cpu().numpy())
+    say(f"    rel {rel(out[0], out[1]):.1e}")
+    assert rel(out[0], out[1]) <= tol
