@@ -184,6 +184,13 @@ int st_plan_solver_info(const st_plan* plan, int* fu_degree, int* ca_degree, dou
 /* The current state used (either given or computed), host [nt][(n+1)^2]. */
 int st_plan_export_jbar(const st_plan* plan, double* jbar);
 
+/* Stored layout of the J apply (SELL, eq. (jacobianSTDiscrete)): entries per
+ * segment including the padding of each 64-row slice, slots[0] for the
+ * per-slab blocks (one value set per slab), slots[1] for the slab-invariant
+ * blocks and slots[2] for the previous-slab coupling, and the number of
+ * slices.  Host only; any pointer may be NULL. */
+int st_plan_jacobian_slots(const st_plan* plan, int64_t slots[3], int* nslices);
+
 int st_plan_destroy(st_plan* plan);
 
 /* Uploads the plan into the caller's device workspace `ws` (>= workspace size

@@ -57,7 +57,7 @@ class StInfo(ctypes.Structure):
 
 EXPORTED = [
     "st_plan_create", "st_plan_workspace_size", "st_plan_sizes", "st_plan_export_block", "st_plan_export_jbar",
-    "st_plan_solver_info",
+    "st_plan_solver_info", "st_plan_jacobian_slots",
     "st_plan_destroy", "st_create", "st_destroy", "st_apply_jacobian", "st_apply_jacobian_t",
     "st_apply_precond", "st_apply_precond_t", "st_apply_initial_coupling", "st_fgmres_solve", "st_adjoint_solve",
     "st_sizes", "st_tuning", "st_batch_create", "st_batch_workspace_size", "st_batch_upload", "st_batch_launch_counts",
@@ -80,6 +80,7 @@ def _load(path=LIB_PATH):
         "st_plan_export_block": ([vp, ctypes.c_int, ctypes.c_int, ip, ip, i64p, ip, ip, dp], ctypes.c_int),
         "st_plan_export_jbar": ([vp, dp], ctypes.c_int),
         "st_plan_solver_info": ([vp, ip, ip, dp, dp], ctypes.c_int),
+        "st_plan_jacobian_slots": ([vp, i64p, ip], ctypes.c_int),
         "st_plan_destroy": ([vp], ctypes.c_int),
         "st_create": ([vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)], ctypes.c_int),
         "st_destroy": ([vp], ctypes.c_int),
@@ -205,6 +206,13 @@ class Plan:
         _check(lib().st_plan_solver_info(self.ptr, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
                                          ctypes.byref(d)), "solver_info")
         return a.value, b.value, c.value, d.value
+
+    def jacobian_slots(self):
+        """([per-slab, slab-invariant, coupling] SELL entries of J with padding, slices)."""
+        slots = (ctypes.c_int64 * 3)()
+        ns = ctypes.c_int()
+        _check(lib().st_plan_jacobian_slots(self.ptr, slots, ctypes.byref(ns)), "jacobian_slots")
+        return list(slots), ns.value
 
     def export_jbar(self):
         out = np.empty((self.nt, (self.n + 1) ** 2))

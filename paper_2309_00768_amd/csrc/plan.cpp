@@ -464,6 +464,15 @@ int st_plan_solver_info(const st_plan* plan, int* fu_degree, int* ca_degree, dou
   return ST_OK;
 }
 
+int st_plan_jacobian_slots(const st_plan* plan, int64_t slots[3], int* nslices) {
+  if (!plan) return ST_EINVAL;
+  const st::SellGroup& g = plan->p.J;
+  if (slots)
+    for (int s = 0; s < 3; ++s) slots[s] = s < g.nseg ? g.seg[s].total : 0;
+  if (nslices) *nslices = g.nslices;
+  return ST_OK;
+}
+
 int st_plan_export_jbar(const st_plan* plan, double* jbar) {
   if (!plan || !jbar) return ST_EINVAL;
   std::copy(plan->p.blk.jbar.begin(), plan->p.blk.jbar.end(), jbar);

@@ -109,3 +109,21 @@ def test_plan_sizes_and_workspace(n, nt):
     lay = inputs.slab_sizes(n)
     assert plan.ns == lay["slab"]
     assert plan.workspace_bytes > 8 * plan.ns * nt * 60
+
+
+def test_jacobian_layout_holds_every_entry():
+    """The J apply's SELL segments hold every structural nonzero of their blocks
+    (per-slab: F_u, Z_j, Z_A, Y, F_A; slab-invariant: B^T, B, M_j, K_jA;
+    coupling: M_u, M_A), padded to whole 64-row slices."""
+    cfg = inputs.CONFIGS["cfg1"]
+    ub, ab = inputs.state(cfg)
+    plan = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab)
+    slots, nslices = plan.jacobian_slots()
+    nnz = [sum(plan.block_nnz(b) for b in ("Fu", "Zj", "ZA", "Y", "FA")),
+           2 * plan.block_nnz("B") + plan.block_nnz("Mj") + plan.block_nnz("KjA"),
+           plan.block_nnz("Mu") + plan.block_nnz("MA")]
+    assert nslices == (plan.ns + 63) // 64
+    for s, n in zip(slots, nnz):
+        assert s % 64 == 0 and s >= n
+    plan.close()
+
