@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of one J apply at the default workload from FETCH_SIZE / WRITE_SIZE
 # counter runs calibrated with a 1 GiB copy (profiles/pmc_cfg3_jacobian_fetch_write.md),
 # valid while the kernel source it measured is unchanged (digest of that source).
-JAC_COUNTERS = {"config": "cfg3", "j_slabs": 8, "source_sha256_16": "113261cced6ea653", "traffic_bytes": 2.644e9}
+JAC_COUNTERS = {"config": "cfg3", "j_slabs": 8, "source_sha256_16": "2863946ff1f01491", "traffic_bytes": 2.330e9}
 
 
 def jacobian_kernel_digest():

@@ -226,7 +226,8 @@ __device__ inline void spmv_slabs_body(const SpmvSlabsArgs& sa, int bx, int by) 
 #pragma unroll
       for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int u = 0; u < B; ++u) vv[v][u] = (g.vstride || v == 0) ? vals[v][o[u]] : 0.0;
+        for (int u = 0; u < B; ++u)
+          vv[v][u] = g.vstride ? __builtin_nontemporal_load(vals[v] + o[u]) : (v == 0 ? vals[v][o[u]] : 0.0);
 #pragma unroll
       for (int v = 0; v < NV; ++v)
 #pragma unroll
