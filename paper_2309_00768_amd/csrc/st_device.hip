@@ -57,7 +57,8 @@ struct DAmg {
 };
 
 // One launch of a replayed program: a recorded op through its own kernel, or
-// one step of each sweep through k_sweep_pair; arguments by value.
+// one op of each program through a paired kernel (k_two, k_two_solve);
+// arguments by value.
 struct ReplayItem {
   const void* fn = nullptr;
   dim3 grid;
