@@ -154,8 +154,9 @@ __global__ ST_LATENCY_KERNEL void k_spmv(SpmvArgs<T, TX> a) {
 // The space-time Jacobian (or its transpose) over NV consecutive slabs per
 // wavefront: each column index and each slab-invariant value of a row is
 // loaded once for the NV slabs, the slab-dependent values and the gathered x
-// once per slab; all loads of a batch of B entries are issued together (at
-// cfg3 the loads in flight per lane pay more than occupancy).  One lane per
+// once per slab; all loads of a batch of B entries are issued together (on a
+// 64 x 64 mesh with 128 slabs the loads in flight per lane pay more than
+// occupancy).  One lane per
 // row.  Per row and slab the products are summed in the same order as k_spmv
 // (segment by segment, entries in order), so the result is the same.
 struct SpmvSlabsArgs {

@@ -294,9 +294,10 @@ static int build_plan(Plan& P, std::string& err) {
     const double red_ca = pr.ca_reduction > 0 ? pr.ca_reduction : 0.3;
     // The degree meets the reduction target on the estimated interval, and is
     // at least kMinAlone (the sweeps solve for increments, so the error of a
-    // step is not amplified by the recursion in time; measured at the cfg3 and
-    // uneven-batch sizes, tighter solves do not lower the FGMRES iteration
-    // count, and C_A below degree 4 raises it).  Beyond kMaxAlone steps one
+    // step is not amplified by the recursion in time; measured on a 64 x 64
+    // mesh with 128 slabs and on meshes of 16 to 96 cells with up to 256 slabs,
+    // tighter solves do not lower the FGMRES iteration count, and C_A below
+    // degree 4 raises it).  Beyond kMaxAlone steps one
     // V-cycle is cheaper per slab.
     constexpr int kMinAlone = 4, kMaxAlone = 48;
     auto pick = [&](int opt, const Amg& a, double red) -> int {
