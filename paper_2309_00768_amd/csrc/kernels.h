@@ -196,6 +196,9 @@ __device__ inline void spmv_slabs_body(const SpmvSlabsArgs& sa, int bx, int by) 
   for (int s = 0; s < 3; ++s) {
     if (s >= a.nseg) break;
     const Seg<double>& g = a.seg[s];
+    // An empty segment (the coupling of a single slab) has no slab whose data
+    // is in range: skip it (uniform across the launch).
+    if (g.vlo >= g.vhi) continue;
     // Slabs outside the segment's range read slab vlo's data (in bounds) and
     // their sums are dropped, so every load of a batch is issued together.
     bool on[NV];

@@ -1037,6 +1037,38 @@ void emit_finalize(Ctx& c, Handle& H, const Krylov& K, double* x) {
   slab_shift<double>(c, x + d.off[2], int64_t(d.ns), d.np, d.nt, K.psum, 1.0 / H.msum);
 }
 
+// Begin/end events recorded around each J or P_T apply of a solve, on the
+// solve's stream; the destructor releases them on every return path.
+struct EventPairs {
+  hipStream_t s;
+  std::vector<hipEvent_t> v;
+  explicit EventPairs(hipStream_t st) : s(st) {}
+  EventPairs(const EventPairs&) = delete;
+  EventPairs& operator=(const EventPairs&) = delete;
+  ~EventPairs() {
+    for (hipEvent_t e : v)
+      if (e) (void)hipEventDestroy(e);
+  }
+  void mark() {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+    if (e) (void)hipEventRecord(e, s);
+    v.push_back(e);
+  }
+  void begin() { mark(); }
+  void end() { mark(); }
+  int pairs() const { return int(v.size() / 2); }
+  // Sum of the pairs' durations (stream synchronised by the caller).
+  double elapsed_ms() const {
+    double acc = 0.0;
+    for (size_t i = 0; i + 1 < v.size(); i += 2) {
+      float ms = 0.f;
+      if (v[i] && v[i + 1] && hipEventElapsedTime(&ms, v[i], v[i + 1]) == hipSuccess) acc += ms;
+    }
+    return acc;
+  }
+};
+
 int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* info, hipStream_t s, bool adjoint) {
   auto t0 = std::chrono::steady_clock::now();
   const int m = o->restart > 0 ? o->restart : 30;
@@ -1046,26 +1078,16 @@ int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* 
   const Krylov K = krylov(H, m);
   Ctx c{s, nullptr};
   double* hs = H.host_small;
-  std::vector<hipEvent_t> evs, jevs;
+  EventPairs evs(s), jevs(s);
   auto jac = [&](const double* xin, double* yout, double alpha, const double* bb) {
-    hipEvent_t a, bev;
-    (void)hipEventCreate(&a);
-    (void)hipEventCreate(&bev);
-    (void)hipEventRecord(a, s);
+    jevs.begin();
     apply_J(H, xin, yout, c, adjoint, alpha, bb);
-    (void)hipEventRecord(bev, s);
-    jevs.push_back(a);
-    jevs.push_back(bev);
+    jevs.end();
   };
   auto precond = [&](const double* r, double* z) {
-    hipEvent_t a, bev;
-    (void)hipEventCreate(&a);
-    (void)hipEventCreate(&bev);
-    (void)hipEventRecord(a, s);
+    evs.begin();
     apply_precond(H, r, z, c, adjoint);
-    (void)hipEventRecord(bev, s);
-    evs.push_back(a);
-    evs.push_back(bev);
+    evs.end();
   };
   auto fetch = [&](const double* dev, int count) -> int {
     if (hipMemcpyAsync(hs, dev, sizeof(double) * count, hipMemcpyDeviceToHost, s) != hipSuccess) return ST_EHIP;
@@ -1125,19 +1147,9 @@ int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* 
   emit_finalize(c, H, K, x);
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipGetLastError());
-  auto elapsed = [](std::vector<hipEvent_t>& v) {
-    double acc = 0.0;
-    for (size_t i = 0; i + 1 < v.size(); i += 2) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, v[i], v[i + 1]) == hipSuccess) acc += ms;
-      (void)hipEventDestroy(v[i]);
-      (void)hipEventDestroy(v[i + 1]);
-    }
-    return acc;
-  };
-  const double pms = elapsed(evs), jms = elapsed(jevs);
-  info->precond_calls = int(evs.size() / 2);
-  info->jacobian_calls = int(jevs.size() / 2);
+  const double pms = evs.elapsed_ms(), jms = jevs.elapsed_ms();
+  info->precond_calls = evs.pairs();
+  info->jacobian_calls = jevs.pairs();
   info->jacobian_seconds = jms * 1e-3;
   info->iterations = its;
   info->converged = status == ST_OK ? 1 : 0;
