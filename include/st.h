@@ -83,9 +83,12 @@ typedef struct st_problem {
   int mass_iters;     /* Chebyshev steps per mass-matrix solve (0: 6 AMG mode,
                          60 EXACT mode)                                        */
   int cheb_degree;    /* Chebyshev-Jacobi smoother degree (0: 3)              */
-  int fu_solver;      /* inner solver of F_u,k in AMG mode: 0 auto (from the
-                         estimated condition number of D^{-1} F_u), -1 one SA-AMG
-                         V(1,1) cycle, k > 0 Chebyshev-Jacobi of degree k alone */
+  int fu_solver;      /* inner solver of F_u,k: 0 auto (AMG mode: from the
+                         estimated condition number of D^{-1} F_u; EXACT mode:
+                         repeated V-cycles), -1 one SA-AMG V(1,1) cycle (AMG
+                         mode), k > 0 Chebyshev-Jacobi of degree k alone in
+                         either mode (EXACT mode then converges the K_p and
+                         mass solves only)                                  */
   int ca_solver;      /* the same for the wave blocks C_A,k                   */
   int max_restart;    /* largest FGMRES restart length the workspace holds (0: 30) */
   int sell_sigma;     /* SELL sorting window in rows (0: whole matrix)        */
@@ -207,14 +210,22 @@ int st_destroy(st_handle* h);
  * Asynchronous on `stream`. */
 int st_apply_jacobian(st_handle* h, const double* x, double* y, void* stream);
 
-/* y = J^T x (block upper-bidiagonal in time). */
+/* y = J^T x: the transpose of eq. (jacobianSTDiscrete), block upper-bidiagonal
+ * in time (diagonal blocks the transposed single-step Jacobians of eq.
+ * (jacobianDiscrete), super-diagonal -diag(M_u/dt, 0, 0, M_A/dt), the mass
+ * matrices being symmetric).  Needs a handle created with adjoint = 1 (else
+ * ST_EINVAL).  Same layout, aliasing and stream rules as st_apply_jacobian. */
 int st_apply_jacobian_t(st_handle* h, const double* x, double* y, void* stream);
 
 /* z = P_T^{-1} r (eq. (PT)); internal precision per the problem; FP64 in/out.
  * r and z device, length N, must not alias.  Asynchronous on `stream`. */
 int st_apply_precond(st_handle* h, const double* r, double* z, void* stream);
 
-/* z = P_T^{-T} r: the transposed preconditioner (backward-in-time sweeps). */
+/* z = P_T^{-T} r: the transpose of eq. (PT), P_T^T = Utilde_up^T Ubar_ujA^T
+ * with eqs. (Utilde) and (barUuja) transposed; its F_u and C_A solves become
+ * backward-in-time sweeps on the transposed blocks of eqs. (STFu) and (CAs).
+ * Needs adjoint = 1 (else ST_EINVAL).  FP64 in/out, device, length N, no
+ * aliasing; asynchronous on `stream`. */
 int st_apply_precond_t(st_handle* h, const double* r, double* z, void* stream);
 
 /* y = (M_A / dt) a0: how an initial vector potential A^0 (interior Q1 nodes,
@@ -226,13 +237,25 @@ int st_apply_initial_coupling(st_handle* h, const double* a0, double* y, void* s
 
 /* ------------------------------------------------------------- solves --- */
 
-/* Right-preconditioned FGMRES(m) on J x = b with P_T; residual, Arnoldi (CGS2)
- * and the Hessenberg least-squares problem in FP64 on the device.  Blocks until
- * done.  Returns ST_OK, ST_ENOTCONV (x = last iterate) or an error. */
+/* Right-preconditioned FGMRES(m) on J x = b with P_T, the Krylov method the
+ * paper wraps around eq. (PT) (Sec. "Performance of preconditioner", GMRES
+ * right-preconditioned; flexible here because the inner solves are
+ * iterative); residual, Arnoldi (CGS2) and the Hessenberg least-squares
+ * problem in FP64 on the device.  b, x device, length N, slab-major; the
+ * pressure rows of b are projected to zero sum per slab and x is normalised
+ * to 1^T M_p p^k = 0.  Stops when ||b - J x||_2 <= max(rtol ||b||_2, atol) (true
+ * residual).  o->restart <= the plan's max_restart (else ST_EINVAL).  Blocks
+ * until done.  Returns ST_OK, ST_ENOTCONV (x = last iterate, info filled),
+ * ST_EBREAKDOWN (a NaN or Inf in b or in the iteration) or another error. */
 int st_fgmres_solve(st_handle* h, const double* b, double* x, const st_opts* o,
                     st_info* info, void* stream);
 
-/* Adjoint solve J^T lam = g with FGMRES right-preconditioned by P_T^{-T}. */
+/* Adjoint solve J^T lam = g (the transpose of eq. (jacobianSTDiscrete), a
+ * backward-in-time recurrence) with FGMRES right-preconditioned by P_T^{-T}
+ * (st_apply_precond_t); the gradient of a terminal functional of A^{Nt} with
+ * respect to A^0 is then st_apply_initial_coupling(lambda_A^1).  Needs
+ * adjoint = 1.  Options, stopping test, outputs and status codes as for
+ * st_fgmres_solve. */
 int st_adjoint_solve(st_handle* h, const double* g, double* lam, const st_opts* o,
                      st_info* info, void* stream);
 

@@ -301,8 +301,9 @@ static int build_plan(Plan& P, std::string& err) {
     // V-cycle is cheaper per slab.
     constexpr int kMinAlone = 4, kMaxAlone = 48;
     auto pick = [&](int opt, const Amg& a, double red) -> int {
-      if (P.exact || opt < 0) return 0;
-      if (opt > 0) return opt;
+      if (opt < 0) return 0;
+      if (opt > 0) return opt;   // explicit degree, also in EXACT mode
+      if (P.exact) return 0;
       const double sk = std::sqrt(a.kappa), r = (sk - 1.0) / (sk + 1.0);
       const int deg = int(std::ceil(std::log(red / 2.0) / std::log(r)));
       return deg > kMaxAlone ? 0 : std::max(kMinAlone, deg);

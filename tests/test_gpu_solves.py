@@ -21,6 +21,7 @@ import oracle
 from oracle.blocks import ConstantBlocks, SlabBlocks, current_from_potential
 from oracle.fem import Mesh
 from paper_2309_00768_amd import inputs
+from parity_util import assert_blocks
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -53,7 +54,7 @@ def test_cfg2_jacobian():
     say("[gpu] cfg2 J apply")
     cfg, ref, sysg = cfg2_pair()
     x = np.random.default_rng(11).standard_normal(ref.N)
-    assert rel(sysg.apply_jacobian(dev(x)).cpu().numpy(), ref.apply_J(x)) <= 1e-12
+    assert_blocks(sysg.apply_jacobian(dev(x)).cpu().numpy(), ref.apply_J(x), sysg.offsets, cfg.nt, 1e-12, "J")
 
 
 def test_cfg2_precond_exact_parity():
@@ -61,7 +62,7 @@ def test_cfg2_precond_exact_parity():
     cfg, ref, sysg = cfg2_pair()
     r = np.random.default_rng(13).standard_normal(ref.N)
     z = sysg.apply_precond(dev(r)).cpu().numpy()
-    assert rel(z, ref.apply_PT_inv(r)) <= 1e-10
+    assert_blocks(z, ref.apply_PT_inv(r), sysg.offsets, cfg.nt, 1e-10, "P_T^-1")
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
@@ -79,7 +80,7 @@ def test_cfg2_fgmres_iterates_match_oracle(seed):
                               maxit=30)
     xr = ref.normalise_pressure(xr)
     say(f"    gpu res={info.true_rel_residual:.3e}")
-    assert rel(x.cpu().numpy(), xr) <= 1e-10, rel(x.cpu().numpy(), xr)
+    assert_blocks(x.cpu().numpy(), xr, sysg.offsets, cfg.nt, 1e-10, "x_30")
 
 
 def test_cfg2_size_fourier_state_solve_matches_direct_solution():
@@ -94,7 +95,7 @@ def test_cfg2_size_fourier_state_solve_matches_direct_solution():
     x, info, rc, _ = sysg.solve(dev(b), rtol=1e-13)
     say(f"    its={info.iterations} res={info.true_rel_residual:.2e}")
     assert rc == 0
-    assert rel(x.cpu().numpy(), ref.direct_solve(b)) <= 1e-10
+    assert_blocks(x.cpu().numpy(), ref.direct_solve(b), sysg.offsets, cfg.nt, 1e-10, "x vs x*")
 
 
 def sampled_slab(cfg, ub, ab, k):
@@ -139,7 +140,7 @@ def test_cfg3_jacobian_on_sampled_slabs():
         mesh, cb, s = sampled_slab(cfg, ub, ab, k)
         offs = np.cumsum([0, cb.Mu.shape[0], cb.Mp.shape[0], cb.Mj.shape[0], cb.MA.shape[0]])
         yr = slab_apply(cb, s, cfg.dt, X[k], X[k - 1] if k > 0 else None, offs)
-        assert rel(y[k], yr) <= 1e-12, (k, rel(y[k], yr))
+        assert_blocks(y[k], yr, sysg.offsets, 1, 1e-12, f"J slab {k}")
 
 
 def test_cfg3_fp32_solve_residual_on_sampled_slabs():
@@ -207,7 +208,8 @@ def test_single_slab_smallest_mesh_solve():
     ref = oracle.SpaceTimeSystem(2, 1, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab)
     b = inputs.rhs(cfg, 3)
     x, info, rc, _ = sysg.solve(dev(b), rtol=1e-13)
-    assert rc == 0 and rel(x.cpu().numpy(), ref.direct_solve(b)) <= 1e-10
+    assert rc == 0
+    assert_blocks(x.cpu().numpy(), ref.direct_solve(b), sysg.offsets, 1, 1e-10, "x vs x*")
 
 
 def test_fp32_preconditioner_error_statement():
