@@ -29,6 +29,12 @@ HBM_PEAK_GBS = 8000.0
 # counter runs calibrated with a 1 GiB copy (profiles/pmc_cfg3_jacobian_fetch_write.md),
 # valid while the kernel source it measured is unchanged (digest of that source).
 JAC_COUNTERS = {"config": "cfg3", "j_slabs": 8, "source_sha256_16": "2863946ff1f01491", "traffic_bytes": 2.330e9}
+# The same for one launch of the paired sweep-step kernel at the default workload
+# (profiles/pmc_cfg3_sweep_step_fetch_write.md); None until measured.
+SWEEP_COUNTERS = {"config": "cfg3", "source_sha256_16": None, "traffic_bytes": None}
+# rocprofv3 average duration of that kernel at the default workload without event sampling
+# (profiles/kstats_cfg3_fgmres_fp32_pipeline.md), valid for the same kernel source.
+SWEEP_ROCPROF = {"config": "cfg3", "source_sha256_16": "edf3e1f027282742", "avg_us": 4.159}
 
 
 def jacobian_kernel_digest():
@@ -37,6 +43,19 @@ def jacobian_kernel_digest():
     a = src.index("struct SpmvSlabsArgs {")
     b = src.index("// Fused Chebyshev-Jacobi step for A x = b")
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
+def sweep_kernel_digest():
+    """Digest of the stencil step kernel source (the paired sweep-step kernel's bodies)."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2309_00768_amd", "csrc", "kernels.h")).read()
+    a = src.index("// Operator on a structured node grid")
+    b = src.index("// A Chebyshev-Jacobi sweep solve (or a run of its steps)")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+
+
+def variant_name(v):
+    return {"PT": "P_T", "Ptilde": "P-tilde", "P": "full P"}[v]
 
 
 def log(msg):
@@ -52,21 +71,73 @@ def jacobian_bytes(plan, nt, N):
     return 8 * nt * state + 8 * const + 4 * (state + const) + 16 * N, state, const
 
 
-def cpu_baseline(cfg, nt_sample, rtol):
-    """The oracle (exact inner solves, GMRES(30)) on the first slabs of the same workload."""
+def _oracle_worker(cfg_name, nt_sample, seed, rtol, keep_x, barrier, queue):
+    """One oracle solve (exact inner solves, GMRES(30)) on the first nt_sample
+    slabs of a workload, right-hand side seed `seed`; single-threaded.  The
+    setup (assembly and factorisations) runs first; all workers then start
+    their solves together."""
     import oracle
     from paper_2309_00768_amd import inputs
-    ub, ab = inputs.state(cfg)
-    sysm = oracle.SpaceTimeSystem(cfg.n, nt_sample, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub[:nt_sample], ab[:nt_sample])
-    b = inputs.rhs(inputs.Config("s", cfg.n, nt_sample, cfg.dt, cfg.re, cfg.s), cfg.rhs_seeds[0])
-    sysm.apply_PT_inv(b)            # factorisations (setup) outside the timed region
+    cfg = inputs.CONFIGS[cfg_name]
     t0 = time.perf_counter()
+    ub, ab = inputs.state(cfg)
+    sysm = oracle.SpaceTimeSystem(cfg.n, nt_sample, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub[:nt_sample],
+                                  ab[:nt_sample])
+    b = inputs.rhs(inputs.Config("s", cfg.n, nt_sample, cfg.dt, cfg.re, cfg.s), seed)
+    sysm.apply_PT_inv(b)            # factorisations (setup) outside the timed solve
+    setup = time.perf_counter() - t0
+    barrier.wait()
+    t1 = time.perf_counter()
     x, its, _ = oracle.solve_fgmres(sysm, b, rtol=rtol)
-    dt = time.perf_counter() - t0
-    return {"value": sysm.N * its / dt, "unit": "DOF-iter/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle GMRES(30)+P_T with sparse-LU inner solves to {rtol:g} on the first {nt_sample} of "
-                      f"{cfg.nt} slabs of the same workload (N={sysm.N}, {its} iterations, {dt:.1f} s; "
-                      f"single-threaded SuperLU/SciPy, host has {os.cpu_count()} logical CPUs)"}
+    t2 = time.perf_counter()
+    queue.put({"seed": seed, "N": sysm.N, "its": its, "setup_s": setup, "t_start": t1, "t_end": t2,
+               "x": x if keep_x else None})
+
+
+def cpu_baseline(cfg, nt_sample, rtol, workers):
+    """The oracle (exact inner solves, GMRES(30)) on the first `nt_sample` slabs of
+    the same workload, in `workers` single-threaded processes at once, each with
+    its own right-hand side seed (the first with the benchmark's); value = all
+    their DOF-iterations over the wall time from the common start of the solves
+    to the last one's end.  Runs before the GPU is touched (worker processes are
+    started fresh).  Also returns worker 0's solution: J is block
+    lower-bidiagonal in time, so the first nt_sample slabs of the full system's
+    x* are the solution of the nt_sample-slab system."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    barrier, queue = ctx.Barrier(workers), ctx.Queue()
+    env_threads = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in env_threads:
+        os.environ[k] = "1"
+    procs = [ctx.Process(target=_oracle_worker,
+                         args=(cfg.name, nt_sample, cfg.rhs_seeds[0] + 100 * i, rtol, i == 0, barrier, queue))
+             for i in range(workers)]
+    try:
+        for p in procs:
+            p.start()
+        res = [queue.get() for _ in procs]
+        for p in procs:
+            p.join()
+    finally:
+        for k, v in env_threads.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    t0 = min(r["t_start"] for r in res)
+    t1 = max(r["t_end"] for r in res)
+    dof_its = sum(r["N"] * r["its"] for r in res)
+    r0 = next(r for r in res if r["x"] is not None)
+    one = r0["N"] * r0["its"] / (r0["t_end"] - r0["t_start"])
+    out = {"value": dof_its / (t1 - t0), "unit": "DOF-iter/s", "cores": workers, "kind": "oracle",
+           "sample": f"oracle GMRES(30)+P_T with sparse-LU inner solves to {rtol:g} on the first {nt_sample} of "
+                     f"{cfg.nt} slabs of the same workload (N={r0['N']}), {workers} single-threaded processes "
+                     f"at once, one right-hand side each; {dof_its:.3g} DOF-iterations in {t1 - t0:.1f} s "
+                     f"(host has {os.cpu_count()} logical CPUs)",
+           "iterations": [r["its"] for r in res],
+           "one_process_dof_iters_per_s": one,
+           "setup_s_per_process": max(r["setup_s"] for r in res)}
+    return out, r0["x"], r0["its"]
 
 
 def probe_jacobian(cfg, ub, ab, b, dev, launches=5, copy_bytes=1 << 30):
@@ -89,6 +160,31 @@ def probe_jacobian(cfg, ub, ab, b, dev, launches=5, copy_bytes=1 << 30):
     dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"probe": "jacobian", "launches": launches, "algorithmic_bytes_per_launch": jbytes,
+                      "copy_bytes_read": copy_bytes, "copy_bytes_written": copy_bytes}), flush=True)
+
+
+def probe_sweeps(cfg, ub, ab, b, dev, applies=3, copy_bytes=1 << 30):
+    """A few recorded P_T^{-1} applies (FP32) and one device copy of `copy_bytes`,
+    for FETCH_SIZE / WRITE_SIZE counter runs of the paired sweep-step kernel."""
+    import torch
+    from paper_2309_00768_amd import binding
+    plan = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp32")
+    nnz = {k: plan.block_nnz(k) for k in ("Fu", "C0")}
+    sysg = binding.System(plan, dev)
+    plan.close()
+    nu, na = sysg.offsets[2] - sysg.offsets[0], sysg.offsets[5] - sysg.offsets[4]
+    r = torch.from_numpy(b).to(dev)
+    z = torch.empty_like(r)
+    src = torch.ones(copy_bytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(applies):
+        sysg.apply_precond(r, z)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "sweeps", "applies": applies,
+                      "algorithmic_bytes_per_launch": 4 * (nnz["Fu"] + nnz["C0"]) + 28 * (nu + na),
+                      "nnz_Fu": nnz["Fu"], "nnz_CA": nnz["C0"], "rows_u": nu, "rows_A": na,
                       "copy_bytes_read": copy_bytes, "copy_bytes_written": copy_bytes}), flush=True)
 
 
@@ -264,24 +360,48 @@ def main():
     ap.add_argument("--config", default="cfg3")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=1000, help="FGMRES iteration cap of a solve (cfg3 workloads)")
+    ap.add_argument("--restart", type=int, default=30, help="FGMRES restart length m (cfg3 workloads)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-slabs", type=int, default=16)
+    ap.add_argument("--cpu-workers", type=int, default=0, help="oracle processes at once (0: min(16, CPUs))")
+    ap.add_argument("--cpu-rtol", type=float, default=1e-12,
+                    help="oracle tolerance (its solution on the sampled slabs is the reference x*)")
+    ap.add_argument("--sweep-lanes", type=int, default=0, choices=[0, 1, 2],
+                    help="lanes per row of the F_u sweep steps when not autotuned (0: library default)")
+    ap.add_argument("--variant", choices=["PT", "Ptilde", "P"], default="PT",
+                    help="preconditioner: P_T (default), P-tilde or the full P (step by step)")
+    ap.add_argument("--timestep", action="store_true",
+                    help="also solve the workload by sequential time stepping with P_{T,k} (one-slab systems)")
+    ap.add_argument("--profile-every", type=int, default=8,
+                    help="time every k-th launch of the paired sweep-step kernel with HIP events")
     ap.add_argument("--no-separate", action="store_true", help="cfg4: skip the one-at-a-time comparison")
     ap.add_argument("--batch-budget", type=int, default=960, help="cfg4: FGMRES iterations per member")
     ap.add_argument("--no-fd", action="store_true", help="cfg5: skip the finite-difference check")
     ap.add_argument("--no-autotune", action="store_true",
                     help="default launch choices instead of timing them at st_create")
-    ap.add_argument("--probe", choices=["jacobian"], default=None,
-                    help="run only a few J applies and a copy of known size (for hardware-counter runs)")
+    ap.add_argument("--probe", choices=["jacobian", "sweeps"], default=None,
+                    help="run only a few J applies (or P_T applies) and a copy of known size (for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (one system is not sharded "
               f"across GPUs in this build)", file=sys.stderr)
         sys.exit(2)
 
+    from paper_2309_00768_amd import inputs
+
+    cpu = None
+    if args.config not in ("cfg4", "cfg5") and not args.no_cpu and args.probe is None:
+        # before anything touches the GPU: the oracle's worker processes start fresh
+        cfg = inputs.CONFIGS[args.config]
+        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+        log(f"cpu baseline (oracle, {workers} processes, first {args.cpu_slabs} slabs) ...")
+        t0 = time.perf_counter()
+        cpu = cpu_baseline(cfg, args.cpu_slabs, args.cpu_rtol, workers)
+        log(f"cpu baseline done in {time.perf_counter() - t0:.1f} s: {cpu[0]['value']:.3g} DOF-iter/s")
+
     import torch
-    from paper_2309_00768_amd import binding, inputs
+    from paper_2309_00768_amd import binding
 
     dev = torch.device("cuda:0")
     if args.config == "cfg4":
@@ -296,11 +416,17 @@ def main():
     if args.probe == "jacobian":
         probe_jacobian(cfg, ub, ab, b, dev)
         return
+    if args.probe == "sweeps":
+        probe_sweeps(cfg, ub, ab, b, dev)
+        return
     t0 = time.perf_counter()
     tune = not args.no_autotune
-    plan32 = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp32", autotune=tune)
+    m = args.restart
+    plan32 = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp32", autotune=tune,
+                          max_restart=m, sweep_lanes=args.sweep_lanes, variant=args.variant)
     N = plan32.ns * cfg.nt
     jbytes, nnz_state, nnz_const = jacobian_bytes(plan32, cfg.nt, N)
+    plan_nnz = {b: plan32.block_nnz(b) for b in ("Fu", "C0")}
     fu_deg, ca_deg, _, _ = plan32.solver_info()
     inner = (f"Chebyshev-Jacobi sweeps of degree {fu_deg} on F_u,k and {ca_deg} on C_A,k "
              f"(0 = SA-AMG V(1,1)), SA-AMG V(1,1) on K_p")
@@ -311,7 +437,7 @@ def main():
     if not args.no_fp64:
         t0 = time.perf_counter()
         plan64 = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp64",
-                              autotune=tune)
+                              autotune=tune, max_restart=m, sweep_lanes=args.sweep_lanes, variant=args.variant)
         sys64 = binding.System(plan64, dev)
         plan64.close()
         log(f"setup fp64 {time.perf_counter() - t0:.1f} s, launches {sys64.tuning()}")
@@ -321,7 +447,7 @@ def main():
     statuses = []
 
     def solve(sysg):
-        _, info, rc, _ = sysg.solve(bt, x, rtol=args.rtol, restart=30, maxit=args.maxit)
+        _, info, rc, _ = sysg.solve(bt, x, rtol=args.rtol, restart=m, maxit=args.maxit)
         if rc < 0:
             raise RuntimeError(f"solve failed: status {rc}")
         statuses.append(rc)
@@ -330,11 +456,15 @@ def main():
     for i in range(args.warmup):
         info = solve(sys32)
         log(f"warmup {i}: {info.iterations} its, {info.seconds:.3f} s")
+    profiled = sys32.tuning()["precond_launches"] > 0 and args.profile_every > 0
+    if profiled:
+        sys32.profile_kernel(1, args.profile_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = [solve(sys32) for _ in range(args.steps)]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    x32 = x.clone()
     its = sum(i.iterations for i in infos)
     converged = all(rc == 0 for rc in statuses)
     value = N * its / elapsed
@@ -349,7 +479,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32-precond/f64-krylov", "data": "synthetic",
         "config": {"workload": f"{cfg.name}: {cfg.n}x{cfg.n} Q2-Q1/Q1/Q1, Nt={cfg.nt}, dt={cfg.dt}, "
-                               f"Re=S={cfg.re:g}; FGMRES(30) to {args.rtol:g}, P_T in FP32: {inner}",
+                               f"Re=S={cfg.re:g}; FGMRES({m}) to {args.rtol:g}, {variant_name(args.variant)} in FP32: {inner}",
                    "N": N, "nt": cfg.nt, "n": cfg.n},
         "time_to_1e8_s": elapsed / args.steps if converged else None,
         "converged": converged,
@@ -358,6 +488,7 @@ def main():
         "precond_share": sum(i.precond_seconds for i in infos) / elapsed,
         "launch_choices": {"fp32": sys32.tuning(), "autotuned": tune},
     }
+    x64 = None
     if sys64 is not None:
         statuses.clear()
         info64 = solve(sys64)
@@ -366,28 +497,89 @@ def main():
         info64 = solve(sys64)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t0
+        x64 = x.clone()
         ok64 = all(rc == 0 for rc in statuses)
         out["fp64_time_to_1e8_s"] = t64 if ok64 else None
         out["fp64_fgmres_iters"] = info64.iterations
         out["fp32_vs_fp64_speedup"] = t64 / (elapsed / args.steps) if (ok64 and converged) else None
         out["launch_choices"]["fp64"] = sys64.tuning()
         log(f"fp64 precond: {info64.iterations} its, {t64:.3f} s")
-    achieved = jbytes / jac_avg / 1e9
+    # Roofline of the dominant kernel: the paired sweep-step kernel (one
+    # Chebyshev-Jacobi step of an F_u,k solve and one of a C_A,k solve per
+    # launch).  Algorithmic bytes per launch: every true nonzero of the two
+    # slab operators once (4 B in FP32) and 7 vector passes per row (r, x read
+    # and written; d_old, D^{-1} read; d_new written).
+    nnz_fu, nnz_ca = plan_nnz["Fu"], plan_nnz["C0"]
+    nu, na = sys32.offsets[2] - sys32.offsets[0], sys32.offsets[5] - sys32.offsets[4]
+    sweep_bytes = 4 * (nnz_fu + nnz_ca) + 7 * 4 * (nu + na)
+    jac = {"kernel": (f"k_spmv_slabs<{sys32.tuning()['j_slabs']}, 4> (space-time Jacobian apply)"),
+           "bytes_per_launch": jbytes, "avg_launch_ms": jac_avg * 1e3, "launches": jac_n,
+           "achieved_GBs": jbytes / jac_avg / 1e9, "frac": jbytes / jac_avg / 1e9 / HBM_PEAK_GBS,
+           "traffic": None, "nnz_state_per_slab": nnz_state, "nnz_shared": nnz_const}
     nv = sys32.tuning()["j_slabs"]
-    kernel = (f"k_spmv_slabs<{nv}, 4> (space-time Jacobian apply, {nv} slabs per wavefront)" if nv > 1 else
-              "k_spmv<double, double, double, 1> (space-time Jacobian apply, one slab per workgroup row)")
-    traffic = None
     if (args.config == JAC_COUNTERS["config"] and nv == JAC_COUNTERS["j_slabs"]
             and jacobian_kernel_digest() == JAC_COUNTERS["source_sha256_16"]):
-        traffic = JAC_COUNTERS["traffic_bytes"]
-    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                       "kernel": kernel,
-                       "bytes_per_launch": jbytes, "avg_launch_ms": jac_avg * 1e3, "launches": jac_n,
-                       "nnz_state_per_slab": nnz_state, "nnz_shared": nnz_const}
-    if not args.no_cpu:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_slabs, args.rtol)
+        jac["traffic"] = JAC_COUNTERS["traffic_bytes"]
+    if profiled:
+        psec, pn, pseen = sys32.profile_read()
+        p_avg = psec / max(pn, 1)
+        achieved = sweep_bytes / p_avg / 1e9
+        traffic = None
+        if (args.config == SWEEP_COUNTERS["config"] and sweep_kernel_digest() == SWEEP_COUNTERS["source_sha256_16"]):
+            traffic = SWEEP_COUNTERS["traffic_bytes"]
+        frac_rp = None
+        if (args.config == SWEEP_ROCPROF["config"] and sweep_kernel_digest() == SWEEP_ROCPROF["source_sha256_16"]):
+            frac_rp = sweep_bytes / (SWEEP_ROCPROF["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS
+        out["roofline"] = {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "frac_rocprof": frac_rp,
+            "kernel": "k_two<BodyStCheb<float>, BodyStCheb<float>> (paired sweep step: one Chebyshev-Jacobi step "
+                      "of a C_A,k solve and one of an F_u,k solve)",
+            "bytes_per_launch": sweep_bytes, "avg_launch_ms": p_avg * 1e3, "launches_timed": pn,
+            "launches": pseen, "share_of_solve_time": pseen * p_avg / elapsed,
+            "nnz_Fu_per_slab": nnz_fu, "nnz_CA_per_slab": nnz_ca, "rows_u": nu, "rows_A": na,
+            "jacobian": jac}
+    else:
+        out["roofline"] = {"bound": "hbm", "achieved": jac["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": jac["frac"], "traffic": jac["traffic"], "kernel": jac["kernel"],
+                           "bytes_per_launch": jbytes, "avg_launch_ms": jac_avg * 1e3, "launches": jac_n}
+    if args.timestep:
+        # the same workload by sequential time stepping with P_{T,k}: one one-slab
+        # system per slab (FP32 preconditioner), each step to ||r_k|| <= rtol ||b|| / sqrt(Nt)
+        t0 = time.perf_counter()
+        ts = binding.TimeStepping(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, device=dev,
+                                  precision="fp32")
+        log(f"time stepping setup {time.perf_counter() - t0:.1f} s ({cfg.nt} one-slab systems)")
+        xts = torch.zeros_like(bt)
+        ts.solve(bt, xts, rtol=args.rtol)        # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xts, tinfos, trc = ts.solve(bt, xts, rtol=args.rtol)
+        torch.cuda.synchronize()
+        tts = time.perf_counter() - t0
+        step_its = [i.iterations for i in tinfos]
+        avg = sum(step_its) / len(step_its)
+        out["time_stepping"] = {
+            "preconditioner": "P_{T,k} (single step), FP32, FGMRES(30) per step, warm start",
+            "time_s": tts, "converged": trc == 0, "iterations_total": sum(step_its),
+            "iterations_per_step_avg": avg, "iterations_per_step_max": max(step_its),
+            "space_time_over_time_stepping_iterations": (its / args.steps) / avg,
+            "time_stepping_over_space_time_time": tts / (elapsed / args.steps)}
+        log(f"time stepping: {tts:.3f} s, {sum(step_its)} iterations ({avg:.1f} per step)")
+    if cpu is not None:
+        base, xs, its_cpu = cpu
+        k = args.cpu_slabs
+        nk = k * sys32.ns
+        ref = xs[:nk]
+
+        def err(xg):
+            return None if xg is None else float(np.linalg.norm(xg[:nk].cpu().numpy() - ref) / np.linalg.norm(ref))
+        out["error_vs_oracle"] = {
+            "fp32_precond": err(x32), "fp64_precond": err(x64),
+            "reference": f"the oracle's solution of the first {k} slabs (GMRES to {args.cpu_rtol:g} with exact "
+                         f"inner solves, {its_cpu} iterations); J is block lower-bidiagonal in time, so it is the "
+                         f"full system's x* on those slabs"}
+        out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)
 
 

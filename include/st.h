@@ -125,11 +125,23 @@ typedef struct st_problem {
                          one launch per sweep step or the tiled solve) and
                          keeps the fastest (st_tuning reports them); 0: the
                          given or default choices                          */
-  int reserved[1];
+  int sweep_lanes;    /* stencil sweep steps on the two-component F_u,k: 0
+                         default (1), 1 one lane per row, 2 the row's two
+                         column components on two lanes (half the loads per
+                         lane; the same result bit for bit); the autotuner
+                         times both                                         */
   double inner_reduction; /* auto inner solver of F_u,k: target error reduction
                              per spatial solve (0: 0.3; degree at least 4)    */
   double ca_reduction;    /* auto inner solver of C_A,k: target reduction (0: 0.3;
                              degree at least 4)                                */
+  int precond_variant;    /* the preconditioner FGMRES and st_apply_precond use:
+                             0 P_T, eq. (PT) (recorded replay); 1 P-tilde, eq.
+                             (preconditionerSimplified1), one more F_u sweep (the
+                             L_up factor); 2 the full P, eq. (preconditioner),
+                             two more F_u sweeps and an M_j solve (the L_ujA and
+                             L_up factors).  1 and 2 run step by step, forward
+                             only: st_apply_precond_t, the adjoint solve and
+                             batches take 0 only (ST_EINVAL otherwise).      */
 } st_problem;
 
 typedef struct st_opts {
@@ -259,6 +271,24 @@ int st_fgmres_solve(st_handle* h, const double* b, double* x, const st_opts* o,
 int st_adjoint_solve(st_handle* h, const double* g, double* lam, const st_opts* o,
                      st_info* info, void* stream);
 
+/* Sequential time stepping, the baseline the all-at-once solve is compared
+ * with (Sec. "Comparison with sequential time-stepping"): slab k is solved
+ * after slab k-1 from J_k x^k = b^k + diag(M_u/dt, 0, 0, M_A/dt) x^{k-1}, J_k the
+ * single-step Jacobian of eq. (jacobianDiscrete), by FGMRES(m)
+ * right-preconditioned with the single-step P_{T,k} of eq. (PTTS) (with eq.
+ * (ASchurApproxTS)).  hs[k] is a handle created from a one-slab plan (Nt = 1)
+ * of slab k's state, whose P_T is P_{T,k}; all handles share n.  b, x: device,
+ * length nt * Ns, slab-major, the same layout as the all-at-once system.
+ * Step k stops on ||r_k||_2 <= max(rtol ||b||_2, atol) / sqrt(nt) (the paper's
+ * scaling of the step tolerance; the step residuals are the rows of the
+ * space-time residual, so x meets ||b - J x|| <= max(rtol ||b||, atol)).  With
+ * o->x0_given = 1 each step k >= 2 starts from x^{k-1} (the paper's warm
+ * start), else from zero.  infos[k] receives step k's result.  Blocks until
+ * done.  Returns ST_OK if every step converged, ST_ENOTCONV if some did not
+ * (later steps still run from that iterate), else an error. */
+int st_timestep_solve(st_handle* const* hs, int nt, const double* b, double* x, const st_opts* o,
+                      st_info* infos, void* stream);
+
 /* ------------------------------------------------------------ batches --- */
 /* Many independent space-time systems (uneven n and Nt) solved together: the
  * same right-preconditioned FGMRES(m) as st_fgmres_solve on each member, run
@@ -299,10 +329,26 @@ int st_sizes(const st_handle* h, int64_t* n_total, int* ns, int* nt);
 /* Launch choices in effect for a created system (tuned when
    st_problem.autotune = 1): slabs per wavefront of the J apply, rows per
    workgroup of the sweep step kernels, 1 if the sweep solves run as tiled
-   multi-step launches, and the number of launches of one recorded
-   P_T^{-1} apply (0 when it is launched step by step).  Any pointer may be
-   NULL. */
-int st_tuning(const st_handle* h, int* j_slabs, int* step_rows, int* sweep_fuse, int* precond_launches);
+   multi-step launches, the number of launches of one recorded P_T^{-1}
+   apply (0 when it is launched step by step) and the lanes per row of the
+   F_u,k step kernels.  Any pointer may be NULL. */
+int st_tuning(const st_handle* h, int* j_slabs, int* step_rows, int* sweep_fuse, int* precond_launches,
+              int* step_lanes);
+
+/* Sampled timing of the dominant preconditioner kernel inside solves, for
+ * roofline measurements.  kernel = 1 times the paired sweep-step kernel of
+ * the recorded P_T^{-1} replay (one Chebyshev step of the C_A sweep, eq.
+ * (CAs), and one of the F_u sweep, eq. (STFu), in one launch): every
+ * `every`-th launch of it is issued with a pair of HIP events that take that
+ * dispatch's start and end times (hipExtLaunchKernel; no packets between
+ * launches; a pool of 8192 pairs, read after each st_fgmres_solve).  kernel = 0
+ * turns it off.  Either call resets the counts.  ST_EINVAL if the handle
+ * replays no recorded programs (single_stream = 1).  Host only. */
+int st_profile_kernel(st_handle* h, int kernel, int every);
+
+/* Summed event-timed duration (seconds) of the sampled launches, how many were
+ * timed and how many launches of that kernel ran since st_profile_kernel. */
+int st_profile_read(const st_handle* h, double* seconds, int64_t* launches_timed, int64_t* launches_seen);
 
 const char* st_error_string(int code);
 

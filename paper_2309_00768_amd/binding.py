@@ -35,8 +35,9 @@ class StProblem(ctypes.Structure):
         ("adjoint", ctypes.c_int), ("j_lanes", ctypes.c_int), ("sweep_format", ctypes.c_int),
         ("single_stream", ctypes.c_int), ("sweep_chunk", ctypes.c_int), ("sweep_chain", ctypes.c_int),
         ("j_slabs", ctypes.c_int), ("sweep_fuse", ctypes.c_int),
-        ("autotune", ctypes.c_int), ("reserved", ctypes.c_int * 1),
+        ("autotune", ctypes.c_int), ("sweep_lanes", ctypes.c_int),
         ("inner_reduction", ctypes.c_double), ("ca_reduction", ctypes.c_double),
+        ("precond_variant", ctypes.c_int),
     ]
 
 
@@ -59,8 +60,10 @@ EXPORTED = [
     "st_plan_create", "st_plan_workspace_size", "st_plan_sizes", "st_plan_export_block", "st_plan_export_jbar",
     "st_plan_solver_info", "st_plan_jacobian_slots",
     "st_plan_destroy", "st_create", "st_destroy", "st_apply_jacobian", "st_apply_jacobian_t",
-    "st_apply_precond", "st_apply_precond_t", "st_apply_initial_coupling", "st_fgmres_solve", "st_adjoint_solve",
-    "st_sizes", "st_tuning", "st_batch_create", "st_batch_workspace_size", "st_batch_upload", "st_batch_launch_counts",
+    "st_apply_precond", "st_apply_precond_t", "st_apply_initial_coupling",
+    "st_fgmres_solve", "st_adjoint_solve", "st_timestep_solve",
+    "st_sizes", "st_tuning", "st_profile_kernel", "st_profile_read", "st_batch_create", "st_batch_workspace_size",
+    "st_batch_upload", "st_batch_launch_counts",
     "st_fgmres_solve_batched", "st_batch_destroy",
     "st_error_string",
 ]
@@ -91,8 +94,12 @@ def _load(path=LIB_PATH):
         "st_apply_initial_coupling": ([vp, vp, vp, vp], ctypes.c_int),
         "st_fgmres_solve": ([vp, vp, vp, ctypes.POINTER(StOpts), ctypes.POINTER(StInfo), vp], ctypes.c_int),
         "st_adjoint_solve": ([vp, vp, vp, ctypes.POINTER(StOpts), ctypes.POINTER(StInfo), vp], ctypes.c_int),
+        "st_timestep_solve": ([ctypes.POINTER(vp), ctypes.c_int, vp, vp, ctypes.POINTER(StOpts),
+                               ctypes.POINTER(StInfo), vp], ctypes.c_int),
         "st_sizes": ([vp, i64p, ip, ip], ctypes.c_int),
-        "st_tuning": ([vp, ip, ip, ip, ip], ctypes.c_int),
+        "st_tuning": ([vp, ip, ip, ip, ip, ip], ctypes.c_int),
+        "st_profile_kernel": ([vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "st_profile_read": ([vp, dp, i64p, i64p], ctypes.c_int),
         "st_batch_create": ([ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
         "st_batch_workspace_size": ([vp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "st_batch_upload": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
@@ -143,7 +150,7 @@ class Plan:
                  inner_iters=0, mass_iters=0, cheb_degree=0, max_restart=0, sell_sigma=0, adjoint=False,
                  fu_solver=0, ca_solver=0, inner_reduction=0.0, j_lanes=0, ca_reduction=0.0, sweep_format=0,
                  single_stream=False, sweep_chunk=0, sweep_chain=True, j_slabs=0, sweep_fuse=False,
-                 autotune=False):
+                 autotune=False, sweep_lanes=0, variant="PT"):
         self._ub = np.ascontiguousarray(ubar, dtype=np.float64)
         self._ab = np.ascontiguousarray(abar, dtype=np.float64)
         assert self._ub.shape == (nt, 2, (2 * n + 1) ** 2) and self._ab.shape == (nt, (n + 1) ** 2)
@@ -163,6 +170,8 @@ class Plan:
         p.j_slabs = j_slabs
         p.sweep_fuse = 1 if sweep_fuse else 0
         p.autotune = int(autotune)
+        p.sweep_lanes = sweep_lanes
+        p.precond_variant = {"PT": 0, "Ptilde": 1, "P": 2}[variant]
         self.problem = p
         self.n, self.nt = n, nt
         h = ctypes.c_void_p()
@@ -303,11 +312,22 @@ class System:
     def tuning(self):
         """Launch choices in effect (``st_tuning``): J slabs per wavefront, sweep
         step rows per workgroup, tiled sweep solves, launches per P_T apply."""
-        js, rows, fuse, pl = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _check(lib().st_tuning(self.ptr, ctypes.byref(js), ctypes.byref(rows), ctypes.byref(fuse), ctypes.byref(pl)),
-               "st_tuning")
+        js, rows, fuse, pl, lanes = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().st_tuning(self.ptr, ctypes.byref(js), ctypes.byref(rows), ctypes.byref(fuse), ctypes.byref(pl),
+                               ctypes.byref(lanes)), "st_tuning")
         return {"j_slabs": js.value, "step_rows": rows.value, "sweep_fuse": bool(fuse.value),
-                "precond_launches": pl.value}
+                "precond_launches": pl.value, "step_lanes": lanes.value}
+
+    def profile_kernel(self, kernel=1, every=8):
+        """Sampled event timing of the paired sweep-step kernel (``st_profile_kernel``)."""
+        _check(lib().st_profile_kernel(self.ptr, kernel, every), "st_profile_kernel")
+
+    def profile_read(self):
+        """(seconds summed over timed launches, launches timed, launches seen)."""
+        sec, n, seen = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().st_profile_read(self.ptr, ctypes.byref(sec), ctypes.byref(n), ctypes.byref(seen)),
+               "st_profile_read")
+        return sec.value, n.value, seen.value
 
     def close(self):
         if getattr(self, "ptr", None):
@@ -319,6 +339,38 @@ class System:
             self.close()
         except Exception:
             pass
+
+
+class TimeStepping:
+    """Sequential time stepping with the single-step preconditioner P_{T,k}
+    (``st_timestep_solve``): one one-slab system per slab of the state."""
+
+    def __init__(self, n, nt, dt, mu, eta, mu0, ubar, abar, device="cuda:0", precision="fp64", inner="amg",
+                 restart=30, **plan_kw):
+        self.systems = []
+        for k in range(nt):
+            plan = Plan(n, 1, dt, mu, eta, mu0, ubar[k:k + 1], abar[k:k + 1], precision=precision, inner=inner,
+                        max_restart=restart, **plan_kw)
+            self.systems.append(System(plan, device))
+            plan.close()
+        self.nt, self.ns, self.restart = nt, self.systems[0].ns, restart
+        self.N = self.nt * self.ns
+        self.offsets = self.systems[0].offsets
+
+    def solve(self, b, x=None, rtol=1e-8, atol=0.0, maxit=1000, warm_start=True, stream=None):
+        """Returns (x, per-step infos, status)."""
+        import torch
+        assert b.dtype == torch.float64 and b.is_cuda and b.is_contiguous() and b.numel() == self.N
+        x = torch.zeros_like(b) if x is None else x
+        o = StOpts()
+        o.restart, o.maxit, o.rtol, o.atol, o.x0_given = self.restart, maxit, rtol, atol, int(warm_start)
+        o.history_len = 0
+        o.history = ctypes.POINTER(ctypes.c_double)()
+        infos = (StInfo * self.nt)()
+        arr = (ctypes.c_void_p * self.nt)(*[s.ptr.value for s in self.systems])
+        rc = _check(lib().st_timestep_solve(arr, self.nt, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                            ctypes.byref(o), infos, _stream_ptr(stream)), "st_timestep_solve")
+        return x, list(infos), rc
 
 
 class Batch:

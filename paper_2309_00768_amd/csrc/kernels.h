@@ -360,43 +360,132 @@ struct StOp {
   int64_t rows;
 };
 
+// Raw buffer access (CDNA buffer resource over [base, base + bytes)): the
+// base lives in scalar registers, each lane supplies a 32-bit byte offset and
+// a wavefront-uniform byte offset can ride in a scalar register, so a load
+// needs no 64-bit address arithmetic per lane.  Offsets past `bytes` read 0.
+typedef unsigned int st_u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kBufFlags = 0x00020000;   // dword 3 of the resource: 32-bit raw data
+
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(bytes), kBufFlags);
+}
+template <class T>
+__device__ inline T buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ inline float buf_ld<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), 0));
+}
+template <>
+__device__ inline double buf_ld<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff), 0));
+}
+template <class T>
+__device__ inline void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, T v);
+template <>
+__device__ inline void buf_st<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, int(voff), 0, 0);
+}
+template <>
+__device__ inline void buf_st<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(st_u32x2, v), r, int(voff), 0, 0);
+}
+
 // (A x)[row] for a stencil operator of radius RAD with NCC column components
 // summed (1, or 2 for the coupled velocity components); every coefficient and
 // neighbour load is independent of the others (one memory round trip).
 // Neighbours outside the column grid have zero coefficients; their (clamped)
-// addresses stay inside x.
+// addresses stay inside x.  The coefficient planes of the row's value set and
+// x are read through buffer resources: the plane offset is uniform (scalar),
+// the row's byte offset and the neighbours' are 32-bit (a set of planes and x
+// stay below 4 GB).
 template <int RAD, int NCC, class T, class TA>
 __device__ inline TA stencil_row_n(const StOp<T>& A, int set, int64_t row, const T* __restrict__ x) {
   constexpr int W = 2 * RAD + 1, NS = W * W;
-  const int64_t per = int64_t(A.gx) * A.gy, cper = int64_t(A.cgx) * A.cgy;
-  const int c = int(row / per);
-  const int rem = int(row - int64_t(c) * per);
-  const int i = rem % A.gx - A.shift, j = rem / A.gx - A.shift;
-  const T* __restrict__ cf = A.coef + (A.set_stride ? int64_t(set) * A.set_stride : 0) + row;
-  int off[NS];
+  constexpr uint32_t B = uint32_t(sizeof(T));
+  const uint32_t per = uint32_t(A.gx) * uint32_t(A.gy), cper = uint32_t(A.cgx) * uint32_t(A.cgy);
+  const uint32_t r32 = uint32_t(row);
+  const uint32_t c = r32 / per;
+  const uint32_t rem = r32 - c * per;
+  const int i = int(rem % uint32_t(A.gx)) - A.shift, j = int(rem / uint32_t(A.gx)) - A.shift;
+  const uint32_t rows = uint32_t(A.rows);
+  const __amdgpu_buffer_rsrc_t rc =
+      buf_rsrc(A.coef + (A.set_stride ? int64_t(set) * A.set_stride : 0), uint32_t(A.nslot) * rows * B);
+  const __amdgpu_buffer_rsrc_t rx = buf_rsrc(x, uint32_t(A.ncomp) * cper * B);
+  const uint32_t rb = r32 * B;
+  uint32_t off[NS];
+  int xs[W];
+#pragma unroll
+  for (int dx = -RAD; dx <= RAD; ++dx) xs[dx + RAD] = min(max(i + dx, 0), A.cgx - 1);
 #pragma unroll
   for (int dy = -RAD; dy <= RAD; ++dy) {
-    const int jj = min(max(j + dy, 0), A.cgy - 1);
+    const int jj = min(max(j + dy, 0), A.cgy - 1) * A.cgx;
 #pragma unroll
-    for (int dx = -RAD; dx <= RAD; ++dx) off[(dy + RAD) * W + dx + RAD] = jj * A.cgx + min(max(i + dx, 0), A.cgx - 1);
+    for (int dx = -RAD; dx <= RAD; ++dx) off[(dy + RAD) * W + dx + RAD] = uint32_t(jj + xs[dx + RAD]);
   }
   T cv[NCC][NS], xv[NCC][NS];
 #pragma unroll
   for (int q = 0; q < NCC; ++q) {
-    const T* __restrict__ xc = x + int64_t(NCC == 1 && A.diag_comp ? c : q) * cper;
-    const T* __restrict__ cq = cf + int64_t(q) * NS * A.rows;
+    const uint32_t cb = (NCC == 1 && A.diag_comp ? c : uint32_t(q)) * cper;
 #pragma unroll
     for (int o = 0; o < NS; ++o) {
-      cv[q][o] = cq[int64_t(o) * A.rows];
-      xv[q][o] = xc[off[o]];
+      cv[q][o] = buf_ld<T>(rc, rb, uint32_t(q * NS + o) * rows * B);
+      xv[q][o] = buf_ld<T>(rx, (cb + off[o]) * B, 0u);
     }
   }
+  // one partial sum per column component, then their sum (the order every
+  // form of this product keeps, so that they agree bit for bit)
   TA acc = TA(0);
 #pragma unroll
-  for (int q = 0; q < NCC; ++q)
+  for (int q = 0; q < NCC; ++q) {
+    TA part = TA(0);
 #pragma unroll
-    for (int o = 0; o < NS; ++o) acc += TA(cv[q][o]) * TA(xv[q][o]);
+    for (int o = 0; o < NS; ++o) part += TA(cv[q][o]) * TA(xv[q][o]);
+    acc = q == 0 ? part : acc + part;
+  }
   return acc;
+}
+
+// The same for a two-component operator with the row's two column
+// components on two neighbouring lanes (lane 2t + q sums component q of row
+// t): half the loads per lane, then the partial sums are exchanged, so both
+// lanes return the sum partial_0 + partial_1 of the one-lane form.
+template <int RAD, class T>
+__device__ inline T stencil_row_2lane(const StOp<T>& A, int set, int64_t row, const T* __restrict__ x, int q) {
+  constexpr int W = 2 * RAD + 1, NS = W * W;
+  constexpr uint32_t B = uint32_t(sizeof(T));
+  const uint32_t per = uint32_t(A.gx) * uint32_t(A.gy), cper = uint32_t(A.cgx) * uint32_t(A.cgy);
+  const uint32_t r32 = uint32_t(row);
+  const uint32_t c = r32 / per;
+  const uint32_t rem = r32 - c * per;
+  const int i = int(rem % uint32_t(A.gx)) - A.shift, j = int(rem / uint32_t(A.gx)) - A.shift;
+  const uint32_t rows = uint32_t(A.rows);
+  const __amdgpu_buffer_rsrc_t rc =
+      buf_rsrc(A.coef + (A.set_stride ? int64_t(set) * A.set_stride : 0), uint32_t(A.nslot) * rows * B);
+  const __amdgpu_buffer_rsrc_t rx = buf_rsrc(x, uint32_t(A.ncomp) * cper * B);
+  const uint32_t rb = (uint32_t(q) * uint32_t(NS) * rows + r32) * B;
+  const uint32_t cb = uint32_t(q) * cper;
+  uint32_t off[NS];
+  int xs[W];
+#pragma unroll
+  for (int dx = -RAD; dx <= RAD; ++dx) xs[dx + RAD] = min(max(i + dx, 0), A.cgx - 1);
+#pragma unroll
+  for (int dy = -RAD; dy <= RAD; ++dy) {
+    const int jj = min(max(j + dy, 0), A.cgy - 1) * A.cgx;
+#pragma unroll
+    for (int dx = -RAD; dx <= RAD; ++dx) off[(dy + RAD) * W + dx + RAD] = uint32_t(jj + xs[dx + RAD]);
+  }
+  T cv[NS], xv[NS];
+#pragma unroll
+  for (int o = 0; o < NS; ++o) {
+    cv[o] = buf_ld<T>(rc, rb, uint32_t(o) * rows * B);
+    xv[o] = buf_ld<T>(rx, (cb + off[o]) * B, 0u);
+  }
+  T part = T(0);
+#pragma unroll
+  for (int o = 0; o < NS; ++o) part += cv[o] * xv[o];
+  const T other = __shfl_xor(part, 1);
+  return q == 0 ? part + other : other + part;
 }
 
 // The same for any operator: one column component (diagonal-component
@@ -405,6 +494,15 @@ template <int RAD, class T, class TA>
 __device__ inline TA stencil_row(const StOp<T>& A, int set, int64_t row, const T* __restrict__ x) {
   if (A.diag_comp || A.ncomp == 1) return stencil_row_n<RAD, 1, T, TA>(A, set, row, x);
   return stencil_row_n<RAD, 2, T, TA>(A, set, row, x);
+}
+
+// Row product with one lane per row, or (lanes == 2, two-component operators)
+// component q of the row on this lane; the same value either way.
+template <class T>
+__device__ inline T stencil_row_lanes(const StOp<T>& A, int set, int64_t row, const T* __restrict__ x, int lanes,
+                                      int q) {
+  if (lanes == 2) return stencil_row_2lane<2, T>(A, set, row, x, q);
+  return stencil_row<2, T, T>(A, set, row, x);
 }
 
 // First step of a sweep solve with Chebyshev-Jacobi alone, fused with the
@@ -428,26 +526,32 @@ struct StInitArgs {
   int64_t rows;
   int guess;
   double g1, g2;
-  int rpb;              // rows per workgroup (<= kBlock; fewer spread a small grid over more CUs)
+  int rpb;              // rows per workgroup (lanes * rpb <= kBlock; fewer spread a small grid over more CUs)
+  int lanes;            // 1, or 2 for two-component operators: a row's components on two lanes
 };
 
 template <class T>
 __device__ inline void st_init_body(const StInitArgs<T>& a, int bx) {
-  if (int(threadIdx.x) >= a.rpb) return;
-  const int64_t row = int64_t(bx) * a.rpb + threadIdx.x;
-  if (row >= a.rows) return;
-  T acc = a.q[row];
-  if (a.n1) acc += T(a.a1) * stencil_row<2, T, T>(a.S1, a.set1, row, a.y1);
-  if (a.n2) acc += T(a.a2) * stencil_row<2, T, T>(a.S2, a.set2, row, a.y2);
-  const T d = a.dinv[row] * acc / T(a.theta);
+  const int lq = a.lanes == 2 ? int(threadIdx.x & 1) : 0;
+  const int t = a.lanes == 2 ? int(threadIdx.x >> 1) : int(threadIdx.x);
+  if (t >= a.rpb) return;
+  const int64_t row = int64_t(bx) * a.rpb + t;
+  if (row >= a.rows) return;   // both lanes of a row leave together
+  const uint32_t vb = uint32_t(a.rows) * uint32_t(sizeof(T)), ro = uint32_t(row) * uint32_t(sizeof(T));
+  T acc = buf_ld<T>(buf_rsrc(a.q, vb), ro, 0u);
+  const T dg = buf_ld<T>(buf_rsrc(a.dinv, vb), ro, 0u);
+  if (a.n1) acc += T(a.a1) * stencil_row_lanes<T>(a.S1, a.set1, row, a.y1, a.lanes, lq);
+  if (a.n2) acc += T(a.a2) * stencil_row_lanes<T>(a.S2, a.set2, row, a.y2, a.lanes, lq);
+  const T d = dg * acc / T(a.theta);
   T x0 = T(0);
   if (a.guess) {
-    x0 = T(a.g1) * a.y1[row];
-    if (a.g2 != 0.0) x0 += T(a.g2) * a.y2[row];
+    x0 = T(a.g1) * buf_ld<T>(buf_rsrc(a.y1, vb), ro, 0u);
+    if (a.g2 != 0.0) x0 += T(a.g2) * buf_ld<T>(buf_rsrc(a.y2, vb), ro, 0u);
   }
-  a.r[row] = acc;
-  a.d[row] = d;
-  a.x[row] = x0 + d;
+  if (lq) return;
+  buf_st<T>(buf_rsrc(a.r, vb), ro, acc);
+  buf_st<T>(buf_rsrc(a.d, vb), ro, d);
+  buf_st<T>(buf_rsrc(a.x, vb), ro, x0 + d);
 }
 
 template <class T, int Role>
@@ -467,23 +571,31 @@ struct StChebArgs {
   T* r;
   T* x;
   int64_t rows;
-  int rpb;              // rows per workgroup (<= kBlock)
+  int rpb;              // rows per workgroup (lanes * rpb <= kBlock)
+  int lanes;            // 1, or 2 for a two-component operator (see StInitArgs)
 };
 
 template <class T>
 __device__ inline void st_cheb_body(const StChebArgs<T>& a, int bx) {
-  if (int(threadIdx.x) >= a.rpb) return;
-  const int64_t row = int64_t(bx) * a.rpb + threadIdx.x;
-  if (row >= a.rows) return;
-  const T od = a.dold[row];
-  const T dg = a.dinv[row];
-  const T rr = a.r[row];
-  const T t = stencil_row<2, T, T>(a.A, a.set, row, a.dold);
+  const int lq = a.lanes == 2 ? int(threadIdx.x & 1) : 0;
+  const int tr = a.lanes == 2 ? int(threadIdx.x >> 1) : int(threadIdx.x);
+  if (tr >= a.rpb) return;
+  const int64_t row = int64_t(bx) * a.rpb + tr;
+  if (row >= a.rows) return;   // both lanes of a row leave together
+  const uint32_t vb = uint32_t(a.rows) * uint32_t(sizeof(T)), ro = uint32_t(row) * uint32_t(sizeof(T));
+  const __amdgpu_buffer_rsrc_t rd = buf_rsrc(a.dold, vb), rg = buf_rsrc(a.dinv, vb), rr_ = buf_rsrc(a.r, vb),
+                               rn_ = buf_rsrc(a.dnew, vb), rx = buf_rsrc(a.x, vb);
+  const T od = buf_ld<T>(rd, ro, 0u);
+  const T dg = buf_ld<T>(rg, ro, 0u);
+  const T rr = buf_ld<T>(rr_, ro, 0u);
+  const T xo = buf_ld<T>(rx, ro, 0u);
+  const T t = stencil_row_lanes<T>(a.A, a.set, row, a.dold, a.lanes, lq);
   const T rn = rr - t;
   const T d = T(a.c1) * od + T(a.c2) * dg * rn;
-  a.r[row] = rn;
-  a.dnew[row] = d;
-  a.x[row] += d;
+  if (lq) return;
+  buf_st<T>(rr_, ro, rn);
+  buf_st<T>(rn_, ro, d);
+  buf_st<T>(rx, ro, xo + d);
 }
 
 template <class T, int Role>
@@ -557,9 +669,12 @@ __device__ inline T stencil_row_lds_n(const StOp<T>& A, int set, int64_t row, in
   }
   T acc = T(0);
 #pragma unroll
-  for (int q = 0; q < NCC; ++q)
+  for (int q = 0; q < NCC; ++q) {
+    T part = T(0);
 #pragma unroll
-    for (int o = 0; o < NS; ++o) acc += cv[q][o] * xv[q][o];
+    for (int o = 0; o < NS; ++o) part += cv[q][o] * xv[q][o];
+    acc = q == 0 ? part : acc + part;
+  }
   return acc;
 }
 

@@ -135,6 +135,7 @@ WsLayout workspace_layout(const Plan& P) {
   L.small = take(8 * 64 + 8 * 4 * size_t(m + 2));
   L.partial = take(8 * size_t(kPartialBlocks) * (m + 2));
   L.psum = take(8 * size_t(d.nt) * 2);
+  L.pt_begin = L.psum;
   const size_t nt = d.nt;
   L.ru = take(ts * nt * d.nu);
   L.yu = take(ts * nt * d.nu);
@@ -178,6 +179,18 @@ static int build_plan(Plan& P, std::string& err) {
   }
   if (pr.sweep_fuse != 0 && pr.sweep_fuse != 1) {
     err = "sweep_fuse must be 0 or 1";
+    return ST_EINVAL;
+  }
+  if (pr.precond_variant < 0 || pr.precond_variant > 2) {
+    err = "precond_variant must be 0 (P_T), 1 (P-tilde) or 2 (P)";
+    return ST_EINVAL;
+  }
+  if (pr.precond_variant != 0 && pr.adjoint) {
+    err = "the transposed preconditioner exists for P_T only (precond_variant 0)";
+    return ST_EINVAL;
+  }
+  if (pr.sweep_lanes < 0 || pr.sweep_lanes > 2) {
+    err = "sweep_lanes must be 0, 1 or 2";
     return ST_EINVAL;
   }
   if (pr.autotune != 0 && pr.autotune != 1) {
@@ -258,6 +271,9 @@ static int build_plan(Plan& P, std::string& err) {
     // C_A sweep couplings: rhs = s^k + (1/dt) C1_{k-1} y^{k-1} - (1/dt^2) C2 y^{k-2}
     P.C1 = pack_sell(img, {&b.C1, &b.C2}, fp, sigma);
   }
+  P.variant = pr.precond_variant;
+  if (P.variant >= 1) P.Bv = pack_sell(img, {&b.B}, fp, sigma);
+  if (P.variant == 2) P.Yv = pack_sell(img, {&b.Y}, fp, sigma);
   if (pr.adjoint) {
     P.KjAt = pack_sell(img, {&b.KjAt}, fp, sigma);
     P.B = pack_sell(img, {&b.B}, fp, sigma);

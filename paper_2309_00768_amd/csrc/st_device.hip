@@ -6,6 +6,7 @@
 // PCD operator of eq. (Fp) and the magnetic Schur approximation
 // S_A^{-1} ~ C_A^{-1} F_A M_A^{-1} of eq. (ASchurApprox); GMRES on J with right
 // preconditioning (Sec. "Performance of preconditioner").
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -76,9 +77,15 @@ struct Handle {
   int first_chunk = 0;             // slabs in the first chunk of the recorded forward apply (0: chunk)
   int mj_place = 1;                // current solves: 0 the program that finishes b first, 1 b, 2 a
   int step_rows = 0;               // rows per workgroup of the sweep step kernels (0: by precision)
+  int step_lanes = 1;              // lanes per row of the two-component (F_u) step kernels: 1 or 2
   char* base = nullptr;
   WsLayout L;
+  // Preconditioner scratch: null = in the workspace at its layout offsets;
+  // otherwise the range [L.pt_begin, L.end) is relocated to sbase.
+  char* sbase = nullptr;
   DGroup J, JT, MA, Mj, Mp, FA, FAt, Fp, Fpt, KjA, KjAt, Bt, B, Zj, Zjt, ZAt, Mu, C1, C1t, MA64;
+  DGroup Yv, Bv;                   // Y and B for the lower factors of P and P-tilde
+  int variant = 0;                 // 0 P_T, 1 P-tilde, 2 P
   const void *dMA = nullptr, *dMj = nullptr, *dMp = nullptr;
   const double* mp_rowsum = nullptr;
   double msum = 1.0;              // 1^T M_p 1 (the area)
@@ -98,6 +105,15 @@ struct Handle {
   std::vector<ReplayItem> pt_items, pt_items_t;   // forward and transposed applies
   const double** rslot = nullptr;
   double** zslot = nullptr;
+  // Sampled event timing of one kernel of the replayed preconditioner
+  // (st_profile_kernel): every prof_every-th launch of prof_fn is bracketed by
+  // a pair of events from a pool; the pairs are read after each solve.
+  const void* prof_fn = nullptr;
+  int prof_every = 0;
+  int64_t prof_seen = 0, prof_n = 0;
+  double prof_ms = 0.0;
+  std::vector<hipEvent_t> prof_ev;
+  size_t prof_used = 0;
 };
 
 }  // namespace st
@@ -121,6 +137,12 @@ namespace {
 template <class T>
 T* at(char* base, size_t off) {
   return reinterpret_cast<T*>(base + off);
+}
+
+// A preconditioner scratch buffer at layout offset off (off >= L.pt_begin).
+template <class T>
+T* scr(const Handle& H, size_t off) {
+  return H.sbase ? reinterpret_cast<T*>(H.sbase + (off - H.L.pt_begin)) : at<T>(H.base, off);
 }
 
 DGroup mirror(char* base, const SellGroup& g) {
@@ -503,8 +525,12 @@ void sweep_step_stencil(Ctx& c, Handle& H, DAmg& a, const StencilOp& A, const St
   ia.guess = guess ? 1 : 0;
   ia.g1 = g1;
   ia.g2 = g2;
-  const int rpb = H.step_rows > 0 ? H.step_rows : st_rows<T>();
+  // Two lanes per row only for two-component operators (F_u,k and its coupling).
+  auto two = [](const StencilOp* o) { return !o || (o->ncomp == 2 && !o->diag_comp); };
+  const int lanes = H.step_lanes == 2 && two(&A) && two(S1) && two(S2) ? 2 : 1;
+  const int rpb = std::min(H.step_rows > 0 ? H.step_rows : st_rows<T>(), kBlock / lanes);
   ia.rpb = rpb;
+  ia.lanes = lanes;
   if (H.sweep_fuse && solve_fusable(A)) {
     StSolveArgs<T> sa;
     std::memset(&sa, 0, sizeof(sa));
@@ -544,6 +570,7 @@ void sweep_step_stencil(Ctx& c, Handle& H, DAmg& a, const StencilOp& A, const St
   ca.r = r;
   ca.x = x;
   ca.rpb = rpb;
+  ca.lanes = lanes;
   T* d[2] = {d0, d1};
   const double sigma = theta / delta;
   double rho_prev = 1.0 / sigma, rho = rho_prev;
@@ -575,13 +602,13 @@ int precond_forward(Handle& H, const double* r, double* z, Ctx& c, Ctx& ca, cons
   const int nt = d.nt;
   char* B = H.base;
   const WsLayout& L = H.L;
-  T* ru = at<T>(B, L.ru); T* yu = at<T>(B, L.yu); T* xu = at<T>(B, L.xu);
-  T* rp = at<T>(B, L.rp); T* q = at<T>(B, L.q); T* t = at<T>(B, L.t); T* xp = at<T>(B, L.xp);
-  T* rj = at<T>(B, L.rj); T* yj = at<T>(B, L.yj);
-  T* ra = at<T>(B, L.ra); T* w = at<T>(B, L.wA); T* sA = at<T>(B, L.sA); T* yA = at<T>(B, L.yA);
-  T* mr = at<T>(B, L.mr); T* md0 = at<T>(B, L.md0); T* md1 = at<T>(B, L.md1);
-  T* mr2 = at<T>(B, L.mr2); T* md02 = at<T>(B, L.md02); T* md12 = at<T>(B, L.md12);
-  double* psum = at<double>(B, L.psum);
+  T* ru = scr<T>(H, L.ru); T* yu = scr<T>(H, L.yu); T* xu = scr<T>(H, L.xu);
+  T* rp = scr<T>(H, L.rp); T* q = scr<T>(H, L.q); T* t = scr<T>(H, L.t); T* xp = scr<T>(H, L.xp);
+  T* rj = scr<T>(H, L.rj); T* yj = scr<T>(H, L.yj);
+  T* ra = scr<T>(H, L.ra); T* w = scr<T>(H, L.wA); T* sA = scr<T>(H, L.sA); T* yA = scr<T>(H, L.yA);
+  T* mr = scr<T>(H, L.mr); T* md0 = scr<T>(H, L.md0); T* md1 = scr<T>(H, L.md1);
+  T* mr2 = scr<T>(H, L.mr2); T* md02 = scr<T>(H, L.md02); T* md12 = scr<T>(H, L.md12);
+  double* psum = scr<double>(H, L.psum);
   const int o2 = d.off[2], o3 = d.off[3], o4 = d.off[4], ns = d.ns;
   const int nu = d.nu, np = d.np, nj = d.nj, na = d.na;
   const double dt = H.dt;
@@ -704,9 +731,9 @@ int precond_forward(Handle& H, const double* r, double* z, Ctx& c, Ctx& ca, cons
       cha.yA = yA;
       cha.rj = rj;
       cha.yj = yj;
-      cha.r = at<T>(B, L.chr);
-      cha.d0 = at<T>(B, L.chd0);
-      cha.d1 = at<T>(B, L.chd1);
+      cha.r = scr<T>(H, L.chr);
+      cha.d0 = scr<T>(H, L.chd0);
+      cha.d1 = scr<T>(H, L.chd1);
       hipLaunchKernelGGL((k_ca_chain<T>), dim3(1), dim3(kChainBlock), 0, ca.s, cha);
     } else {
       for (int k = k0; k < k1; ++k) ca_step(ca, k);
@@ -756,13 +783,13 @@ int precond_transpose(Handle& H, const double* r, double* z, Ctx& c, Ctx& ca, co
   const int nt = d.nt;
   char* B = H.base;
   const WsLayout& L = H.L;
-  T* ru = at<T>(B, L.ru); T* xu = at<T>(B, L.xu);
-  T* rp = at<T>(B, L.rp); T* q = at<T>(B, L.q); T* t = at<T>(B, L.t); T* xp = at<T>(B, L.xp);
-  T* rj = at<T>(B, L.rj); T* yj = at<T>(B, L.yj);
-  T* ra = at<T>(B, L.ra); T* cA = at<T>(B, L.wA); T* f = at<T>(B, L.sA); T* yA = at<T>(B, L.yA);
-  T* mr = at<T>(B, L.mr); T* md0 = at<T>(B, L.md0); T* md1 = at<T>(B, L.md1);
-  T* mr2 = at<T>(B, L.mr2); T* md02 = at<T>(B, L.md02); T* md12 = at<T>(B, L.md12);
-  double* psum = at<double>(B, L.psum);
+  T* ru = scr<T>(H, L.ru); T* xu = scr<T>(H, L.xu);
+  T* rp = scr<T>(H, L.rp); T* q = scr<T>(H, L.q); T* t = scr<T>(H, L.t); T* xp = scr<T>(H, L.xp);
+  T* rj = scr<T>(H, L.rj); T* yj = scr<T>(H, L.yj);
+  T* ra = scr<T>(H, L.ra); T* cA = scr<T>(H, L.wA); T* f = scr<T>(H, L.sA); T* yA = scr<T>(H, L.yA);
+  T* mr = scr<T>(H, L.mr); T* md0 = scr<T>(H, L.md0); T* md1 = scr<T>(H, L.md1);
+  T* mr2 = scr<T>(H, L.mr2); T* md02 = scr<T>(H, L.md02); T* md12 = scr<T>(H, L.md12);
+  double* psum = scr<double>(H, L.psum);
   const int o2 = d.off[2], o3 = d.off[3], o4 = d.off[4], ns = d.ns;
   const int nu = d.nu, np = d.np, nj = d.nj, na = d.na;
   const double dt = H.dt;
@@ -876,17 +903,156 @@ int record_precond(Handle& H, Program& prog, const double* const* rslot, double*
 }
 
 // Replay of the recorded forward P_T^{-1} on stream s.
+// =============================== P and P-tilde (eqs. (preconditioner), ===
+// (preconditionerSimplified1)), step by step on one stream:
+//   P^{-1}      = Utilde_up^{-1} L_up^{-1} Ubar_ujA^{-1} L_ujA^{-1},
+//   Ptilde^{-1} = Utilde_up^{-1} L_up^{-1} Ubar_ujA^{-1},
+// with L_ujA^{-1}: x_A += Y F_u^{-1}(Z_j M_j^{-1} x_j - x_u) (step 1 of the paper's
+// application of P) and L_up^{-1}: y_p -= B F_u^{-1} y_u (eq. (PupLU)); the
+// Ubar_ujA and Utilde_up parts are P_T's.  Every F_u^{-1} is a whole forward
+// sweep (the same sweep steps as P_T's).
+template <class T>
+void fu_sweep_all(Ctx& c, Handle& H, const T* q, T* x) {
+  const int nt = H.d.nt, nu = H.d.nu;
+  const int vc = H.exact ? H.inner_iters : 1;
+  const double dt = H.dt;
+  for (int k = 0; k < nt; ++k) {
+    if (H.use_stencil && H.fu_deg > 0) {
+      sweep_step_stencil<T>(c, H, H.amgFu, H.sFu, k >= 1 ? &H.sAu : nullptr, k, -1.0, x + int64_t(k - 1) * nu,
+                            nullptr, 0, 0.0, nullptr, q + int64_t(k) * nu, x + int64_t(k) * nu, k, H.fu_deg, 1,
+                            k >= 1, 1.0, 0.0);
+    } else {
+      Seg<T> sg = seg<T>(H.Mu, 0, 0, 0, x + int64_t(k - 1) * nu, 0, 0, 0, 1, 1.0 / dt);
+      sweep_step<T>(c, H.amgFu, H.Mu, k >= 1 ? 1 : 0, &sg, q + int64_t(k) * nu, x + int64_t(k) * nu, k, H.fu_deg,
+                    vc);
+    }
+  }
+}
+
+template <class T>
+int precond_variant(Handle& H, const double* r, double* z, Ctx& c) {
+  const Dims& d = H.d;
+  const int nt = d.nt;
+  char* B = H.base;
+  const WsLayout& L = H.L;
+  T* ru = scr<T>(H, L.ru); T* yu = scr<T>(H, L.yu); T* xu = scr<T>(H, L.xu);
+  T* rp = scr<T>(H, L.rp); T* q = scr<T>(H, L.q); T* t = scr<T>(H, L.t); T* xp = scr<T>(H, L.xp);
+  T* rj = scr<T>(H, L.rj); T* yj = scr<T>(H, L.yj);
+  T* ra = scr<T>(H, L.ra); T* w = scr<T>(H, L.wA); T* sA = scr<T>(H, L.sA); T* yA = scr<T>(H, L.yA);
+  T* mr = scr<T>(H, L.mr); T* md0 = scr<T>(H, L.md0); T* md1 = scr<T>(H, L.md1);
+  double* psum = scr<double>(H, L.psum);
+  const int o2 = d.off[2], o3 = d.off[3], o4 = d.off[4], ns = d.ns;
+  const int nu = d.nu, np = d.np, nj = d.nj, na = d.na;
+  const double dt = H.dt;
+  const int vc = H.exact ? H.inner_iters : 1;
+  const int mit = H.mass_iters;
+  const double mlo = 0.24, mhi = 2.3, mth = 0.5 * (mhi + mlo), mde = 0.5 * (mhi - mlo);
+  // split r, the pressure rows projected to zero sum per slab
+  slab_sums_d(c, r, int64_t(ns), o2, np, nullptr, psum, nt);
+  {
+    SplitArgs<T> a{r, ns, nt, o2, o3, o4, psum, ru, rp, rj, ra, nullptr};
+    emit(c, kKSplit, dim3(grid_for(int64_t(ns) * nt)), &k_split<T>, a);
+  }
+  auto mj_solve = [&](const T* rhs, T* out) {
+    cheb_solve<T>(c, H.Mj, nt, 0, 0, static_cast<const T*>(H.dMj), 0, nullptr, mth, mde, rhs, out, mr, md0, md1,
+                  nj, mit, 0, false);
+  };
+  if (H.variant == 2) {
+    // L_ujA^{-1}: t_j = M_j^{-1} x_j; s = F_u^{-1}(Z_j t_j - x_u); x_A += Y s
+    mj_solve(rj, yj);
+    Seg<T> sz = seg<T>(H.Zj, 0, 0, 1, yj, nj, 0, 0, nt, 1.0);
+    spmv<T, T>(c, H.Zj, nt, 1, &sz, ru, nu, -1.0, yu, nu);
+    fu_sweep_all<T>(c, H, yu, xu);
+    spmv1<T>(c, H.Yv, nt, 0, 1, xu, nu, 1.0, ra, 1.0, ra, na);
+  }
+  // Ubar_ujA^{-1}: y_A = C_A^{-1} F_A M_A^{-1} x_A; y_j = M_j^{-1}(x_j - K_jA y_A);
+  // y_u = x_u - Z_j y_j - Z_A y_A
+  cheb_solve<T>(c, H.MA, nt, 0, 0, static_cast<const T*>(H.dMA), 0, nullptr, mth, mde, ra, w, mr, md0, md1, na, mit,
+                0, false);
+  {
+    Seg<T> sg[2] = {seg<T>(H.FA, 0, 0, 1, w, na, 0, 0, nt, 1.0), seg<T>(H.FA, 1, 0, 0, w, na, -1, 1, nt, 1.0)};
+    spmv<T, T>(c, H.FA, nt, 2, sg, nullptr, na, 0.0, sA, na);
+  }
+  for (int k = 0; k < nt; ++k) {
+    if (H.use_stencil && H.ca_deg > 0) {
+      sweep_step_stencil<T>(c, H, H.amgC0, H.sC0, k >= 1 ? &H.sCP : nullptr, k, 1.0, yA + int64_t(k - 1) * na,
+                            k >= 2 ? &H.sCQ : nullptr, k, 1.0, yA + int64_t(k - 2) * na, sA + int64_t(k) * na,
+                            yA + int64_t(k) * na, k, H.ca_deg, 2, k >= 1, k >= 2 ? 2.0 : 1.0, k >= 2 ? -1.0 : 0.0);
+    } else {
+      Seg<T> sg[2];
+      int nsg = 0;
+      if (k >= 1) sg[nsg++] = seg<T>(H.C1, 0, k - 1, 0, yA + int64_t(k - 1) * na, 0, 0, 0, 1, 1.0 / dt);
+      if (k >= 2) sg[nsg++] = seg<T>(H.C1, 1, 0, 0, yA + int64_t(k - 2) * na, 0, 0, 0, 1, -1.0 / (dt * dt));
+      sweep_step<T>(c, H.amgC0, H.C1, nsg, sg, sA + int64_t(k) * na, yA + int64_t(k) * na, k, H.ca_deg, vc);
+    }
+  }
+  spmv1<T>(c, H.KjA, nt, 0, 0, yA, na, -1.0, rj, 1.0, rj, nj);
+  mj_solve(rj, yj);
+  {
+    Seg<T> sg[2] = {seg<T>(H.Zj, 0, 0, 1, yj, nj, 0, 0, nt, -1.0), seg<T>(H.Zj, 1, 0, 1, yA, na, 0, 0, nt, -1.0)};
+    spmv<T, T>(c, H.Zj, nt, 2, sg, ru, nu, 1.0, yu, nu);
+  }
+  // L_up^{-1}: y_p = x_p - B F_u^{-1} y_u
+  fu_sweep_all<T>(c, H, yu, xu);
+  spmv1<T>(c, H.Bv, nt, 0, 0, xu, nu, -1.0, rp, 1.0, rp, np);
+  // Utilde_up^{-1}: x_p = -M_p^{-1} F_p K_p^{-1} y_p (xp holds M_p^{-1} F_p q);
+  // x_u = F_u^{-1}(y_u - B^T x_p)
+  amg_solve<T>(c, H.amgKp, nt, 0, 0, q, rp, vc);
+  {
+    Seg<T> sg[2] = {seg<T>(H.Fp, 0, 0, 1, q, np, 0, 0, nt, 1.0), seg<T>(H.Fp, 1, 0, 0, q, np, -1, 1, nt, 1.0)};
+    spmv<T, T>(c, H.Fp, nt, 2, sg, nullptr, np, 0.0, t, np);
+  }
+  cheb_solve<T>(c, H.Mp, nt, 0, 0, static_cast<const T*>(H.dMp), 0, nullptr, mth, mde, t, xp, mr, md0, md1, np, mit,
+                0, false);
+  spmv1<T>(c, H.Bt, nt, 0, 0, xp, np, 1.0, yu, 1.0, yu, nu);
+  fu_sweep_all<T>(c, H, yu, xu);
+  slab_sums_t<T>(c, xp, int64_t(np), np, H.mp_rowsum, psum + nt, nt);
+  {
+    JoinArgs<T> a{z, ns, nt, o2, o3, o4, xu, xp, -1.0, psum + nt, H.msum, yj, yA, nullptr};
+    emit(c, kKJoin, dim3(grid_for(int64_t(ns) * nt)), &k_join<T>, a);
+  }
+  (void)B;
+  return ST_OK;
+}
+
 int replay_precond(Handle& H, const double* r, double* z, hipStream_t s, bool transpose = false) {
   SetPtrsArgs sp{H.rslot, H.zslot, r, z};
   hipLaunchKernelGGL(k_set_ptrs, dim3(1), dim3(kBlock), 0, s, sp);
   for (ReplayItem& it : transpose ? H.pt_items_t : H.pt_items) {
     void* params[] = {it.args};
-    (void)hipLaunchKernel(it.fn, it.grid, dim3(unsigned(it.block)), params, 0, s);
+    const bool timed = H.prof_fn && it.fn == H.prof_fn && (H.prof_seen++ % H.prof_every) == 0 &&
+                       H.prof_used + 2 <= H.prof_ev.size();
+    if (timed) {
+      // the events take the dispatch's own start and end times (no extra
+      // packets between launches, which would break their back-to-back issue)
+      (void)hipExtLaunchKernel(it.fn, it.grid, dim3(unsigned(it.block)), params, 0, s, H.prof_ev[H.prof_used],
+                               H.prof_ev[H.prof_used + 1], 0);
+      H.prof_used += 2;
+    } else {
+      (void)hipLaunchKernel(it.fn, it.grid, dim3(unsigned(it.block)), params, 0, s);
+    }
   }
   return ST_OK;
 }
 
+// Adds the sampled kernel durations recorded so far (the stream is synchronised
+// by the caller) and frees the pool for the next solve.
+void profile_harvest(Handle& H) {
+  for (size_t i = 0; i + 1 < H.prof_used; i += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, H.prof_ev[i], H.prof_ev[i + 1]) == hipSuccess) {
+      H.prof_ms += ms;
+      H.prof_n += 1;
+    }
+  }
+  H.prof_used = 0;
+}
+
 int apply_precond(Handle& H, const double* r, double* z, Ctx& c, bool transpose) {
+  if (H.variant != 0) {
+    if (transpose || c.recording()) return ST_EINVAL;
+    return H.fp32 ? precond_variant<float>(H, r, z, c) : precond_variant<double>(H, r, z, c);
+  }
   if (!c.recording() && (transpose ? H.pipeline_t : H.pipeline)) return replay_precond(H, r, z, c.s, transpose);
   if (H.fp32)
     return transpose ? precond_transpose<float>(H, r, z, c, c) : precond_forward<float>(H, r, z, c, c);
@@ -1147,6 +1313,7 @@ int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* 
   emit_finalize(c, H, K, x);
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipGetLastError());
+  if (H.prof_fn) profile_harvest(H);
   const double pms = evs.elapsed_ms(), jms = jevs.elapsed_ms();
   info->precond_calls = evs.pairs();
   info->jacobian_calls = jevs.pairs();
@@ -1156,6 +1323,72 @@ int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* 
   info->true_rel_residual = true_res / bnorm;
   info->precond_seconds = pms * 1e-3;
   info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return status;
+}
+
+// ---------------------------------------------- sequential time stepping ---
+// The slabs solved one after the other (Sec. "Comparison with sequential
+// time-stepping"): slab k from its single-step Jacobian with FGMRES
+// right-preconditioned by the single-step P_{T,k} of eq. (PTTS), which is P_T
+// of a one-slab system, so hs[k] is a one-slab handle of slab k's state:
+//   J_k x^k = b^k + diag(M_u/dt, 0, 0, M_A/dt) x^{k-1}.
+// Each step stops on ||r_k|| <= max(rtol ||b||, atol) / sqrt(Nt) (the step
+// residuals are the rows of the space-time residual, so the whole x meets
+// the space-time tolerance).  With o->x0_given each step starts from the
+// previous step's solution.
+int timestep_solve(st_handle* const* hs, int nt, const double* b, double* x, const st_opts* o, st_info* infos,
+                   hipStream_t s) {
+  const Dims& d0 = hs[0]->h.d;
+  const int ns = d0.ns;
+  for (int k = 0; k < nt; ++k) {
+    const Dims& d = hs[k]->h.d;
+    if (d.nt != 1 || d.ns != ns || d.n != d0.n) return ST_EINVAL;
+    for (int i = 0; i < 6; ++i)
+      if (d.off[i] != d0.off[i]) return ST_EINVAL;
+  }
+  const int m = o->restart > 0 ? o->restart : 30;
+  Ctx c{s, nullptr};
+  // ||b|| with every slab's pressure rows projected to zero sum
+  double bb = 0.0;
+  for (int k = 0; k < nt; ++k) {
+    Handle& H = hs[k]->h;
+    if (m > H.max_restart) return ST_EINVAL;
+    const Krylov K = krylov(H, m);
+    emit_fgmres_init(c, H, K, b + int64_t(k) * ns, x + int64_t(k) * ns, false);
+    HIP_TRY(hipMemcpyAsync(H.host_small, K.sm, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (!std::isfinite(H.host_small[0])) return ST_EBREAKDOWN;
+    bb += H.host_small[0] * H.host_small[0];
+  }
+  const double tol = std::max(o->rtol * std::sqrt(bb), o->atol) / std::sqrt(double(nt));
+  int status = ST_OK;
+  for (int k = 0; k < nt; ++k) {
+    Handle& H = hs[k]->h;
+    const Krylov K = krylov(H, m);
+    const double* bk = b + int64_t(k) * ns;
+    double* xk = x + int64_t(k) * ns;
+    const double* rhs = bk;
+    if (k > 0) {
+      // rhs = b^k - J_{k,k-1} x^{k-1}, formed in handle k's Arnoldi work vector
+      // (FGMRES reads its right-hand side only when it projects it, before its
+      // first Arnoldi step)
+      const double* xprev = x + int64_t(k - 1) * ns;
+      Seg<double> sg = seg<double>(H.J, 2, 0, 0, xprev, ns, 0, 0, 1, -1.0);
+      spmv<double, double>(c, H.J, 1, 1, &sg, bk, ns, 1.0, K.w, ns, kRoleJ);
+      rhs = K.w;
+      if (o->x0_given) HIP_TRY(hipMemcpyAsync(xk, xprev, sizeof(double) * ns, hipMemcpyDeviceToDevice, s));
+    }
+    st_opts ok = *o;
+    ok.restart = m;
+    ok.rtol = 0.0;
+    ok.atol = tol;
+    ok.x0_given = (o->x0_given && k > 0) ? 1 : 0;
+    ok.history = nullptr;
+    ok.history_len = 0;
+    const int rc = fgmres(H, rhs, xk, &ok, &infos[k], s, false);
+    if (rc < 0) return rc;
+    if (rc == ST_ENOTCONV) status = ST_ENOTCONV;
+  }
   return status;
 }
 
@@ -1365,13 +1598,14 @@ int autotune(Handle& H, hipStream_t s, bool pipeline) {
     H.j_slabs = best;
   }
   if (rc == ST_OK && H.use_stencil) {
-    struct Cand { int fuse, rows; };
-    const Cand cands[] = {{0, 64}, {0, 128}, {0, 256}, {1, 0}};
+    struct Cand { int fuse, rows, lanes; };
+    const Cand cands[] = {{0, 64, 1}, {0, 128, 1}, {0, 256, 1}, {0, 64, 2}, {0, 128, 2}, {1, 0, 1}};
     Cand best = cands[0];
     float tbest = 1e30f;
     for (const Cand& cd : cands) {
       H.sweep_fuse = cd.fuse;
       H.step_rows = cd.rows;
+      H.step_lanes = cd.lanes;
       if (pipeline && (rc = build_pipeline(H)) != ST_OK) break;
       const float t = timed([&] { (void)apply_precond(H, x, y, c, false); }, 4);
       if (rc != ST_OK) break;
@@ -1382,6 +1616,7 @@ int autotune(Handle& H, hipStream_t s, bool pipeline) {
     }
     H.sweep_fuse = best.fuse;
     H.step_rows = best.rows;
+    H.step_lanes = best.lanes;
     if (rc == ST_OK && pipeline) rc = build_pipeline(H);
   }
   // the recorded forward apply's schedule: size of the first chunk (how long
@@ -1796,6 +2031,7 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
   H.ca_deg = P.ca_deg;
   H.use_stencil = P.use_stencil;
   H.sweep_fuse = P.prob.sweep_fuse == 1 ? 1 : 0;
+  H.step_lanes = P.prob.sweep_lanes == 2 ? 2 : 1;
   H.j_slabs = P.prob.j_slabs;
   H.sFu = P.sFu;
   H.sAu = P.sAu;
@@ -1850,6 +2086,9 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
     H.ZAt = mirror(base, P.ZAt);
     H.C1t = mirror(base, P.C1t);
   }
+  H.variant = P.variant;
+  if (H.variant >= 1) H.Bv = mirror(base, P.Bv);
+  if (H.variant == 2) H.Yv = mirror(base, P.Yv);
   H.mp_rowsum = at<double>(base, P.mp_rowsum.off);
   {
     const double* m = reinterpret_cast<const double*>(P.img.bytes.data() + P.mp_rowsum.off);
@@ -1880,8 +2119,8 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
   {
     int rc = ST_OK;
     try {
-      if (P.prob.single_stream == 0) rc = build_pipeline(H);
-      if (rc == ST_OK && P.prob.autotune == 1) rc = autotune(H, s, P.prob.single_stream == 0);
+      if (P.prob.single_stream == 0 && H.variant == 0) rc = build_pipeline(H);
+      if (rc == ST_OK && P.prob.autotune == 1) rc = autotune(H, s, P.prob.single_stream == 0 && H.variant == 0);
     } catch (...) {
       rc = ST_ENOMEM;
     }
@@ -1898,6 +2137,7 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
 int st_destroy(st_handle* h) {
   if (!h) return ST_OK;
   if (h->h.host_small) (void)hipHostFree(h->h.host_small);
+  for (hipEvent_t e : h->h.prof_ev) (void)hipEventDestroy(e);
   delete h;
   return ST_OK;
 }
@@ -1910,13 +2150,45 @@ int st_sizes(const st_handle* h, int64_t* n_total, int* ns, int* nt) {
   return ST_OK;
 }
 
-int st_tuning(const st_handle* h, int* j_slabs, int* step_rows, int* sweep_fuse, int* precond_launches) {
+int st_tuning(const st_handle* h, int* j_slabs, int* step_rows, int* sweep_fuse, int* precond_launches,
+              int* step_lanes) {
   if (!h) return ST_EINVAL;
   const st::Handle& H = h->h;
   if (j_slabs) *j_slabs = H.J.lanes != 1 ? 1 : (H.j_slabs == 0 ? 8 : H.j_slabs);
   if (step_rows) *step_rows = H.step_rows > 0 ? H.step_rows : (H.fp32 ? st::st_rows<float>() : st::st_rows<double>());
   if (sweep_fuse) *sweep_fuse = H.sweep_fuse;
   if (precond_launches) *precond_launches = H.pipeline ? int(H.pt_items.size()) + 1 : 0;
+  if (step_lanes) *step_lanes = H.step_lanes;
+  return ST_OK;
+}
+
+int st_profile_kernel(st_handle* h, int kernel, int every) {
+  using namespace st;
+  if (!h || kernel < 0 || kernel > 1 || (kernel == 1 && every < 1)) return ST_EINVAL;
+  Handle& H = h->h;
+  H.prof_fn = nullptr;
+  H.prof_seen = H.prof_n = 0;
+  H.prof_ms = 0.0;
+  H.prof_used = 0;
+  if (kernel == 0) return ST_OK;
+  if (!H.pipeline) return ST_EINVAL;
+  constexpr size_t kPairs = 8192;
+  while (H.prof_ev.size() < 2 * kPairs) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return ST_EHIP;
+    H.prof_ev.push_back(e);
+  }
+  H.prof_fn = H.fp32 ? reinterpret_cast<const void*>(&k_two<BodyStCheb<float>, BodyStCheb<float>>)
+                     : reinterpret_cast<const void*>(&k_two<BodyStCheb<double>, BodyStCheb<double>>);
+  H.prof_every = every;
+  return ST_OK;
+}
+
+int st_profile_read(const st_handle* h, double* seconds, int64_t* launches_timed, int64_t* launches_seen) {
+  if (!h) return ST_EINVAL;
+  if (seconds) *seconds = h->h.prof_ms * 1e-3;
+  if (launches_timed) *launches_timed = h->h.prof_n;
+  if (launches_seen) *launches_seen = h->h.prof_seen;
   return ST_OK;
 }
 
@@ -1968,6 +2240,18 @@ int st_adjoint_solve(st_handle* h, const double* g, double* lam, const st_opts* 
   return st::fgmres(h->h, g, lam, o, info, static_cast<hipStream_t>(stream), true);
 }
 
+int st_timestep_solve(st_handle* const* hs, int nt, const double* b, double* x, const st_opts* o,
+                      st_info* infos, void* stream) {
+  if (!hs || nt < 1 || !b || !x || !o || !infos || b == x) return ST_EINVAL;
+  for (int k = 0; k < nt; ++k)
+    if (!hs[k]) return ST_EINVAL;
+  try {
+    return st::timestep_solve(hs, nt, b, x, o, infos, static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return ST_ENOMEM;
+  }
+}
+
 int st_batch_create(st_handle* const* hs, int nsys, int restart, st_batch** out) {
   using namespace st;
   if (!hs || !out || nsys < 1 || nsys > kMaxMembers) return ST_EINVAL;
@@ -1976,6 +2260,7 @@ int st_batch_create(st_handle* const* hs, int nsys, int restart, st_batch** out)
   for (int i = 0; i < nsys; ++i) {
     if (!hs[i]) return ST_EINVAL;
     if (m > hs[i]->h.max_restart) return ST_EINVAL;
+    if (hs[i]->h.variant != 0) return ST_EINVAL;
     if (hs[i]->h.fp32 != hs[0]->h.fp32) return ST_EINVAL;
     for (int k = 0; k < i; ++k)
       if (hs[k] == hs[i]) return ST_EINVAL;

@@ -201,6 +201,8 @@ struct Plan {
   SellGroup FA, FAt, Fp, Fpt;     // per-slab bidiagonal applies (diag blocks)
   SellGroup KjA, KjAt, Bt, B;     // shared couplings
   SellGroup Zj, ZA, Zjt, ZAt;     // per-slab couplings
+  SellGroup Yv, Bv;               // Y (per slab) and B for the lower factors of P, P-tilde
+  int variant = 0;                // 0 P_T, 1 P-tilde, 2 P
   SellGroup Mu;                   // sweep coupling of F_u
   SellGroup C1, C2, C1t, C2t;     // sweep couplings of C_A
   SellGroup MA64;                 // M_A / dt in FP64 (initial-condition coupling)
@@ -224,6 +226,9 @@ struct WsLayout {
   size_t io = 0;                                // 2 pointers: input/output slots of a recorded P_T
   std::vector<size_t> kp_lev, fu_lev, ca_lev;   // 6 vectors per level each
   size_t end = 0;
+  // [pt_begin, end) holds only the preconditioner's scratch (psum onwards):
+  // the allocation-free apply relocates exactly this range.
+  size_t pt_begin = 0;
 };
 constexpr int kPartialBlocks = 1024;   // blocks of the two-stage reductions
 constexpr int kOpArgBytes = 448;       // largest argument block of a recorded launch

@@ -255,7 +255,7 @@ def test_autotuned_launches_give_the_same_results(precision):
         sysg = binding.System(plan, "cuda:0")
         t = sysg.tuning()
         say(f"    autotune={tune}: {t}")
-        assert t["j_slabs"] in (1, 4, 8) and t["step_rows"] in (64, 128, 256)
+        assert t["j_slabs"] in (1, 4, 8) and t["step_rows"] in (64, 128, 256) and t["step_lanes"] in (1, 2)
         r = np.random.default_rng(11).standard_normal(ref.N)
         out.append([sysg.apply_jacobian(dev(r)).cpu().numpy(), sysg.apply_precond(dev(r)).cpu().numpy(),
                     sysg.apply_precond(dev(r), transpose=True).cpu().numpy()])
@@ -281,3 +281,26 @@ def test_chain_kernel_matches_per_step_launches(precision, tol):
         out.append(sysg.apply_precond(dev(r)).cpu().numpy())
     say(f"    rel {rel(out[0], out[1]):.1e}")
     assert rel(out[0], out[1]) <= tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,nt", [(12, 6), (3, 4), (20, 3)])
+def test_two_lane_sweep_steps_match_one_lane(precision, n, nt):
+    """F_u,k sweep steps with the row's two column components on two lanes
+    (partial sums exchanged between the lanes) compute what one lane per row
+    computes, bit for bit, in P_T^{-1} (recorded replay) and P_T^{-T}; the
+    meshes leave ragged last workgroups (F_u grids of 23 x 23, 5 x 5 and
+    39 x 39 nodes per component)."""
+    say(f"[gpu] two-lane vs one-lane sweep steps {precision} n={n} nt={nt}")
+    from paper_2309_00768_amd import binding
+    cfg, ub, ab, ref = case(n, nt)
+    out = []
+    for lanes in (1, 2):
+        plan = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision=precision,
+                            adjoint=True, sweep_lanes=lanes, sweep_chain=False)
+        sysg = binding.System(plan, "cuda:0")
+        assert sysg.tuning()["step_lanes"] == lanes
+        r = np.random.default_rng(15).standard_normal(ref.N)
+        out.append((sysg.apply_precond(dev(r)).cpu().numpy(), sysg.apply_precond(dev(r), transpose=True).cpu().numpy()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
