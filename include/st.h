@@ -48,7 +48,9 @@ typedef enum st_status {
   ST_ENOTCONV = 1,      /* solver hit maxit; x holds the best iterate, info is filled */
   ST_EINVAL = -1,       /* bad argument (null pointer, size, option) */
   ST_EHIP = -2,         /* a HIP runtime call failed */
-  ST_ENOMEM = -3,       /* workspace smaller than st_plan_workspace_size() */
+  ST_ENOMEM = -3,       /* workspace smaller than st_plan_workspace_size(), or a system
+                           whose preconditioner scratch exceeds the static
+                           array of st_apply_precond_noalloc */
   ST_EBREAKDOWN = -4,   /* NaN or Inf in a residual or in the Hessenberg matrix */
   ST_EINTERNAL = -5     /* setup failed (e.g. singular coarse matrix) */
 } st_status;
@@ -140,8 +142,9 @@ typedef struct st_problem {
                              L_up factor); 2 the full P, eq. (preconditioner),
                              two more F_u sweeps and an M_j solve (the L_ujA and
                              L_up factors).  1 and 2 run step by step, forward
-                             only: st_apply_precond_t, the adjoint solve and
-                             batches take 0 only (ST_EINVAL otherwise).      */
+                             only: st_apply_precond_t, the adjoint solve, the
+                             allocation-free apply and batches take 0 only
+                             (ST_EINVAL otherwise).                         */
 } st_problem;
 
 typedef struct st_opts {
@@ -239,6 +242,25 @@ int st_apply_precond(st_handle* h, const double* r, double* z, void* stream);
  * Needs adjoint = 1 (else ST_EINVAL).  FP64 in/out, device, length N, no
  * aliasing; asynchronous on `stream`. */
 int st_apply_precond_t(st_handle* h, const double* r, double* z, void* stream);
+
+/* z = P_T^{-1} r exactly as st_apply_precond computes it (the same kernels,
+ * launched step by step), for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  It calls no hipMalloc, hipFree or allocating library routine:
+ * the preconditioner's scratch (per-block vectors, Chebyshev and V-cycle
+ * buffers, pressure sums) lives in one static device array of 128 MiB per
+ * GPU, held from the library's load onto that GPU until the process ends; the
+ * operators stay in the handle's workspace, r and z are the caller's (FP64,
+ * device, length N, no aliasing).  The scratch a system needs is
+ * workspace_size - (operators + Krylov vectors); a system needing more than
+ * 128 MiB is rejected with ST_ENOMEM and a message on stderr, before any
+ * launch.  The calling thread's current device must be the one the handle was
+ * created on (else ST_EINVAL).  Every call on a GPU shares that GPU's array,
+ * which keeps the last call's contents; nothing in it has to start at zero
+ * (each buffer is written before it is read within a call).  Calls that
+ * overlap on one GPU (other streams, other threads, other handles) race on
+ * the array and must be serialised by the caller.  Asynchronous on `stream`. */
+int st_apply_precond_noalloc(st_handle* h, const double* r, double* z, void* stream);
 
 /* y = (M_A / dt) a0: how an initial vector potential A^0 (interior Q1 nodes,
  * length (n-1)^2, device, FP64) enters the right-hand side of the first slab

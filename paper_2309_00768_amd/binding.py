@@ -60,7 +60,7 @@ EXPORTED = [
     "st_plan_create", "st_plan_workspace_size", "st_plan_sizes", "st_plan_export_block", "st_plan_export_jbar",
     "st_plan_solver_info", "st_plan_jacobian_slots",
     "st_plan_destroy", "st_create", "st_destroy", "st_apply_jacobian", "st_apply_jacobian_t",
-    "st_apply_precond", "st_apply_precond_t", "st_apply_initial_coupling",
+    "st_apply_precond", "st_apply_precond_t", "st_apply_precond_noalloc", "st_apply_initial_coupling",
     "st_fgmres_solve", "st_adjoint_solve", "st_timestep_solve",
     "st_sizes", "st_tuning", "st_profile_kernel", "st_profile_read", "st_batch_create", "st_batch_workspace_size",
     "st_batch_upload", "st_batch_launch_counts",
@@ -91,6 +91,7 @@ def _load(path=LIB_PATH):
         "st_apply_jacobian_t": ([vp, vp, vp, vp], ctypes.c_int),
         "st_apply_precond": ([vp, vp, vp, vp], ctypes.c_int),
         "st_apply_precond_t": ([vp, vp, vp, vp], ctypes.c_int),
+        "st_apply_precond_noalloc": ([vp, vp, vp, vp], ctypes.c_int),
         "st_apply_initial_coupling": ([vp, vp, vp, vp], ctypes.c_int),
         "st_fgmres_solve": ([vp, vp, vp, ctypes.POINTER(StOpts), ctypes.POINTER(StInfo), vp], ctypes.c_int),
         "st_adjoint_solve": ([vp, vp, vp, ctypes.POINTER(StOpts), ctypes.POINTER(StInfo), vp], ctypes.c_int),
@@ -281,6 +282,13 @@ class System:
         z = torch.empty_like(r) if z is None else z
         fn = lib().st_apply_precond_t if transpose else lib().st_apply_precond
         _check(fn(self.ptr, self._vec(r), self._vec(z), _stream_ptr(stream)), "st_apply_precond")
+        return z
+
+    def apply_precond_noalloc(self, r, z, stream=None):
+        """z = P_T^{-1} r with the library's static scratch (``st_apply_precond_noalloc``):
+        no device allocation in the call; z must be given."""
+        _check(lib().st_apply_precond_noalloc(self.ptr, self._vec(r), self._vec(z), _stream_ptr(stream)),
+               "st_apply_precond_noalloc")
         return z
 
     def initial_coupling(self, a0, y=None, stream=None):

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <utility>
@@ -81,8 +82,11 @@ struct Handle {
   char* base = nullptr;
   WsLayout L;
   // Preconditioner scratch: null = in the workspace at its layout offsets;
-  // otherwise the range [L.pt_begin, L.end) is relocated to sbase.
+  // otherwise the range [L.pt_begin, L.end) is relocated to sbase (the
+  // allocation-free apply, whose scratch is the library's static array).
   char* sbase = nullptr;
+  int scratch_dev = -1;                  // device of the handle's workspace
+  char* noalloc_scratch = nullptr;       // that device's static scratch array
   DGroup J, JT, MA, Mj, Mp, FA, FAt, Fp, Fpt, KjA, KjAt, Bt, B, Zj, Zjt, ZAt, Mu, C1, C1t, MA64;
   DGroup Yv, Bv;                   // Y and B for the lower factors of P and P-tilde
   int variant = 0;                 // 0 P_T, 1 P-tilde, 2 P
@@ -2001,6 +2005,54 @@ struct st_batch {
 
 
 // ============================================================ C ABI ===
+// Scratch of the allocation-free preconditioner apply (st_apply_precond_noalloc):
+// one array per GPU, placed by the code-object loader and held until the
+// process ends.  In host code its name is a host-side stand-in, never a device
+// address: kernels receive the address hipGetSymbolAddress returns for the
+// current device.
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace st {
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array, looked up once per
+// device (with that device current).
+int scratch_for_current_device(int* dev_out, char** ptr_out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return ST_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(::scratch));
+    if (e != hipSuccess || !p) {
+      std::fprintf(stderr, "libst: hipGetSymbolAddress(scratch) failed on device %d: %s\n", dev,
+                   hipGetErrorString(e));
+      return ST_EHIP;
+    }
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  *dev_out = dev;
+  *ptr_out = g_scratch_ptr[dev];
+  return ST_OK;
+}
+
+// The level buffers of a hierarchy with the preconditioner scratch relocated
+// to sbase.
+std::vector<void*> relocated(const Handle& H, const std::vector<size_t>& offs, char* sbase) {
+  std::vector<void*> v;
+  for (size_t o : offs) v.push_back(sbase + (o - H.L.pt_begin));
+  return v;
+}
+
+}  // namespace
+}  // namespace st
+
 extern "C" {
 
 int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_handle** out) {
@@ -2130,6 +2182,15 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
       return rc;
     }
   }
+  {
+    // the allocation-free apply's scratch on this device (set-up, once per device)
+    const int rc = scratch_for_current_device(&H.scratch_dev, &H.noalloc_scratch);
+    if (rc) {
+      (void)hipHostFree(H.host_small);
+      delete hh;
+      return rc;
+    }
+  }
   *out = hh;
   return ST_OK;
 }
@@ -2218,6 +2279,46 @@ int st_apply_precond_t(st_handle* h, const double* r, double* z, void* stream) {
   if (!h || !r || !z || r == z || !h->h.adjoint) return ST_EINVAL;
   st::Ctx c{static_cast<hipStream_t>(stream), nullptr};
   int rc = st::apply_precond(h->h, r, z, c, true);
+  if (rc) return rc;
+  return hipGetLastError() == hipSuccess ? ST_OK : ST_EHIP;
+}
+
+int st_apply_precond_noalloc(st_handle* h, const double* r, double* z, void* stream) {
+  using namespace st;
+  if (!h || !r || !z || r == z) return ST_EINVAL;
+  Handle& H = h->h;
+  if (H.variant != 0) return ST_EINVAL;
+  const size_t need = H.L.end - H.L.pt_begin;
+  if (need > ::kNoAllocScratchBytes) {
+    std::fprintf(stderr,
+                 "libst: st_apply_precond_noalloc: this system's preconditioner scratch (%zu bytes) exceeds the "
+                 "library's static scratch (%zu bytes)\n",
+                 need, ::kNoAllocScratchBytes);
+    return ST_ENOMEM;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != H.scratch_dev || !H.noalloc_scratch) return ST_EINVAL;
+  // Step by step on the caller's stream (the recorded programs hold workspace
+  // scratch addresses), every scratch buffer relocated to the static array.
+  char* const sb = H.noalloc_scratch;
+  std::vector<void*> fu = relocated(H, H.L.fu_lev, sb), ca = relocated(H, H.L.ca_lev, sb),
+                     kp = relocated(H, H.L.kp_lev, sb);
+  std::swap(H.amgFu.buf, fu);
+  std::swap(H.amgC0.buf, ca);
+  std::swap(H.amgKp.buf, kp);
+  H.sbase = sb;
+  // st_apply_precond replays the recorded programs, which never use the chain
+  // kernel; without them it runs step by step, chain kernel included: the
+  // same choice here gives the same result, bit for bit.
+  const int use_chain = H.use_chain;
+  if (H.pipeline) H.use_chain = 0;
+  Ctx c{static_cast<hipStream_t>(stream), nullptr};
+  const int rc = H.fp32 ? precond_forward<float>(H, r, z, c, c) : precond_forward<double>(H, r, z, c, c);
+  H.use_chain = use_chain;
+  H.sbase = nullptr;
+  std::swap(H.amgFu.buf, fu);
+  std::swap(H.amgC0.buf, ca);
+  std::swap(H.amgKp.buf, kp);
   if (rc) return rc;
   return hipGetLastError() == hipSuccess ? ST_OK : ST_EHIP;
 }
