@@ -283,6 +283,53 @@ def bench_batch(args, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_newton(args, dev):
+    """Space-time Newton on the paper's model problems (island coalescence and
+    the tearing mode's Harris sheet on the unit square), mu = eta = mu0 = 1,
+    Newton to ||R|| <= 1e-10 with FGMRES(30) + P_T to a relative 1e-2 or an
+    absolute 1e-14 per correction (the paper's tolerances), over a grid of
+    mesh and time-step sizes with T = 1: the shape of the paper's Table 1."""
+    import torch
+    from paper_2309_00768_amd import binding, inputs
+    rows = []
+    sizes = [(16, 16), (32, 16), (32, 32), (32, 64), (64, 32)]
+    # spatial solves of the sweeps: one SA-AMG V(1,1) cycle (these problems are
+    # diffusion-dominated: mu dt / h^2 = 16 to 256), the automatic choice per
+    # solve, or converged ones (EXACT mode: the paper's exact inner solves)
+    inner = {"vcycle": {"fu_solver": -1, "ca_solver": -1}, "auto": {}, "exact": {"inner": "exact"}}
+    t_all = time.perf_counter()
+    for name, n, nt, how in [(nm, n, nt, h) for nm in ("island", "tearing") for (n, nt) in sizes
+                             for h in ("vcycle", "auto", "exact") if h == "vcycle" or (n, nt) in ((16, 16), (32, 32))]:
+            prob = inputs.ModelProblem(name, n, nt, 1.0 / nt)
+            fl = inputs.model_newton_fields(prob)
+            t0 = time.perf_counter()
+            nw = binding.Newton(n, nt, prob.dt, prob.mu, prob.eta, prob.mu0, fl, device=dev, precision=args.precision,
+                                **inner[how])
+            setup = time.perf_counter() - t0
+            torch.cuda.synchronize()
+            x, info, rc = nw.solve(atol=1e-10, lin_rtol=1e-2, lin_atol=1e-14)
+            its = list(info.linear_iterations[:info.newton_iterations])
+            rows.append({"problem": name, "n": n, "nt": nt, "inner": how, "N": nw.N, "newton": info.newton_iterations,
+                         "fgmres_per_newton": sum(its) / max(len(its), 1), "converged": bool(info.converged),
+                         "final_residual": info.residual_norm[info.newton_iterations],
+                         "seconds": info.seconds, "reassembly_seconds": info.setup_seconds, "setup_s": setup})
+            log(f"{name} n={n} Nt={nt} ({how}): Newton {info.newton_iterations} ({rows[-1]['fgmres_per_newton']:.2f} "
+                f"FGMRES its each), ||R|| {rows[-1]['final_residual']:.1e}, {info.seconds:.2f} s "
+                f"({info.setup_seconds:.2f} s re-assembly)")
+            del nw
+    total = time.perf_counter() - t_all
+    dofs = sum(r["N"] * sum([r["fgmres_per_newton"] * r["newton"]]) for r in rows)
+    out = {"metric": METRIC, "value": dofs / sum(r["seconds"] for r in rows), "unit": "DOF-iter/s", "n_gpus": 1,
+           "steps": 1, "warmup": 0, "ms_per_step": 1e3 * sum(r["seconds"] for r in rows),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32-precond/f64-krylov" if args.precision == "fp32" else "f64", "data": "synthetic",
+           "config": {"workload": "space-time Newton on island coalescence and the tearing mode (unit square, "
+                                  "Dirichlet u and A, mu = eta = mu0 = 1, T = 1), Newton to 1e-10, FGMRES(30) + P_T "
+                                  "to rel 1e-2 / abs 1e-14"},
+           "newton": rows, "wall_s": total}
+    print(json.dumps(out), flush=True)
+
+
 def bench_adjoint(args, dev):
     """Adjoint workload: 128 x 128 mesh, Nt = 128, dt = 0.005, Re = S = 500, FP64.
     A step is one gradient of J = 1/2 |A(T) - A_target|^2 with respect to the
@@ -369,6 +416,8 @@ def main():
                     help="oracle tolerance (its solution on the sampled slabs is the reference x*)")
     ap.add_argument("--sweep-lanes", type=int, default=0, choices=[0, 1, 2],
                     help="lanes per row of the F_u sweep steps when not autotuned (0: library default)")
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32",
+                    help="newton: preconditioner precision of the corrections")
     ap.add_argument("--variant", choices=["PT", "Ptilde", "P"], default="PT",
                     help="preconditioner: P_T (default), P-tilde or the full P (step by step)")
     ap.add_argument("--timestep", action="store_true",
@@ -391,7 +440,7 @@ def main():
     from paper_2309_00768_amd import inputs
 
     cpu = None
-    if args.config not in ("cfg4", "cfg5") and not args.no_cpu and args.probe is None:
+    if args.config not in ("cfg4", "cfg5", "newton") and not args.no_cpu and args.probe is None:
         # before anything touches the GPU: the oracle's worker processes start fresh
         cfg = inputs.CONFIGS[args.config]
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
@@ -409,6 +458,9 @@ def main():
         return
     if args.config == "cfg5":
         bench_adjoint(args, dev)
+        return
+    if args.config == "newton":
+        bench_newton(args, dev)
         return
     cfg = inputs.CONFIGS[args.config]
     ub, ab = inputs.state(cfg)

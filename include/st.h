@@ -311,6 +311,78 @@ int st_adjoint_solve(st_handle* h, const double* g, double* lam, const st_opts* 
 int st_timestep_solve(st_handle* const* hs, int nt, const double* b, double* x, const st_opts* o,
                       st_info* infos, void* stream);
 
+/* --------------------------------------------------- space-time Newton --- */
+/* The nonlinear recurrence, eq. (recurrence), solved for all slabs at once by
+ * Newton's method, each correction from the space-time Jacobian of eq.
+ * (jacobianSTDiscrete) linearised about the current iterate and solved by
+ * FGMRES with P_T (Sec. "Performance of preconditioner").
+ *
+ * Fields are full nodal arrays on the unit square's n x n mesh: Q2 velocity on
+ * the (2n+1)^2 grid ([2][(2n+1)^2] per slab), Q1 p, j, A on the (n+1)^2 grid,
+ * lexicographic with x fastest.  The unknown x (device, length nt * Ns, the
+ * linear solver's slab-major layout [u_x | u_y | p | j | A]: interior u and A,
+ * all p and j) is added to base fields, which carry the Dirichlet values of u
+ * and A on the boundary and the initial guess; u_init and a_init are the
+ * fields at t_0 that the first slab couples to.  f (momentum forcing) and e
+ * (the imposed electric field E of the induction equation) are nodal fields per
+ * slab, integrated against the test functions; either may be NULL (zero).
+ * All pointers are host arrays, copied at st_nl_create. */
+typedef struct st_nl st_nl;
+
+typedef struct st_nl_problem {
+  int n, nt;
+  double dt, mu, eta, mu0;
+  const double* u_base;  /* [nt][2][(2n+1)^2] */
+  const double* p_base;  /* [nt][(n+1)^2] */
+  const double* j_base;  /* [nt][(n+1)^2] */
+  const double* a_base;  /* [nt][(n+1)^2] */
+  const double* u_init;  /* [2][(2n+1)^2] */
+  const double* a_init;  /* [(n+1)^2] */
+  const double* f;       /* [nt][2][(2n+1)^2] or NULL */
+  const double* e;       /* [nt][(n+1)^2] or NULL */
+} st_nl_problem;
+
+#define ST_NEWTON_MAX 32
+typedef struct st_newton_opts {
+  int max_newton;     /* Newton steps at most (0: 20; at most ST_NEWTON_MAX) */
+  double atol;        /* stop when ||R(x)||_2 <= atol (the paper: 1e-10)     */
+  st_opts linear;     /* FGMRES of each correction (the paper: rtol 1e-2,
+                         atol 1e-14); x0_given and the history are ignored   */
+} st_newton_opts;
+
+typedef struct st_newton_info {
+  int newton_iterations;                        /* corrections applied         */
+  int converged;
+  int linear_iterations_total;
+  int linear_iterations[ST_NEWTON_MAX];         /* FGMRES iterations per step   */
+  double residual_norm[ST_NEWTON_MAX + 1];      /* ||R|| before each step, and at the end */
+  double seconds;                               /* wall time of the whole solve */
+  double setup_seconds;                         /* of which re-assembly and upload */
+} st_newton_info;
+
+/* Device bytes st_nl_create needs (base, initial and forcing fields, element
+ * residuals, three N-vectors, the linearisation state). */
+int st_nl_workspace_size(const st_nl_problem* p, size_t* bytes);
+/* Copies the fields into the caller's workspace `ws` (256-byte aligned) on
+ * `stream` and waits for it. */
+int st_nl_create(const st_nl_problem* p, void* ws, size_t ws_bytes, void* stream, st_nl** out);
+/* r = R(base + x): the left-hand side of eq. (recurrence) minus its right-hand
+ * side (f in the momentum rows; E, carried with a minus sign on the right of
+ * the induction equation, enters the residual with a plus), by 4 x 4 Gauss
+ * quadrature per element; rows in the slab-major layout of x.  x, r device,
+ * no aliasing; asynchronous on `stream`. */
+int st_nl_residual(st_nl* nl, const double* x, double* r, void* stream);
+/* Newton from the given x (device, updated in place): each step evaluates R,
+ * stops if ||R|| <= o->atol, else assembles the linearisation about base + x
+ * on the host (the template `lin` supplies every option of st_problem but the
+ * state and sizes; precond_variant 0, adjoint 0), uploads it into `lin_ws`
+ * (the caller's, >= st_plan_workspace_size of the same problem) and applies
+ * x += d with J d = -R from FGMRES.  Blocks until done.  ST_OK when converged,
+ * ST_ENOTCONV after max_newton steps, else an error. */
+int st_newton_solve(st_nl* nl, const st_problem* lin, void* lin_ws, size_t lin_ws_bytes, double* x,
+                    const st_newton_opts* o, st_newton_info* info, void* stream);
+int st_nl_destroy(st_nl* nl);
+
 /* ------------------------------------------------------------ batches --- */
 /* Many independent space-time systems (uneven n and Nt) solved together: the
  * same right-preconditioned FGMRES(m) as st_fgmres_solve on each member, run

@@ -20,7 +20,14 @@ incompressible resistive magnetohydrodynamics", arXiv:2309.00768):
                  preconditioner"), its transpose, right-preconditioned GMRES,
                  and the direct forward/backward substitutions in time;
 * ``nonlinear``  the residual of the recurrence, eq. (recurrence), used to pin
-                 the Jacobian by finite differences.
+                 the Jacobian by finite differences;
+* ``newton``     the space-time Newton solve of the recurrence (forcing rows,
+                 linearisation about an iterate, Newton with direct or
+                 GMRES + P_T corrections);
+* ``timestepping`` sequential time stepping with the single-step
+                 preconditioner P_{T,k}, eq. (PTTS);
+* ``variants``   the full preconditioner P and P-tilde, eqs. (preconditioner),
+                 (preconditionerSimplified1), from their factors.
 
 Parity status: every function here is pinned by a ``-m "not gpu"`` test against
 closed forms, invariants, brute force or finite differences, except the PCD

@@ -48,11 +48,37 @@ class StOpts(ctypes.Structure):
     ]
 
 
+class StNlProblem(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int), ("nt", ctypes.c_int),
+        ("dt", ctypes.c_double), ("mu", ctypes.c_double), ("eta", ctypes.c_double), ("mu0", ctypes.c_double),
+        ("u_base", ctypes.POINTER(ctypes.c_double)), ("p_base", ctypes.POINTER(ctypes.c_double)),
+        ("j_base", ctypes.POINTER(ctypes.c_double)), ("a_base", ctypes.POINTER(ctypes.c_double)),
+        ("u_init", ctypes.POINTER(ctypes.c_double)), ("a_init", ctypes.POINTER(ctypes.c_double)),
+        ("f", ctypes.POINTER(ctypes.c_double)), ("e", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+ST_NEWTON_MAX = 32
+
+
 class StInfo(ctypes.Structure):
     _fields_ = [
         ("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
         ("true_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double), ("precond_seconds", ctypes.c_double),
         ("jacobian_seconds", ctypes.c_double), ("jacobian_calls", ctypes.c_int), ("precond_calls", ctypes.c_int),
+    ]
+
+
+class StNewtonOpts(ctypes.Structure):
+    _fields_ = [("max_newton", ctypes.c_int), ("atol", ctypes.c_double), ("linear", StOpts)]
+
+
+class StNewtonInfo(ctypes.Structure):
+    _fields_ = [
+        ("newton_iterations", ctypes.c_int), ("converged", ctypes.c_int), ("linear_iterations_total", ctypes.c_int),
+        ("linear_iterations", ctypes.c_int * ST_NEWTON_MAX), ("residual_norm", ctypes.c_double * (ST_NEWTON_MAX + 1)),
+        ("seconds", ctypes.c_double), ("setup_seconds", ctypes.c_double),
     ]
 
 
@@ -65,6 +91,7 @@ EXPORTED = [
     "st_sizes", "st_tuning", "st_profile_kernel", "st_profile_read", "st_batch_create", "st_batch_workspace_size",
     "st_batch_upload", "st_batch_launch_counts",
     "st_fgmres_solve_batched", "st_batch_destroy",
+    "st_nl_workspace_size", "st_nl_create", "st_nl_residual", "st_newton_solve", "st_nl_destroy",
     "st_error_string",
 ]
 
@@ -108,6 +135,12 @@ def _load(path=LIB_PATH):
         "st_fgmres_solve_batched": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(StOpts),
                                      ctypes.POINTER(StInfo), ip, vp], ctypes.c_int),
         "st_batch_destroy": ([vp], ctypes.c_int),
+        "st_nl_workspace_size": ([ctypes.POINTER(StNlProblem), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "st_nl_create": ([ctypes.POINTER(StNlProblem), vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "st_nl_residual": ([vp, vp, vp, vp], ctypes.c_int),
+        "st_newton_solve": ([vp, ctypes.POINTER(StProblem), vp, ctypes.c_size_t, vp, ctypes.POINTER(StNewtonOpts),
+                             ctypes.POINTER(StNewtonInfo), vp], ctypes.c_int),
+        "st_nl_destroy": ([vp], ctypes.c_int),
         "st_error_string": ([ctypes.c_int], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -379,6 +412,91 @@ class TimeStepping:
         rc = _check(lib().st_timestep_solve(arr, self.nt, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
                                             ctypes.byref(o), infos, _stream_ptr(stream)), "st_timestep_solve")
         return x, list(infos), rc
+
+
+class Newton:
+    """Space-time Newton on the nonlinear recurrence (``st_nl_*``, ``st_newton_solve``).
+
+    ``fields`` holds host arrays u_base, p_base, a_base, u_init, a_init and
+    optionally j_base, f, e (see ``st_nl_problem``).  Without j_base the base
+    current is the one a plan computes from the base potential (its discrete
+    current equation, ``st_plan_export_jbar``).  ``plan_kw`` are the options of
+    every linearisation's plan (precision, inner solvers, ...)."""
+
+    def __init__(self, n, nt, dt, mu, eta, mu0, fields, device="cuda:0", stream=None, **plan_kw):
+        import torch
+        self.n, self.nt, self.dt, self.mu, self.eta, self.mu0 = n, nt, dt, mu, eta, mu0
+        arr = {k: (None if v is None else np.ascontiguousarray(v, dtype=np.float64)) for k, v in fields.items()}
+        # the plan of the base state: template of every linearisation, and the base current
+        plan = Plan(n, nt, dt, mu, eta, mu0, arr["u_base"], arr["a_base"], jbar=arr.get("j_base"), **plan_kw)
+        if arr.get("j_base") is None:
+            arr["j_base"] = plan.export_jbar()
+        self.template = plan.problem
+        self.template.ubar = self.template.abar = self.template.jbar = ctypes.POINTER(ctypes.c_double)()
+        self.lin_bytes = plan.workspace_bytes
+        plan.close()
+        self._arr = arr
+        p = StNlProblem()
+        p.n, p.nt, p.dt, p.mu, p.eta, p.mu0 = n, nt, dt, mu, eta, mu0
+        null = ctypes.POINTER(ctypes.c_double)()
+        for k in ("u_base", "p_base", "j_base", "a_base", "u_init", "a_init", "f", "e"):
+            setattr(p, k, _dptr(arr[k]) if arr.get(k) is not None else null)
+        self.problem = p
+        wb = ctypes.c_size_t()
+        _check(lib().st_nl_workspace_size(ctypes.byref(p), ctypes.byref(wb)), "st_nl_workspace_size")
+        self.device = torch.device(device)
+        self.ws = torch.empty(wb.value + 256, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        _check(lib().st_nl_create(ctypes.byref(p), ctypes.c_void_p((self.ws.data_ptr() + 255) & ~255),
+                                  ctypes.c_size_t(wb.value), _stream_ptr(stream), ctypes.byref(h)), "st_nl_create")
+        self.ptr = h
+        self.ns = int(inputs_slab_size(n))
+        self.N = self.ns * nt
+        # the linear workspace, reused by every linearisation (a quarter of margin for
+        # hierarchies whose sizes follow the state)
+        self.lin_ws_bytes = int(self.lin_bytes * 1.25) + (1 << 20)
+        self.lin_ws = torch.empty(self.lin_ws_bytes + 256, dtype=torch.uint8, device=self.device)
+
+    def residual(self, x, r=None, stream=None):
+        import torch
+        r = torch.empty_like(x) if r is None else r
+        _check(lib().st_nl_residual(self.ptr, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(r.data_ptr()),
+                                    _stream_ptr(stream)), "st_nl_residual")
+        return r
+
+    def solve(self, x=None, atol=1e-10, max_newton=20, lin_rtol=1e-2, lin_atol=1e-14, restart=30, maxit=1000,
+              stream=None):
+        """Newton from x (zero if None), updated in place.  Returns (x, info, status)."""
+        import torch
+        x = torch.zeros(self.N, dtype=torch.float64, device=self.device) if x is None else x
+        o = StNewtonOpts()
+        o.max_newton, o.atol = max_newton, atol
+        o.linear.restart, o.linear.maxit, o.linear.rtol, o.linear.atol = restart, maxit, lin_rtol, lin_atol
+        o.linear.history_len = 0
+        o.linear.history = ctypes.POINTER(ctypes.c_double)()
+        info = StNewtonInfo()
+        ws_ptr = (self.lin_ws.data_ptr() + 255) & ~255
+        rc = _check(lib().st_newton_solve(self.ptr, ctypes.byref(self.template), ctypes.c_void_p(ws_ptr),
+                                          ctypes.c_size_t(self.lin_ws_bytes), ctypes.c_void_p(x.data_ptr()),
+                                          ctypes.byref(o), ctypes.byref(info), _stream_ptr(stream)),
+                    "st_newton_solve")
+        return x, info, rc
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().st_nl_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def inputs_slab_size(n):
+    """Unknowns of one slab: interior u (2 components), all p and j, interior A."""
+    return 2 * (2 * n - 1) ** 2 + 2 * (n + 1) ** 2 + (n - 1) ** 2
 
 
 class Batch:

@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "kernels_nl.h"
 #include "kernels_vec.h"
 #include "launch.h"
 #include "st_internal.h"
@@ -2053,6 +2054,190 @@ std::vector<void*> relocated(const Handle& H, const std::vector<size_t>& offs, c
 }  // namespace
 }  // namespace st
 
+namespace st {
+namespace {
+
+// ================================================= space-time Newton ===
+// Newton's method on the nonlinear recurrence, eq. (recurrence), all slabs at
+// once (Sec. "Performance of preconditioner"): the residual on the device
+// (kernels_nl.h), the linearisation about the current iterate assembled on the
+// host into a plan and uploaded into the caller's linear workspace, its
+// correction from FGMRES with P_T, and the update on the device.
+struct NonlinearState {
+  int n = 0, nt = 0, ns = 0;
+  double dt = 0, mu = 0, eta = 0, mu0 = 0;
+  int64_t N = 0;
+  char* base = nullptr;
+  double *ub = nullptr, *pb = nullptr, *jb = nullptr, *ab = nullptr, *u0 = nullptr, *a0 = nullptr;
+  double *f = nullptr, *e = nullptr, *elem = nullptr, *r = nullptr, *b = nullptr, *d = nullptr;
+  double *su = nullptr, *sj = nullptr, *sa = nullptr, *part = nullptr;
+  double* host = nullptr;   // pinned: the norm partials
+};
+
+constexpr int kNlNormBlocks = 256;
+
+struct NlLayoutHost {
+  size_t ub, pb, jb, ab, u0, a0, f, e, elem, r, b, d, su, sj, sa, part, end;
+};
+
+NlLayoutHost nl_layout(const st_nl_problem& p) {
+  NlLayoutHost L{};
+  size_t cur = 0;
+  auto take = [&](size_t bytes) {
+    const size_t off = cur;
+    cur = (cur + bytes + 255) & ~size_t(255);
+    return off;
+  };
+  const size_t nt = size_t(p.nt), nq2 = size_t(2 * p.n + 1) * (2 * p.n + 1), nq1 = size_t(p.n + 1) * (p.n + 1);
+  const NlLayout D(p.n);
+  const size_t N = nt * size_t(D.ns);
+  L.ub = take(8 * nt * 2 * nq2);
+  L.pb = take(8 * nt * nq1);
+  L.jb = take(8 * nt * nq1);
+  L.ab = take(8 * nt * nq1);
+  L.u0 = take(8 * 2 * nq2);
+  L.a0 = take(8 * nq1);
+  L.f = take(p.f ? 8 * nt * 2 * nq2 : 0);
+  L.e = take(p.e ? 8 * nt * nq1 : 0);
+  L.elem = take(8 * nt * size_t(p.n) * p.n * kNlLocal);
+  L.r = take(8 * N);
+  L.b = take(8 * N);
+  L.d = take(8 * N);
+  L.su = take(8 * nt * 2 * nq2);
+  L.sj = take(8 * nt * nq1);
+  L.sa = take(8 * nt * nq1);
+  L.part = take(8 * kNlNormBlocks);
+  L.end = cur;
+  return L;
+}
+
+NlArgs nl_args(const NonlinearState& S, const double* x, double* r) {
+  NlArgs a;
+  a.n = S.n;
+  a.nt = S.nt;
+  a.h = 1.0 / S.n;
+  a.dt = S.dt;
+  a.mu = S.mu;
+  a.eta = S.eta;
+  a.mu0 = S.mu0;
+  a.ub = S.ub;
+  a.pb = S.pb;
+  a.jb = S.jb;
+  a.ab = S.ab;
+  a.u0 = S.u0;
+  a.a0 = S.a0;
+  a.f = S.f;
+  a.e = S.e;
+  a.x = x;
+  a.elem = S.elem;
+  a.r = r;
+  return a;
+}
+
+void nl_residual(const NonlinearState& S, const double* x, double* r, hipStream_t s) {
+  const NlArgs a = nl_args(S, x, r);
+  const int64_t ne = int64_t(S.n) * S.n * S.nt;
+  hipLaunchKernelGGL(k_nl_element, dim3(unsigned((ne + 255) / 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_nl_gather, dim3(unsigned((S.N + 255) / 256)), dim3(256), 0, s, a);
+}
+
+int nl_norm(NonlinearState& S, const double* x, hipStream_t s, double* out) {
+  NlNormArgs a{x, S.N, S.part};
+  hipLaunchKernelGGL(k_nl_norm_partial, dim3(kNlNormBlocks), dim3(256), 0, s, a);
+  HIP_TRY(hipMemcpyAsync(S.host, S.part, sizeof(double) * kNlNormBlocks, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double acc = 0.0;
+  for (int i = 0; i < kNlNormBlocks; ++i) acc += S.host[i];
+  *out = std::sqrt(acc);
+  return ST_OK;
+}
+
+void nl_axpby(const double* x, double* y, double alpha, double beta, int64_t n, hipStream_t s) {
+  NlAxpbyArgs a{x, y, alpha, beta, n};
+  hipLaunchKernelGGL(k_nl_axpby, dim3(unsigned(std::min<int64_t>((n + 255) / 256, 8192))), dim3(256), 0, s, a);
+}
+
+}  // namespace
+}  // namespace st
+
+struct st_nl {
+  st::NonlinearState s;
+};
+
+namespace st {
+namespace {
+
+int newton_solve(st_nl* nl, const st_problem* lin, void* lin_ws, size_t lin_ws_bytes, double* x,
+                 const st_newton_opts* o, st_newton_info* info, hipStream_t s) {
+  NonlinearState& S = nl->s;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int maxn = std::min(o->max_newton > 0 ? o->max_newton : 20, ST_NEWTON_MAX);
+  std::memset(info, 0, sizeof(*info));
+  const size_t nq2 = size_t(2 * S.n + 1) * (2 * S.n + 1), nq1 = size_t(S.n + 1) * (S.n + 1);
+  std::vector<double> hu(size_t(S.nt) * 2 * nq2), hj(size_t(S.nt) * nq1), ha(size_t(S.nt) * nq1);
+  for (int it = 0;; ++it) {
+    nl_residual(S, x, S.r, s);
+    double rn = 0.0;
+    int rc = nl_norm(S, S.r, s, &rn);
+    if (rc) return rc;
+    if (!std::isfinite(rn)) return ST_EBREAKDOWN;
+    info->residual_norm[it] = rn;
+    info->newton_iterations = it;
+    if (rn <= o->atol) {
+      info->converged = 1;
+      break;
+    }
+    if (it >= maxn) break;
+    // linearisation state: full nodal fields of the iterate, to the host
+    NlStateArgs sa{S.n, S.nt, S.ub, S.jb, S.ab, x, S.su, S.sj, S.sa};
+    const int64_t per = int64_t(2 * nq2 + 2 * nq1) * S.nt;
+    hipLaunchKernelGGL(k_nl_state, dim3(unsigned((per + 255) / 256)), dim3(256), 0, s, sa);
+    HIP_TRY(hipMemcpyAsync(hu.data(), S.su, 8 * hu.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hj.data(), S.sj, 8 * hj.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ha.data(), S.sa, 8 * ha.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const auto ts = std::chrono::steady_clock::now();
+    st_problem pr = *lin;
+    pr.n = S.n;
+    pr.nt = S.nt;
+    pr.dt = S.dt;
+    pr.mu = S.mu;
+    pr.eta = S.eta;
+    pr.mu0 = S.mu0;
+    pr.ubar = hu.data();
+    pr.abar = ha.data();
+    pr.jbar = hj.data();
+    st_plan* plan = nullptr;
+    rc = st_plan_create(&pr, &plan);
+    if (rc) return rc;
+    st_handle* h = nullptr;
+    rc = st_create(plan, lin_ws, lin_ws_bytes, s, &h);
+    st_plan_destroy(plan);
+    if (rc) return rc;
+    info->setup_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count();
+    // correction: J d = -r with FGMRES and P_T, from zero
+    nl_axpby(S.r, S.b, -1.0, 0.0, S.N, s);
+    st_opts lo = o->linear;
+    lo.x0_given = 0;
+    lo.history = nullptr;
+    lo.history_len = 0;
+    st_info li;
+    std::memset(&li, 0, sizeof(li));
+    rc = fgmres(h->h, S.b, S.d, &lo, &li, s, false);
+    st_destroy(h);
+    if (rc < 0) return rc;
+    info->linear_iterations[it] = li.iterations;
+    info->linear_iterations_total += li.iterations;
+    nl_axpby(S.d, x, 1.0, 1.0, S.N, s);
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return info->converged ? ST_OK : ST_ENOTCONV;
+}
+
+}  // namespace
+}  // namespace st
+
 extern "C" {
 
 int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_handle** out) {
@@ -2469,6 +2654,102 @@ int st_batch_destroy(st_batch* b) {
   if (b->b.host_out) (void)hipHostFree(b->b.host_out);
   if (b->b.staging) (void)hipHostFree(b->b.staging);
   delete b;
+  return ST_OK;
+}
+
+int st_nl_workspace_size(const st_nl_problem* p, size_t* bytes) {
+  if (!p || !bytes || p->n < 2 || p->nt < 1) return ST_EINVAL;
+  *bytes = st::nl_layout(*p).end;
+  return ST_OK;
+}
+
+int st_nl_create(const st_nl_problem* p, void* ws, size_t ws_bytes, void* stream, st_nl** out) {
+  using namespace st;
+  if (!p || !ws || !out || p->n < 2 || p->nt < 1 || !(p->dt > 0) || !p->u_base || !p->p_base || !p->j_base ||
+      !p->a_base || !p->u_init || !p->a_init)
+    return ST_EINVAL;
+  *out = nullptr;
+  const NlLayoutHost L = nl_layout(*p);
+  if (ws_bytes < L.end) return ST_ENOMEM;
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return ST_EINVAL;
+  st_nl* nl = nullptr;
+  try {
+    nl = new st_nl;
+  } catch (...) {
+    return ST_ENOMEM;
+  }
+  NonlinearState& S = nl->s;
+  S.n = p->n;
+  S.nt = p->nt;
+  S.dt = p->dt;
+  S.mu = p->mu;
+  S.eta = p->eta;
+  S.mu0 = p->mu0;
+  S.ns = NlLayout(p->n).ns;
+  S.N = int64_t(S.ns) * S.nt;
+  S.base = static_cast<char*>(ws);
+  char* B = S.base;
+  S.ub = at<double>(B, L.ub);
+  S.pb = at<double>(B, L.pb);
+  S.jb = at<double>(B, L.jb);
+  S.ab = at<double>(B, L.ab);
+  S.u0 = at<double>(B, L.u0);
+  S.a0 = at<double>(B, L.a0);
+  S.f = p->f ? at<double>(B, L.f) : nullptr;
+  S.e = p->e ? at<double>(B, L.e) : nullptr;
+  S.elem = at<double>(B, L.elem);
+  S.r = at<double>(B, L.r);
+  S.b = at<double>(B, L.b);
+  S.d = at<double>(B, L.d);
+  S.su = at<double>(B, L.su);
+  S.sj = at<double>(B, L.sj);
+  S.sa = at<double>(B, L.sa);
+  S.part = at<double>(B, L.part);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t nt = size_t(p->nt), nq2 = size_t(2 * p->n + 1) * (2 * p->n + 1), nq1 = size_t(p->n + 1) * (p->n + 1);
+  bool ok = hipHostMalloc(reinterpret_cast<void**>(&S.host), sizeof(double) * kNlNormBlocks, hipHostMallocDefault) ==
+            hipSuccess;
+  auto up = [&](double* dst, const double* src, size_t count) {
+    if (ok && src) ok = hipMemcpyAsync(dst, src, 8 * count, hipMemcpyHostToDevice, s) == hipSuccess;
+  };
+  up(S.ub, p->u_base, nt * 2 * nq2);
+  up(S.pb, p->p_base, nt * nq1);
+  up(S.jb, p->j_base, nt * nq1);
+  up(S.ab, p->a_base, nt * nq1);
+  up(S.u0, p->u_init, 2 * nq2);
+  up(S.a0, p->a_init, nq1);
+  up(S.f, p->f, nt * 2 * nq2);
+  up(S.e, p->e, nt * nq1);
+  if (!ok || hipStreamSynchronize(s) != hipSuccess) {
+    if (S.host) (void)hipHostFree(S.host);
+    delete nl;
+    return ST_EHIP;
+  }
+  *out = nl;
+  return ST_OK;
+}
+
+int st_nl_residual(st_nl* nl, const double* x, double* r, void* stream) {
+  if (!nl || !x || !r || x == r) return ST_EINVAL;
+  st::nl_residual(nl->s, x, r, static_cast<hipStream_t>(stream));
+  return hipGetLastError() == hipSuccess ? ST_OK : ST_EHIP;
+}
+
+int st_newton_solve(st_nl* nl, const st_problem* lin, void* lin_ws, size_t lin_ws_bytes, double* x,
+                    const st_newton_opts* o, st_newton_info* info, void* stream) {
+  if (!nl || !lin || !lin_ws || !x || !o || !info) return ST_EINVAL;
+  if (lin->n != nl->s.n || lin->nt != nl->s.nt || lin->precond_variant != 0 || lin->adjoint) return ST_EINVAL;
+  try {
+    return st::newton_solve(nl, lin, lin_ws, lin_ws_bytes, x, o, info, static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return ST_ENOMEM;
+  }
+}
+
+int st_nl_destroy(st_nl* nl) {
+  if (!nl) return ST_OK;
+  if (nl->s.host) (void)hipHostFree(nl->s.host);
+  delete nl;
   return ST_OK;
 }
 

@@ -186,3 +186,76 @@ def free_a_field(cfg: Config, seed: int) -> np.ndarray:
     x1, y1 = q1_coords(cfg.n)
     f = _fourier_field(params[0], x1, y1, 0.0).reshape(cfg.n + 1, cfg.n + 1)
     return np.ascontiguousarray(f[1:-1, 1:-1].ravel())
+
+
+# --------------------------------------------------------- model problems ---
+# The paper's two model problems (Sec. "Model problems") as closed-form nodal
+# fields on the unit square: a magnetic equilibrium (A_eq, the pressure p_eq
+# that balances its Lorentz force, and the electric field E_eq that sustains
+# it against resistive diffusion), a quiet flow, and a perturbed initial
+# potential.  Island coalescence lives on the unit square as in the paper;
+# the tearing mode's Harris sheet is centred at y = 1/2 of the unit square
+# (x-length L = 1).  Boundary values are those of the fields (Dirichlet on
+# every side for u and A).
+
+
+@dataclasses.dataclass(frozen=True)
+class ModelProblem:
+    name: str
+    n: int
+    nt: int
+    dt: float
+    mu: float = 1.0
+    eta: float = 1.0
+    mu0: float = 1.0
+
+
+def model_fields(prob: ModelProblem):
+    """(A_eq, p_eq, E_eq) at the Q1 nodes and A_init (the perturbed initial
+    potential) at the Q1 nodes, float64; the flow is at rest (u = 0)."""
+    x, y = q1_coords(prob.n)
+    if prob.name == "island":
+        beta, eps = 0.2, 1e-3
+        den = np.cosh(2 * math.pi * y) + beta * np.cos(2 * math.pi * x)
+        A = np.log(den) / (2 * math.pi)
+        p = (1 - beta ** 2) / den ** 2 / (2 * prob.mu0)
+        E = (prob.eta / prob.mu0) * 2 * math.pi * (1 - beta ** 2) / den ** 2
+        A0 = A + eps * np.cos(0.5 * math.pi * y) * np.cos(math.pi * x)
+    elif prob.name == "tearing":
+        lam, eps, L = 5.0, 1e-3, 1.0
+        ys = y - 0.5
+        A = np.log(np.cosh(lam * ys)) / lam
+        p = 1.0 / np.cosh(lam * ys) ** 2 / (2 * prob.mu0)
+        E = (lam * prob.eta / prob.mu0) / np.cosh(lam * ys) ** 2
+        A0 = A - eps * np.cos(math.pi * ys) * np.cos(2 * math.pi * x / L)
+    else:
+        raise ValueError(prob.name)
+    return A, p - p.mean(), E, A0
+
+
+def model_newton_fields(prob: ModelProblem):
+    """Base fields, fields at t_0 and forcing of the model problem's space-time
+    Newton solve, float64 C-contiguous:
+
+    * base: every slab at the equilibrium (u = 0, p = p_eq, A = A_eq), except
+      that A's boundary values are those of the initial potential (Dirichlet
+      data, fixed in time);
+    * u_init = 0, A_init = the perturbed potential;
+    * E: the sustaining electric field on every slab; no momentum forcing.
+
+    The base current is not included: it solves the discrete current equation
+    of each slab's base potential (computed by the solver in use)."""
+    A, p, E, A0 = model_fields(prob)
+    n, nt = prob.n, prob.nt
+    nq2 = (2 * n + 1) ** 2
+    x, y = q1_coords(n)
+    bnd = (x == 0.0) | (x == 1.0) | (y == 0.0) | (y == 1.0)
+    Ab = np.where(bnd, A0, A)
+    return {
+        "u_base": np.zeros((nt, 2, nq2)),
+        "p_base": np.ascontiguousarray(np.tile(p, (nt, 1))),
+        "a_base": np.ascontiguousarray(np.tile(Ab, (nt, 1))),
+        "u_init": np.zeros((2, nq2)),
+        "a_init": np.ascontiguousarray(A0),
+        "e": np.ascontiguousarray(np.tile(E, (nt, 1))),
+    }
