@@ -54,6 +54,10 @@ def sweep_kernel_digest():
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
+GROUPING = {"all": "every member in one lockstep batch", "mesh": "one lockstep batch per mesh size",
+            "split": "members with n < 64 in one lockstep batch, the others one at a time"}
+
+
 def variant_name(v):
     return {"PT": "P_T", "Ptilde": "P-tilde", "P": "full P"}[v]
 
@@ -210,27 +214,48 @@ def bench_batch(args, dev):
         log(f"setup {c.name}: n={c.n} Nt={c.nt} N={systems[-1].N}, inner degrees F_u {si[0]} C_A {si[1]} "
             f"(kappa {si[2]:.1f}, {si[3]:.1f}), launches {systems[-1].tuning()}")
     log(f"setup {time.perf_counter() - t0:.1f} s, {len(cfgs)} systems, N total {ntot}")
-    batch = binding.Batch(systems, restart=30)
-    lock, sep = batch.launch_counts()
+    # Lockstep groups: every member in one batch, or one batch per mesh size
+    # (members of one size have launches of similar length, so a grouped
+    # launch does not wait for a much larger member's op).
+    if args.batch_groups == "mesh":
+        sizes = sorted({c.n for c in cfgs})
+        groups = [[i for i, c in enumerate(cfgs) if c.n == nn] for nn in sizes]
+    elif args.batch_groups == "split":
+        # members whose sweep steps fill the GPU alone (n >= 64: 32,258 F_u rows
+        # per slab or more) solved one at a time, the latency-bound rest in lockstep
+        groups = [[i for i, c in enumerate(cfgs) if c.n < 64]] + [[i] for i, c in enumerate(cfgs) if c.n >= 64]
+    else:
+        groups = [list(range(len(cfgs)))]
+    batches = [binding.Batch([systems[i] for i in g], restart=30) if len(g) > 1 else None for g in groups]
+    counts = [b.launch_counts() if b is not None else (0, 0) for b in batches]
+    lock, sep = sum(c[0] for c in counts), sum(c[1] for c in counts)
     # Iteration budget per member, in calls of whole restart cycles (the next
     # call restarts from the iterate); members that stagnate use all of it.
-    chunk, budget = 240, args.batch_budget
+    budget = args.batch_budget
+    chunk = min(240, budget)
 
     def solve_all(label):
-        xs = [torch.zeros_like(b) for b in rhs]
         total = [0] * len(rhs)
         status = [1] * len(rhs)
         res = [1.0] * len(rhs)
-        for call in range(max(1, budget // chunk)):
-            xs, infos, sts, rc, _ = batch.solve(rhs, xs, rtol=args.rtol, maxit=chunk, x0=call > 0)
-            if rc < 0:
-                raise RuntimeError(f"batched solve: status {rc}, member statuses {sts}")
-            total = [t + i.iterations for t, i in zip(total, infos)]
-            status, res = list(sts), [i.true_rel_residual for i in infos]
-            log(f"  {label}: {sum(total)} member iterations, open: "
-                f"{[(k, f'{res[k]:.1e}') for k, st in enumerate(status) if st != 0]}")
-            if rc == 0:
-                break
+        for g, batch in zip(groups, batches):
+            bs = [rhs[i] for i in g]
+            xs = [torch.zeros_like(b) for b in bs]
+            for call in range(max(1, budget // chunk)):
+                if batch is None:   # one member: its own recorded pipeline
+                    x1, info1, rc, _ = systems[g[0]].solve(bs[0], xs[0], rtol=args.rtol, maxit=chunk, x0=call > 0)
+                    xs, infos, sts = [x1], [info1], [rc]
+                else:
+                    xs, infos, sts, rc, _ = batch.solve(bs, xs, rtol=args.rtol, maxit=chunk, x0=call > 0)
+                if rc < 0:
+                    raise RuntimeError(f"batched solve: status {rc}, member statuses {sts}")
+                for i, inf, st in zip(g, infos, sts):
+                    total[i] += inf.iterations
+                    status[i], res[i] = st, inf.true_rel_residual
+                if rc == 0:
+                    break
+            log(f"  {label}: group {g}: {sum(total[i] for i in g)} member iterations, open: "
+                f"{[(k, f'{res[k]:.1e}') for k in g if status[k] != 0]}")
         return total, status, res
 
     for i in range(args.warmup):
@@ -249,12 +274,14 @@ def bench_batch(args, dev):
         "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32-precond/f64-krylov", "data": "synthetic",
         "config": {"workload": f"cfg4: {len(cfgs)} uneven systems (n, Nt) = "
-                               f"{[(c.n, c.nt) for c in cfgs]}, dt = 1/Nt, Re=S=300; lockstep FGMRES(30) to "
+                               f"{[(c.n, c.nt) for c in cfgs]}, dt = 1/Nt, Re=S=300; lockstep FGMRES(30) "
+                               f"({GROUPING[args.batch_groups]}) to "
                                f"{args.rtol:g} within {budget} iterations per member, P_T in FP32",
                    "N_total": ntot},
         "time_to_1e8_s": elapsed / args.steps if all(converged) else None,
         "fgmres_iters": its, "converged": converged, "true_rel_residual": res,
         "launches_per_arnoldi_step": {"lockstep": lock, "one_at_a_time": sep},
+        "lockstep_groups": groups,
     }
     if not args.no_separate:
         # the same systems one at a time, same budget (each with its own recorded pipeline)
@@ -426,6 +453,8 @@ def main():
                     help="time every k-th launch of the paired sweep-step kernel with HIP events")
     ap.add_argument("--no-separate", action="store_true", help="cfg4: skip the one-at-a-time comparison")
     ap.add_argument("--batch-budget", type=int, default=960, help="cfg4: FGMRES iterations per member")
+    ap.add_argument("--batch-groups", choices=sorted(GROUPING), default="all",
+                    help="cfg4: " + "; ".join(f"{k}: {v}" for k, v in GROUPING.items()))
     ap.add_argument("--no-fd", action="store_true", help="cfg5: skip the finite-difference check")
     ap.add_argument("--no-autotune", action="store_true",
                     help="default launch choices instead of timing them at st_create")

@@ -286,51 +286,61 @@ template <class T> struct KB<kKSetPtrs, T> {
   __device__ static void run(const Args& a, int, int) { set_ptrs_body(a); }
 };
 
-struct GroupMember {
-  const unsigned char* args;   // device copy of the op's argument block
-  int blocks;                  // gx * gy
-  int gx;
-  int second;                  // k_group2: 1 = the second body
-  int pad;
-};
+// An op's argument block, read from device memory word by word into scalar
+// registers at the start of the workgroup: the address is the same for the
+// whole workgroup, and v_readfirstlane tells the compiler that every field is
+// uniform.  (Copied as a struct, parts of the block land in vector registers
+// as values that may differ between lanes, and every buffer load built from
+// them becomes a loop over the lanes' distinct resources.)  The blocks are
+// written before the launch and only read by it.
+template <class A>
+__device__ inline A load_args(const unsigned char* p) {
+  static_assert(sizeof(A) % 4 == 0, "argument blocks are whole words");
+  constexpr int W = int(sizeof(A) / 4);
+  const __attribute__((address_space(4))) uint32_t* src = (const __attribute__((address_space(4))) uint32_t*)(p);
+  uint32_t w[W];
+#pragma unroll
+  for (int i = 0; i < W; ++i) w[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  A a;
+  __builtin_memcpy(&a, w, sizeof(A));
+  return a;
+}
 
+// The ops of one grouped launch: op i runs on workgroups [start[i],
+// start[i + 1]) with its argument block args[i] (a device copy), its own grid
+// width gx[i] and (k_group2) body second[i]; start[n] is the total and the
+// starts after it are INT_MAX.
 struct GroupArgs {
   int n;
   int pad;
-  GroupMember m[kMaxMembersG];
+  int start[kMaxMembersG + 1];
+  int gx[kMaxMembersG];
+  int second[kMaxMembersG];
+  const unsigned char* args[kMaxMembersG];
 };
 
-// Finds the member of workgroup blockIdx.x: returns its index and the block
-// within it (static member indices only, so the table stays in kernel arguments).
+// Finds the op of workgroup blockIdx.x: returns its index and the block
+// within it.  A binary search over the starts (nondecreasing, INT_MAX after
+// the total) for the last one at or below the workgroup: six scalar loads
+// from the kernel arguments, whatever the number of ops.
 __device__ inline int group_member(const GroupArgs& g, int& rem) {
-  rem = blockIdx.x;
-  int sel = -1;
+  static_assert((kMaxMembersG & (kMaxMembersG - 1)) == 0, "the search halves a power of two");
+  const int b = int(blockIdx.x);
+  int lo = 0;
 #pragma unroll
-  for (int i = 0; i < kMaxMembersG; ++i) {
-    if (sel < 0 && i < g.n) {
-      if (rem < g.m[i].blocks) sel = i;
-      else rem -= g.m[i].blocks;
-    }
-  }
-  return sel;
+  for (int step = kMaxMembersG / 2; step > 0; step >>= 1)
+    if (b >= g.start[lo + step]) lo += step;
+  rem = b - g.start[lo];
+  return lo;
 }
 
 template <int K, class T>
 __global__ ST_LATENCY_KERNEL void k_group(GroupArgs g) {
   int rem = 0;
   const int sel = group_member(g, rem);
-  if (sel < 0) return;
-  const unsigned char* p = nullptr;
-  int gx = 1;
-#pragma unroll
-  for (int i = 0; i < kMaxMembersG; ++i)
-    if (i == sel) {
-      p = g.m[i].args;
-      gx = g.m[i].gx;
-    }
   using A = typename KB<K, T>::Args;
-  const A a = *reinterpret_cast<const A* __restrict__>(p);
-  KB<K, T>::run(a, rem, gx);
+  const A a = load_args<A>(g.args[sel]);
+  KB<K, T>::run(a, rem, g.gx[sel]);
 }
 
 // Tiled sweep solves of several systems (both sweeps of each) in one launch.
@@ -338,12 +348,7 @@ template <class T>
 __global__ ST_SOLVE_KERNEL void k_group_solve(GroupArgs g) {
   int rem = 0;
   const int sel = group_member(g, rem);
-  if (sel < 0) return;
-  const unsigned char* p = nullptr;
-#pragma unroll
-  for (int i = 0; i < kMaxMembersG; ++i)
-    if (i == sel) p = g.m[i].args;
-  const StSolveArgs<T> a = *reinterpret_cast<const StSolveArgs<T>* __restrict__>(p);
+  const StSolveArgs<T> a = load_args<StSolveArgs<T>>(g.args[sel]);
   st_solve_body<T>(a, rem);
 }
 
@@ -351,23 +356,15 @@ template <int K1, int K2, class T>
 __global__ ST_LATENCY_KERNEL void k_group2(GroupArgs g) {
   int rem = 0;
   const int sel = group_member(g, rem);
-  if (sel < 0) return;
-  const unsigned char* p = nullptr;
-  int gx = 1, second = 0;
-#pragma unroll
-  for (int i = 0; i < kMaxMembersG; ++i)
-    if (i == sel) {
-      p = g.m[i].args;
-      gx = g.m[i].gx;
-      second = g.m[i].second;
-    }
-  if (second) {
+  const unsigned char* p = g.args[sel];
+  const int gx = g.gx[sel];
+  if (g.second[sel]) {
     using A = typename KB<K2, T>::Args;
-    const A a = *reinterpret_cast<const A* __restrict__>(p);
+    const A a = load_args<A>(p);
     KB<K2, T>::run(a, rem, gx);
   } else {
     using A = typename KB<K1, T>::Args;
-    const A a = *reinterpret_cast<const A* __restrict__>(p);
+    const A a = load_args<A>(p);
     KB<K1, T>::run(a, rem, gx);
   }
 }

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <new>
 #include <type_traits>
@@ -1813,13 +1814,15 @@ void launch_groups(const MultiArgs& step, hipStream_t s) {
     for (int i = 0; i < step.nmem; ++i) {
       const Member& m = step.m[i];
       if (m.kind != k1 && m.kind != k2) continue;
-      GroupMember& gm = g.m[g.n++];
-      gm.args = m.args;
-      gm.blocks = m.blocks;
-      gm.gx = m.gx;
-      gm.second = m.kind == k2 && k2 != k1 ? 1 : 0;
+      g.start[g.n] = int(total);
+      g.args[g.n] = m.args;
+      g.gx[g.n] = m.gx;
+      g.second[g.n] = m.kind == k2 && k2 != k1 ? 1 : 0;
+      ++g.n;
       total += m.blocks;
     }
+    g.start[g.n] = int(total);
+    for (int i = g.n + 1; i <= kMaxMembersG; ++i) g.start[i] = std::numeric_limits<int>::max();
     void* params[] = {&g};
     (void)hipLaunchKernel(fn, dim3(unsigned(total)), dim3(unsigned(block_of(k1))), params, 0, s);
   };
