@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 # valid while the kernel source it measured is unchanged (digest of that source).
 JAC_COUNTERS = {"config": "cfg3", "j_slabs": 8, "source_sha256_16": "2863946ff1f01491", "traffic_bytes": 2.330e9}
 # The same for one launch of the paired sweep-step kernel at the default workload
-# (profiles/pmc_cfg3_sweep_step_fetch_write.md); None until measured.
-SWEEP_COUNTERS = {"config": "cfg3", "source_sha256_16": None, "traffic_bytes": None}
+# (profiles/pmc_cfg3_sweep_step_fetch_write.md).
+SWEEP_COUNTERS = {"config": "cfg3", "source_sha256_16": "edf3e1f027282742", "traffic_bytes": 1.050e7}
 # rocprofv3 average duration of that kernel at the default workload without event sampling
 # (profiles/kstats_cfg3_fgmres_fp32_pipeline.md), valid for the same kernel source.
 SWEEP_ROCPROF = {"config": "cfg3", "source_sha256_16": "edf3e1f027282742", "avg_us": 4.159}
