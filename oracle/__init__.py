@@ -27,7 +27,10 @@ incompressible resistive magnetohydrodynamics", arXiv:2309.00768):
 * ``timestepping`` sequential time stepping with the single-step
                  preconditioner P_{T,k}, eq. (PTTS);
 * ``variants``   the full preconditioner P and P-tilde, eqs. (preconditioner),
-                 (preconditionerSimplified1), from their factors.
+                 (preconditionerSimplified1), from their factors;
+* ``paratime``   Parareal over the slab steps of the F_u and C_A sweeps
+                 (parallel-in-time inner solves, the paper's outlook) and the
+                 Chebyshev-Jacobi spatial solve of its coarse propagator.
 
 Parity status: every function here is pinned by a ``-m "not gpu"`` test against
 closed forms, invariants, brute force or finite differences, except the PCD
