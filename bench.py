@@ -443,6 +443,15 @@ def main():
                     help="oracle tolerance (its solution on the sampled slabs is the reference x*)")
     ap.add_argument("--sweep-lanes", type=int, default=0, choices=[0, 1, 2],
                     help="lanes per row of the F_u sweep steps when not autotuned (0: library default)")
+    ap.add_argument("--time-parallel", type=int, default=0,
+                    help="Parareal iterations for the two sweeps of P_T (0: forward substitution in time)")
+    ap.add_argument("--time-coarse", type=int, default=1,
+                    help="Chebyshev steps of the Parareal coarse propagator per slab")
+    ap.add_argument("--single-stream", action="store_true",
+                    help="P_T step by step in program order instead of the recorded two-program replay")
+    ap.add_argument("--inner", choices=["auto", "vcycle"], default="auto",
+                    help="spatial solves of the F_u and C_A sweeps: automatic (Chebyshev-Jacobi alone at the "
+                         "default workload) or one SA-AMG V(1,1) cycle per sweep step")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32",
                     help="newton: preconditioner precision of the corrections")
     ap.add_argument("--variant", choices=["PT", "Ptilde", "P"], default="PT",
@@ -503,14 +512,24 @@ def main():
     t0 = time.perf_counter()
     tune = not args.no_autotune
     m = args.restart
+    # spatial solves of the sweeps: the automatic choice (Chebyshev-Jacobi alone where it reaches the
+    # target reduction), or one SA-AMG V(1,1) cycle per sweep step on F_u,k and C_A,k
+    solver = {"fu_solver": -1, "ca_solver": -1} if args.inner == "vcycle" else {}
+    if args.time_parallel > 0:
+        solver.update(time_parallel=args.time_parallel, time_coarse_degree=args.time_coarse)
+    if args.single_stream:
+        solver.update(single_stream=True)
     plan32 = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp32", autotune=tune,
-                          max_restart=m, sweep_lanes=args.sweep_lanes, variant=args.variant)
+                          max_restart=m, sweep_lanes=args.sweep_lanes, variant=args.variant, **solver)
     N = plan32.ns * cfg.nt
     jbytes, nnz_state, nnz_const = jacobian_bytes(plan32, cfg.nt, N)
     plan_nnz = {b: plan32.block_nnz(b) for b in ("Fu", "C0")}
     fu_deg, ca_deg, _, _ = plan32.solver_info()
     inner = (f"Chebyshev-Jacobi sweeps of degree {fu_deg} on F_u,k and {ca_deg} on C_A,k "
              f"(0 = SA-AMG V(1,1)), SA-AMG V(1,1) on K_p")
+    if args.time_parallel > 0:
+        inner += (f"; both sweeps by {args.time_parallel} Parareal iterations (coarse propagator: "
+                  f"{args.time_coarse} Chebyshev step(s) per slab), step by step")
     sys32 = binding.System(plan32, dev)
     plan32.close()
     log(f"setup fp32 {time.perf_counter() - t0:.1f} s, N={N}, launches {sys32.tuning()}")
@@ -518,7 +537,8 @@ def main():
     if not args.no_fp64:
         t0 = time.perf_counter()
         plan64 = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp64",
-                              autotune=tune, max_restart=m, sweep_lanes=args.sweep_lanes, variant=args.variant)
+                              autotune=tune, max_restart=m, sweep_lanes=args.sweep_lanes, variant=args.variant,
+                              **solver)
         sys64 = binding.System(plan64, dev)
         plan64.close()
         log(f"setup fp64 {time.perf_counter() - t0:.1f} s, launches {sys64.tuning()}")

@@ -145,6 +145,26 @@ typedef struct st_problem {
                              only: st_apply_precond_t, the adjoint solve, the
                              allocation-free apply and batches take 0 only
                              (ST_EINVAL otherwise).                         */
+  int time_parallel;      /* the two sweeps of P_T^{-1} (F_u,k and C_A,k over
+                             the slabs, eqs. (STFu), (CAspacetime)): 0 forward
+                             substitution in time; K >= 1 K iterations of
+                             Parareal, the parallel-in-time inner solves the
+                             paper leaves to future work (Conclusions; footnote
+                             of Sec. "Comparison with single time-step block
+                             preconditioner").  Fine propagator: the slab step
+                             with the plan's Chebyshev degree; coarse: the same
+                             step with time_coarse_degree Chebyshev steps.  The
+                             fine steps of all slabs run together (one launch
+                             per Chebyshev step), the coarse sweep slab by slab;
+                             after K iterations the first K slabs equal the
+                             forward substitution, after Nt all of them.  Needs
+                             the stencil sweeps with Chebyshev alone on both
+                             blocks (sweep_format 0 and a positive degree chosen
+                             for each, else st_plan_create fails); P_T forward
+                             only, step by step: not with adjoint, batches or
+                             the allocation-free apply (ST_EINVAL).         */
+  int time_coarse_degree; /* Chebyshev steps of the coarse propagator per slab
+                             (0: 1); below both sweep degrees                 */
 } st_problem;
 
 typedef struct st_opts {
@@ -198,6 +218,12 @@ int st_plan_export_block(const st_plan* plan, int block, int k, int* nrows, int*
  * C_A,k (0 = SA-AMG V-cycle) and the estimated condition numbers of D^{-1} A. */
 int st_plan_solver_info(const st_plan* plan, int* fu_degree, int* ca_degree, double* fu_kappa,
                         double* ca_kappa);
+
+/* Chebyshev-alone intervals of the sweep blocks, host: which = 0 for F_u,k,
+ * 1 for C_A,k; out[2 k] = theta and out[2 k + 1] = delta of slab k (nt pairs),
+ * the interval [theta - delta, theta + delta] the Chebyshev-Jacobi steps of
+ * that slab's spatial solve assume for the eigenvalues of D^{-1} A. */
+int st_plan_cheb_intervals(const st_plan* plan, int which, double* out);
 
 /* The current state used (either given or computed), host [nt][(n+1)^2]. */
 int st_plan_export_jbar(const st_plan* plan, double* jbar);

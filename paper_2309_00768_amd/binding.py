@@ -37,7 +37,7 @@ class StProblem(ctypes.Structure):
         ("j_slabs", ctypes.c_int), ("sweep_fuse", ctypes.c_int),
         ("autotune", ctypes.c_int), ("sweep_lanes", ctypes.c_int),
         ("inner_reduction", ctypes.c_double), ("ca_reduction", ctypes.c_double),
-        ("precond_variant", ctypes.c_int),
+        ("precond_variant", ctypes.c_int), ("time_parallel", ctypes.c_int), ("time_coarse_degree", ctypes.c_int),
     ]
 
 
@@ -84,7 +84,7 @@ class StNewtonInfo(ctypes.Structure):
 
 EXPORTED = [
     "st_plan_create", "st_plan_workspace_size", "st_plan_sizes", "st_plan_export_block", "st_plan_export_jbar",
-    "st_plan_solver_info", "st_plan_jacobian_slots",
+    "st_plan_solver_info", "st_plan_cheb_intervals", "st_plan_jacobian_slots",
     "st_plan_destroy", "st_create", "st_destroy", "st_apply_jacobian", "st_apply_jacobian_t",
     "st_apply_precond", "st_apply_precond_t", "st_apply_precond_noalloc", "st_apply_initial_coupling",
     "st_fgmres_solve", "st_adjoint_solve", "st_timestep_solve",
@@ -110,6 +110,7 @@ def _load(path=LIB_PATH):
         "st_plan_export_block": ([vp, ctypes.c_int, ctypes.c_int, ip, ip, i64p, ip, ip, dp], ctypes.c_int),
         "st_plan_export_jbar": ([vp, dp], ctypes.c_int),
         "st_plan_solver_info": ([vp, ip, ip, dp, dp], ctypes.c_int),
+        "st_plan_cheb_intervals": ([vp, ctypes.c_int, dp], ctypes.c_int),
         "st_plan_jacobian_slots": ([vp, i64p, ip], ctypes.c_int),
         "st_plan_destroy": ([vp], ctypes.c_int),
         "st_create": ([vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)], ctypes.c_int),
@@ -184,7 +185,7 @@ class Plan:
                  inner_iters=0, mass_iters=0, cheb_degree=0, max_restart=0, sell_sigma=0, adjoint=False,
                  fu_solver=0, ca_solver=0, inner_reduction=0.0, j_lanes=0, ca_reduction=0.0, sweep_format=0,
                  single_stream=False, sweep_chunk=0, sweep_chain=True, j_slabs=0, sweep_fuse=False,
-                 autotune=False, sweep_lanes=0, variant="PT"):
+                 autotune=False, sweep_lanes=0, variant="PT", time_parallel=0, time_coarse_degree=0):
         self._ub = np.ascontiguousarray(ubar, dtype=np.float64)
         self._ab = np.ascontiguousarray(abar, dtype=np.float64)
         assert self._ub.shape == (nt, 2, (2 * n + 1) ** 2) and self._ab.shape == (nt, (n + 1) ** 2)
@@ -206,6 +207,7 @@ class Plan:
         p.autotune = int(autotune)
         p.sweep_lanes = sweep_lanes
         p.precond_variant = {"PT": 0, "Ptilde": 1, "P": 2}[variant]
+        p.time_parallel, p.time_coarse_degree = time_parallel, time_coarse_degree
         self.problem = p
         self.n, self.nt = n, nt
         h = ctypes.c_void_p()
@@ -241,6 +243,13 @@ class Plan:
         _check(lib().st_plan_export_block(self.ptr, BLOCK_IDS[name], k, ctypes.byref(nr), ctypes.byref(nc),
                                           ctypes.byref(nnz), ip(), ip(), ctypes.POINTER(ctypes.c_double)()), "nnz")
         return nnz.value
+
+    def cheb_intervals(self, which):
+        """(nt, 2) array of the (theta, delta) Chebyshev-alone intervals of F_u,k
+        ("Fu") or C_A,k ("CA") per slab."""
+        out = np.zeros((self.nt, 2))
+        _check(lib().st_plan_cheb_intervals(self.ptr, {"Fu": 0, "CA": 1}[which], _dptr(out)), "cheb_intervals")
+        return out
 
     def solver_info(self):
         """(fu_degree, ca_degree, fu_kappa, ca_kappa) chosen by the setup (degree 0 = AMG)."""

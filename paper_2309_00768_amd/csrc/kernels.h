@@ -509,7 +509,8 @@ __device__ inline T stencil_row_lanes(const StOp<T>& A, int set, int64_t row, co
 // sweep right-hand side: r = q + a1 S1 y1 + a2 S2 y2, d = Dinv r/theta and
 // x = x0 + d, where the predictor x0 = g1 y1 + g2 y2 (guess != 0) or 0.  With a
 // predictor the couplings S1, S2 already contain the diagonal block's action
-// on it, so that r is the residual of x0.
+// on it, so that r is the residual of x0.  A third term g3 y3 (g3 != 0) is
+// added to x only, not to the predictor r belongs to: a Parareal correction.
 template <class T>
 struct StInitArgs {
   StOp<T> S1, S2;
@@ -528,6 +529,8 @@ struct StInitArgs {
   double g1, g2;
   int rpb;              // rows per workgroup (lanes * rpb <= kBlock; fewer spread a small grid over more CUs)
   int lanes;            // 1, or 2 for two-component operators: a row's components on two lanes
+  const T* y3;
+  double g3;
 };
 
 template <class T>
@@ -547,6 +550,7 @@ __device__ inline void st_init_body(const StInitArgs<T>& a, int bx) {
   if (a.guess) {
     x0 = T(a.g1) * buf_ld<T>(buf_rsrc(a.y1, vb), ro, 0u);
     if (a.g2 != 0.0) x0 += T(a.g2) * buf_ld<T>(buf_rsrc(a.y2, vb), ro, 0u);
+    if (a.g3 != 0.0) x0 += T(a.g3) * buf_ld<T>(buf_rsrc(a.y3, vb), ro, 0u);
   }
   if (lq) return;
   buf_st<T>(buf_rsrc(a.r, vb), ro, acc);
@@ -755,6 +759,7 @@ __device__ inline void st_solve_body(const StSolveArgs<T>& a, int bx) {
           if (in.guess) {
             x0 = T(in.g1) * in.y1[row];
             if (in.g2 != 0.0) x0 += T(in.g2) * in.y2[row];
+            if (in.g3 != 0.0) x0 += T(in.g3) * in.y3[row];
           }
           xn = x0 + d;
         }

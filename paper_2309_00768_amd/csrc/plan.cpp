@@ -161,6 +161,11 @@ WsLayout workspace_layout(const Plan& P) {
   L.md02 = take(ts * nt * mm);
   L.md12 = take(ts * nt * mm);
   L.io = take(2 * sizeof(void*));
+  if (P.pint > 0)
+    for (int i = 0; i < 6; ++i) {
+      L.pint_u[i] = take(ts * nt * d.nu);
+      L.pint_a[i] = take(ts * nt * d.na);
+    }
   for (const AmgLevel& lv : P.amgKp.lev)
     for (int i = 0; i < 6; ++i) L.kp_lev.push_back(take(ts * nt * lv.nrows));
   for (const AmgLevel& lv : P.amgFu.lev)
@@ -195,6 +200,14 @@ static int build_plan(Plan& P, std::string& err) {
   }
   if (pr.autotune != 0 && pr.autotune != 1) {
     err = "autotune must be 0 or 1";
+    return ST_EINVAL;
+  }
+  if (pr.time_parallel < 0 || pr.time_coarse_degree < 0) {
+    err = "time_parallel and time_coarse_degree must be >= 0";
+    return ST_EINVAL;
+  }
+  if (pr.time_parallel > 0 && (pr.adjoint || pr.precond_variant != 0 || pr.sweep_format != 0)) {
+    err = "time_parallel needs P_T (precond_variant 0), no adjoint and the stencil sweeps (sweep_format 0)";
     return ST_EINVAL;
   }
   int rc = assemble_blocks(pr, P.blk, err);
@@ -328,6 +341,12 @@ static int build_plan(Plan& P, std::string& err) {
     P.ca_deg = pick(pr.ca_solver, P.amgC0, red_ca);
   }
   P.chunk = pr.sweep_chunk > 0 ? pr.sweep_chunk : std::max(4, (nt + 7) / 8);
+  P.pint = pr.time_parallel;
+  P.pint_deg = pr.time_coarse_degree > 0 ? pr.time_coarse_degree : 1;
+  if (P.pint > 0 && (P.fu_deg <= 0 || P.ca_deg <= 0 || P.pint_deg >= std::min(P.fu_deg, P.ca_deg))) {
+    err = "time_parallel needs Chebyshev alone on F_u,k and C_A,k, with degrees above time_coarse_degree";
+    return ST_EINVAL;
+  }
   // Stencil forms of the sweep operators (structured grids, 5x5 neighbourhoods).
   P.use_stencil = (P.fu_deg > 0 || P.ca_deg > 0) && pr.sweep_format == 0 ? 1 : 0;
   // Each sweep step solves for the increment over a predictor from the earlier
@@ -479,6 +498,18 @@ int st_plan_solver_info(const st_plan* plan, int* fu_degree, int* ca_degree, dou
   if (ca_degree) *ca_degree = plan->p.ca_deg;
   if (fu_kappa) *fu_kappa = plan->p.amgFu.kappa;
   if (ca_kappa) *ca_kappa = plan->p.amgC0.kappa;
+  return ST_OK;
+}
+
+int st_plan_cheb_intervals(const st_plan* plan, int which, double* out) {
+  if (!plan || !out || (which != 0 && which != 1)) return ST_EINVAL;
+  const st::Amg& a = which == 0 ? plan->p.amgFu : plan->p.amgC0;
+  const int nt = plan->p.blk.d.nt;
+  for (int k = 0; k < nt; ++k) {
+    const int s = int(a.cheb_alone.size()) >= 2 * nt ? k : 0;
+    out[2 * k] = a.cheb_alone[size_t(2 * s)];
+    out[2 * k + 1] = a.cheb_alone[size_t(2 * s + 1)];
+  }
   return ST_OK;
 }
 

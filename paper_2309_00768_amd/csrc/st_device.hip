@@ -92,6 +92,7 @@ struct Handle {
   DGroup J, JT, MA, Mj, Mp, FA, FAt, Fp, Fpt, KjA, KjAt, Bt, B, Zj, Zjt, ZAt, Mu, C1, C1t, MA64;
   DGroup Yv, Bv;                   // Y and B for the lower factors of P and P-tilde
   int variant = 0;                 // 0 P_T, 1 P-tilde, 2 P
+  int pint = 0, pint_deg = 1;      // Parareal iterations of the two P_T sweeps (0: forward substitution), coarse degree
   const void *dMA = nullptr, *dMj = nullptr, *dMp = nullptr;
   const double* mp_rowsum = nullptr;
   double msum = 1.0;              // 1^T M_p 1 (the area)
@@ -500,7 +501,8 @@ inline int sweep_launches(const Handle& H, int deg) {
 template <class T>
 void sweep_step_stencil(Ctx& c, Handle& H, DAmg& a, const StencilOp& A, const StencilOp* S1, int set1, double a1,
                         const T* y1, const StencilOp* S2, int set2, double a2, const T* y2, const T* q, T* x, int k,
-                        int deg, int role, bool guess = false, double g1 = 0.0, double g2 = 0.0) {
+                        int deg, int role, bool guess = false, double g1 = 0.0, double g2 = 0.0,
+                        const T* y3 = nullptr, double g3 = 0.0) {
   DLevel& L = a.lev[0];
   const int64_t rows = A.rows;
   T* r = static_cast<T*>(a.buf[2]);
@@ -531,6 +533,8 @@ void sweep_step_stencil(Ctx& c, Handle& H, DAmg& a, const StencilOp& A, const St
   ia.guess = guess ? 1 : 0;
   ia.g1 = g1;
   ia.g2 = g2;
+  ia.y3 = y3;
+  ia.g3 = g3;
   // Two lanes per row only for two-component operators (F_u,k and its coupling).
   auto two = [](const StencilOp* o) { return !o || (o->ncomp == 2 && !o->diag_comp); };
   const int lanes = H.step_lanes == 2 && two(&A) && two(S1) && two(S2) ? 2 : 1;
@@ -589,6 +593,112 @@ void sweep_step_stencil(Ctx& c, Handle& H, DAmg& a, const StencilOp& A, const St
     ca.dnew = d[i % 2];
     if (role == 1) emit(c, kKStCheb, grid, &k_st_cheb<T, 1>, ca);
     else emit(c, kKStCheb, grid, &k_st_cheb<T, 2>, ca);
+  }
+}
+
+// ====================================== parallel-in-time sweeps (Parareal) ===
+// The two sweeps of P_T^{-1} with K Parareal iterations instead of forward
+// substitution in time.  A slab step maps the earlier slabs to slab k,
+//   F_u: x^k = x^{k-1} + S_k(g^k - A_k x^{k-1}),  A_k = F_u,k - M_u/dt;
+//   C_A: y^k = p^k + S_k(s^k + C1_{k-1}/dt y^{k-1} - C2/dt^2 y^{k-2} - C0_k p^k),
+//        p^k = 2 y^{k-1} - y^{k-2} (y^0 for k = 1, 0 for k = 0),
+// with S_k Chebyshev-Jacobi on the diagonal block: the plan's degree (fine) or
+// the coarse degree (coarse).  Iteration j -> j+1:
+//   x_{j+1}^k = G_k(x_{j+1}^{<k}) + (F_k - G_k)(x_j^{<k}),
+// from the coarse sweep x_0.  The corrections F_k - G_k = (S^fine - S^coarse) r_k
+// of all slabs are computed together (SELL products and Chebyshev steps over
+// every slab in one launch each: the Chebyshev iterates are nested, so the
+// increments past the coarse degree are the difference); the coarse sweep runs
+// slab by slab with the stencil steps, the correction added to the predictor.
+template <class T>
+struct ParaBufs {
+  T* alt;    // the iterate not held in the output
+  T* corr;   // (S^fine - S^coarse) r per slab
+  T* acc;    // the first coarse-degree increments (discarded)
+  T* r;
+  T* d0;
+  T* d1;
+};
+
+template <class T>
+ParaBufs<T> para_bufs(Handle& H, const size_t* off) {
+  return ParaBufs<T>{scr<T>(H, off[0]), scr<T>(H, off[1]), scr<T>(H, off[2]),
+                     scr<T>(H, off[3]), scr<T>(H, off[4]), scr<T>(H, off[5])};
+}
+
+// corr = (S^fine - S^coarse) r over all nt slabs (r holds the slabs' residuals).
+template <class T>
+void para_correction(Ctx& c, DAmg& a, int nt, int deg_f, int deg_c, const ParaBufs<T>& pb) {
+  DLevel& L = a.lev[0];
+  const int64_t n = L.n;
+  FillArgs f{reinterpret_cast<double*>(pb.corr), int64_t((size_t(nt) * size_t(n) * sizeof(T) + 7) / 8), 0.0};
+  emit(c, kKFill, dim3(grid_for(f.n)), &k_fill, f);
+  T* d[2] = {pb.d0, pb.d1};
+  const int sstep = a.nsets > 1 ? 1 : 0;
+  const int64_t dstride = a.nsets > 1 ? n : 0;
+  for (int i = 0; i < deg_f; ++i)
+    cheb_launch<T>(c, L.A, nt, 0, sstep, static_cast<const T*>(L.dinv), dstride, a.alone_dev, 0, 0, nullptr, pb.r,
+                   i < deg_c ? pb.acc : pb.corr, d[(i + 1) % 2], d[i % 2], n, i == 0 ? 0 : 1, i, 0, 1);
+}
+
+// x = the F_u sweep of g (nt slabs) by K Parareal iterations.
+template <class T>
+void parareal_fu(Ctx& c, Handle& H, const T* g, T* x) {
+  const int nt = H.d.nt, nu = H.d.nu, K = H.pint, dc = H.pint_deg;
+  const double dt = H.dt;
+  const ParaBufs<T> pb = para_bufs<T>(H, H.L.pint_u);
+  auto buf = [&](int j) { return (j % 2) == (K % 2) ? x : pb.alt; };
+  auto at = [&](T* v, int k) { return v + int64_t(k) * nu; };
+  auto coarse_sweep = [&](T* y, bool corr) {
+    for (int k = 0; k < nt; ++k)
+      sweep_step_stencil<T>(c, H, H.amgFu, H.sFu, k >= 1 ? &H.sAu : nullptr, k, -1.0,
+                            k >= 1 ? at(y, k - 1) : at(pb.corr, 0), nullptr, 0, 0.0, nullptr, g + int64_t(k) * nu,
+                            at(y, k), k, dc, 1, corr || k >= 1, k >= 1 ? 1.0 : 0.0, 0.0,
+                            corr ? at(pb.corr, k) : nullptr, corr ? 1.0 : 0.0);
+  };
+  coarse_sweep(buf(0), false);
+  const DGroup& Fu = H.amgFu.lev[0].A;
+  for (int j = 0; j < K; ++j) {
+    const T* cur = buf(j);
+    // r^k = g^k - F_u,k x^{k-1} + (1/dt) M_u x^{k-1} (k >= 1), r^0 = g^0
+    Seg<T> sf = seg<T>(Fu, 0, 0, 1, cur, nu, -1, 1, nt, -1.0);
+    spmv<T, T>(c, Fu, nt, 1, &sf, g, nu, 1.0, pb.r, nu, kRoleSweep);
+    Seg<T> sm = seg<T>(H.Mu, 0, 0, 0, cur, nu, -1, 1, nt, 1.0 / dt);
+    spmv<T, T>(c, H.Mu, nt, 1, &sm, pb.r, nu, 1.0, pb.r, nu, kRoleSweep);
+    para_correction<T>(c, H.amgFu, nt, H.fu_deg, dc, pb);
+    coarse_sweep(buf(j + 1), true);
+  }
+}
+
+// y = the C_A sweep of s (nt slabs) by K Parareal iterations.
+template <class T>
+void parareal_ca(Ctx& c, Handle& H, const T* s, T* y) {
+  const int nt = H.d.nt, na = H.d.na, K = H.pint, dc = H.pint_deg;
+  const double dt = H.dt;
+  const ParaBufs<T> pb = para_bufs<T>(H, H.L.pint_a);
+  auto buf = [&](int j) { return (j % 2) == (K % 2) ? y : pb.alt; };
+  auto at = [&](T* v, int k) { return v + int64_t(k) * na; };
+  auto coarse_sweep = [&](T* v, bool corr) {
+    for (int k = 0; k < nt; ++k)
+      sweep_step_stencil<T>(c, H, H.amgC0, H.sC0, k >= 1 ? &H.sCP : nullptr, k, 1.0,
+                            k >= 1 ? at(v, k - 1) : at(pb.corr, 0), k >= 2 ? &H.sCQ : nullptr, k, 1.0,
+                            k >= 2 ? at(v, k - 2) : at(pb.corr, 0), s + int64_t(k) * na, at(v, k), k, dc, 2,
+                            corr || k >= 1, k >= 2 ? 2.0 : (k >= 1 ? 1.0 : 0.0), k >= 2 ? -1.0 : 0.0,
+                            corr ? at(pb.corr, k) : nullptr, corr ? 1.0 : 0.0);
+  };
+  coarse_sweep(buf(0), false);
+  const DGroup& C0 = H.amgC0.lev[0].A;
+  for (int j = 0; j < K; ++j) {
+    const T* cur = buf(j);
+    // r^k = s^k + (1/dt) C1_{k-1} y^{k-1} - (1/dt^2) C2 y^{k-2} - C0_k p^k
+    Seg<T> s1[2] = {seg<T>(H.C1, 0, -1, 1, cur, na, -1, 1, nt, 1.0 / dt),
+                    seg<T>(H.C1, 1, 0, 0, cur, na, -2, 2, nt, -1.0 / (dt * dt))};
+    spmv<T, T>(c, H.C1, nt, 2, s1, s, na, 1.0, pb.r, na, kRoleSweep);
+    Seg<T> s0[3] = {seg<T>(C0, 0, 0, 1, cur, na, -1, 2, nt, -2.0), seg<T>(C0, 0, 0, 1, cur, na, -2, 2, nt, 1.0),
+                    seg<T>(C0, 0, 0, 1, cur, na, -1, 1, std::min(2, nt), -1.0)};
+    spmv<T, T>(c, C0, nt, 3, s0, pb.r, na, 1.0, pb.r, na, kRoleSweep);
+    para_correction<T>(c, H.amgC0, nt, H.ca_deg, dc, pb);
+    coarse_sweep(buf(j + 1), true);
   }
 }
 
@@ -711,7 +821,17 @@ int precond_forward(Handle& H, const double* r, double* z, Ctx& c, Ctx& ca, cons
     fu_ops = int(tmp.size());
   }
   int tb = rec ? a_split + int(c.rec->size()) : 0;
-  for (int ch = 0; ch < nch; ++ch) {
+  if (H.pint > 0 && !rec) {
+    // both sweeps by Parareal over all slabs at once: y_A, then the current
+    // solves and the velocity right-hand side of every slab, then x_u
+    parareal_ca<T>(ca, H, sA, yA);
+    current_solve(c, 0, nt, mr2, md02, md12);
+    Seg<T> sg[3] = {seg<T>(H.Zj, 0, 0, 1, yj, nj, 0, 0, nt, -1.0), seg<T>(H.Zj, 1, 0, 1, yA, na, 0, 0, nt, -1.0),
+                    seg<T>(H.Zj, 2, 0, 0, xp, np, 0, 0, nt, 1.0)};
+    spmv<T, T>(c, H.Zj, nt, 3, sg, ru, nu, 1.0, yu, nu);
+    parareal_fu<T>(c, H, yu, xu);
+  }
+  for (int ch = 0; ch < nch && !(H.pint > 0 && !rec); ++ch) {
     const int k0 = cb[size_t(ch)], k1 = cb[size_t(ch) + 1], kc = k1 - k0;
     if (chain) {
       ChainArgs<T> cha;
@@ -1058,6 +1178,10 @@ int apply_precond(Handle& H, const double* r, double* z, Ctx& c, bool transpose)
   if (H.variant != 0) {
     if (transpose || c.recording()) return ST_EINVAL;
     return H.fp32 ? precond_variant<float>(H, r, z, c) : precond_variant<double>(H, r, z, c);
+  }
+  if (H.pint > 0) {   // Parareal sweeps: forward, step by step
+    if (transpose || c.recording()) return ST_EINVAL;
+    return H.fp32 ? precond_forward<float>(H, r, z, c, c) : precond_forward<double>(H, r, z, c, c);
   }
   if (!c.recording() && (transpose ? H.pipeline_t : H.pipeline)) return replay_precond(H, r, z, c.s, transpose);
   if (H.fp32)
@@ -2327,6 +2451,8 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
     H.C1t = mirror(base, P.C1t);
   }
   H.variant = P.variant;
+  H.pint = P.pint;
+  H.pint_deg = P.pint_deg;
   if (H.variant >= 1) H.Bv = mirror(base, P.Bv);
   if (H.variant == 2) H.Yv = mirror(base, P.Yv);
   H.mp_rowsum = at<double>(base, P.mp_rowsum.off);
@@ -2359,8 +2485,9 @@ int st_create(const st_plan* plan, void* ws, size_t ws_bytes, void* stream, st_h
   {
     int rc = ST_OK;
     try {
-      if (P.prob.single_stream == 0 && H.variant == 0) rc = build_pipeline(H);
-      if (rc == ST_OK && P.prob.autotune == 1) rc = autotune(H, s, P.prob.single_stream == 0 && H.variant == 0);
+      const bool recorded = P.prob.single_stream == 0 && H.variant == 0 && H.pint == 0;
+      if (recorded) rc = build_pipeline(H);
+      if (rc == ST_OK && P.prob.autotune == 1) rc = autotune(H, s, recorded);
     } catch (...) {
       rc = ST_ENOMEM;
     }
@@ -2475,7 +2602,7 @@ int st_apply_precond_noalloc(st_handle* h, const double* r, double* z, void* str
   using namespace st;
   if (!h || !r || !z || r == z) return ST_EINVAL;
   Handle& H = h->h;
-  if (H.variant != 0) return ST_EINVAL;
+  if (H.variant != 0 || H.pint != 0) return ST_EINVAL;
   const size_t need = H.L.end - H.L.pt_begin;
   if (need > ::kNoAllocScratchBytes) {
     std::fprintf(stderr,
@@ -2549,7 +2676,7 @@ int st_batch_create(st_handle* const* hs, int nsys, int restart, st_batch** out)
   for (int i = 0; i < nsys; ++i) {
     if (!hs[i]) return ST_EINVAL;
     if (m > hs[i]->h.max_restart) return ST_EINVAL;
-    if (hs[i]->h.variant != 0) return ST_EINVAL;
+    if (hs[i]->h.variant != 0 || hs[i]->h.pint != 0) return ST_EINVAL;
     if (hs[i]->h.fp32 != hs[0]->h.fp32) return ST_EINVAL;
     for (int k = 0; k < i; ++k)
       if (hs[k] == hs[i]) return ST_EINVAL;

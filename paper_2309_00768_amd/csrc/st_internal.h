@@ -193,6 +193,7 @@ struct Plan {
   int inner_iters = 40, mass_iters = 12, max_restart = 30, exact = 0;
   int fu_deg = 0, ca_deg = 0;     // > 0: Chebyshev alone of this degree; 0: AMG V-cycle
   int chunk = 8;                  // slabs per chunk of the C_A / F_u sweep pipeline
+  int pint = 0, pint_deg = 1;     // Parareal iterations of the two sweeps (0: forward substitution), coarse degree
   // J and J^T (FP64): segment 0 per-slab values, 1 shared, 2 previous/next slab coupling.
   SellGroup J, JT;
   // P_T pieces (precision per fp32).
@@ -224,6 +225,8 @@ struct WsLayout {
   size_t ra = 0, wA = 0, sA = 0, yA = 0, mr = 0, md0 = 0, md1 = 0, chr = 0, chd0 = 0, chd1 = 0;
   size_t mr2 = 0, md02 = 0, md12 = 0;           // mass-solve scratch of the second program
   size_t io = 0;                                // 2 pointers: input/output slots of a recorded P_T
+  size_t pint_u[6] = {0, 0, 0, 0, 0, 0};        // Parareal sweeps: other iterate, correction, coarse part,
+  size_t pint_a[6] = {0, 0, 0, 0, 0, 0};        // residual, two increments (F_u / C_A, Nt slabs each)
   std::vector<size_t> kp_lev, fu_lev, ca_lev;   // 6 vectors per level each
   size_t end = 0;
   // [pt_begin, end) holds only the preconditioner's scratch (psum onwards):

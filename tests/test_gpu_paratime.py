@@ -1,0 +1,113 @@
+"""Parallel-in-time sweeps inside P_T (Parareal over the slab steps of the F_u
+and C_A sweeps) on the GPU against the oracle, through the C ABI.
+
+* Converged fine solves (Chebyshev-Jacobi of degree 40 on F_u,k and 80 on C_A,k
+  in EXACT mode) and nt Parareal iterations: P_T^{-1} r equals the oracle's
+  exact-inner P_T^{-1} r of eq. (PT) block by block.
+* One and two iterations, coarse degree 1 and 2: P_T^{-1} r equals the oracle's
+  Parareal P_T^{-1} r with exact fine solves and the library's own
+  Chebyshev-Jacobi coarse solves (the plan's intervals, exported per slab).
+* Production inner solves in FP32: FGMRES with Parareal sweeps reaches a true
+  relative residual of 1e-8 (checked by the oracle); the iteration counts
+  against the sequential sweeps are reported.
+* The transposed and the allocation-free applies are rejected.
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import paratime
+from paper_2309_00768_amd import inputs
+from parity_util import assert_blocks
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+@functools.lru_cache(maxsize=None)
+def case(n, nt):
+    cfg = inputs.Config(f"pt{n}x{nt}", n, nt, 0.1, 100.0, 100.0)
+    ub, ab = inputs.state(cfg)
+    return cfg, ub, ab, oracle.system_from_config(cfg, ub, ab)
+
+
+def plan_of(cfg, ub, ab, **kw):
+    from paper_2309_00768_amd import binding
+    return binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, **kw)
+
+
+@pytest.mark.parametrize("n,nt", [(6, 5), (3, 4)])
+def test_parareal_with_nt_iterations_is_PT(n, nt):
+    say(f"[gpu] parareal sweeps, nt iterations, converged fine solves n={n} nt={nt}")
+    from paper_2309_00768_amd import binding
+    cfg, ub, ab, ref = case(n, nt)
+    plan = plan_of(cfg, ub, ab, inner="exact", fu_solver=40, ca_solver=80, time_parallel=nt)
+    sysg = binding.System(plan, "cuda:0")
+    r = np.random.default_rng(21).standard_normal(ref.N)
+    z = sysg.apply_precond(dev(r)).cpu().numpy()
+    assert_blocks(z, ref.apply_PT_inv(r), sysg.offsets, nt, 1e-10, "P_T^-1 parareal(nt)")
+
+
+@pytest.mark.parametrize("iters,coarse", [(1, 1), (2, 1), (1, 2)])
+@pytest.mark.parametrize("n,nt", [(6, 5), (3, 4)])
+def test_parareal_iterations_match_oracle(n, nt, iters, coarse):
+    say(f"[gpu] parareal sweeps vs oracle n={n} nt={nt} iterations={iters} coarse degree={coarse}")
+    from paper_2309_00768_amd import binding
+    cfg, ub, ab, ref = case(n, nt)
+    plan = plan_of(cfg, ub, ab, inner="exact", fu_solver=40, ca_solver=80, time_parallel=iters,
+                   time_coarse_degree=coarse)
+    st = paratime.SweepSteps(ref)
+    fu_c = st.cheb_fu(coarse, plan.cheb_intervals("Fu"))
+    ca_c = st.cheb_ca(coarse, plan.cheb_intervals("CA"))
+    sysg = binding.System(plan, "cuda:0")
+    r = np.random.default_rng(22).standard_normal(ref.N)
+    z = sysg.apply_precond(dev(r)).cpu().numpy()
+    z_ref = paratime.apply_PT_inv_parareal(ref, r, iters, fu_c, ca_c)
+    exact = ref.apply_PT_inv(r)
+    say(f"    distance to P_T^-1 r: {np.linalg.norm(z_ref - exact) / np.linalg.norm(exact):.2e}")
+    assert_blocks(z, z_ref, sysg.offsets, nt, 1e-9, f"P_T^-1 parareal({iters}, coarse {coarse})")
+
+
+@pytest.mark.parametrize("iters", [1, 2])
+def test_parareal_fgmres_production_fp32(iters):
+    say(f"[gpu] FGMRES with parareal sweeps, production FP32, iterations={iters}")
+    from paper_2309_00768_amd import binding
+    cfg, ub, ab, ref = case(8, 8)
+    b = inputs.rhs(cfg, 1)
+    its = {}
+    for k in (0, iters):
+        plan = plan_of(cfg, ub, ab, precision="fp32", time_parallel=k, single_stream=True)
+        fu, ca, _, _ = plan.solver_info()
+        sysg = binding.System(plan, "cuda:0")
+        x, info, rc, _ = sysg.solve(dev(b), rtol=1e-8, maxit=600)
+        its[k] = info.iterations
+        xh = x.cpu().numpy()
+        bp = ref.project_pressure(b)
+        res = np.linalg.norm(bp - ref.apply_J(xh)) / np.linalg.norm(bp)
+        say(f"    time_parallel={k} (degrees {fu}/{ca}): {info.iterations} its, oracle residual {res:.2e}")
+        assert rc == 0 and res <= 1.05e-8
+    say(f"    iterations: sequential {its[0]}, parareal({iters}) {its[iters]}")
+
+
+def test_parareal_rejects_transpose_and_noalloc():
+    from paper_2309_00768_amd import binding
+    cfg, ub, ab, ref = case(4, 3)
+    plan = plan_of(cfg, ub, ab, precision="fp32", time_parallel=1, fu_solver=4, ca_solver=4)
+    sysg = binding.System(plan, "cuda:0")
+    r = dev(np.random.default_rng(23).standard_normal(ref.N))
+    with pytest.raises(RuntimeError):
+        sysg.apply_precond(r, transpose=True)
+    with pytest.raises(RuntimeError):
+        sysg.apply_precond_noalloc(r, torch.empty_like(r))

@@ -127,3 +127,33 @@ def test_jacobian_layout_holds_every_entry():
         assert s % 64 == 0 and s >= n
     plan.close()
 
+
+
+def _plan_kw(n=4, nt=5, **kw):
+    cfg = inputs.Config("pa", n, nt, 0.1, 100.0, 100.0)
+    ub, ab = inputs.state(cfg)
+    return lambda **more: binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab,
+                                       precision="fp32", **{**kw, **more})
+
+
+@pytest.mark.parametrize("bad", [{"adjoint": True}, {"sweep_format": 1}, {"variant": "P"},
+                                 {"fu_solver": -1}, {"time_coarse_degree": 4}, {"time_coarse_degree": -1}])
+def test_parareal_sweeps_reject_what_they_cannot_run(bad):
+    """Parareal sweeps (time_parallel > 0) need P_T's forward stencil sweeps with
+    Chebyshev alone on both blocks, at degrees above the coarse degree (here the
+    chosen degrees are 4)."""
+    make = _plan_kw(fu_solver=4, ca_solver=4)
+    make(time_parallel=2).close()
+    with pytest.raises(RuntimeError):
+        make(time_parallel=2, **bad)
+
+
+def test_chebyshev_intervals_are_exported_per_slab():
+    plan = _plan_kw()(fu_solver=4, ca_solver=5)
+    for which in ("Fu", "CA"):
+        iv = plan.cheb_intervals(which)
+        assert iv.shape == (plan.nt, 2)
+        theta, delta = iv[:, 0], iv[:, 1]
+        # D^{-1} A of these blocks has a positive spectrum: 0 < theta - delta < theta + delta
+        assert np.all(delta > 0) and np.all(theta - delta > 0), iv
+    plan.close()
