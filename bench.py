@@ -28,13 +28,13 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of one J apply at the default workload from FETCH_SIZE / WRITE_SIZE
 # counter runs calibrated with a 1 GiB copy (profiles/pmc_cfg3_jacobian_fetch_write.md),
 # valid while the kernel source it measured is unchanged (digest of that source).
-JAC_COUNTERS = {"config": "cfg3", "j_slabs": 8, "source_sha256_16": "2863946ff1f01491", "traffic_bytes": 2.330e9}
+JAC_COUNTERS = {"config": "cfg3", "j_slabs": 8, "source_sha256_16": "9e73605d16ae5780", "traffic_bytes": 2.332e9}
 # The same for one launch of the paired sweep-step kernel at the default workload
 # (profiles/pmc_cfg3_sweep_step_fetch_write.md).
-SWEEP_COUNTERS = {"config": "cfg3", "source_sha256_16": "edf3e1f027282742", "traffic_bytes": 1.050e7}
+SWEEP_COUNTERS = {"config": "cfg3", "source_sha256_16": "17a2f7a3c39f8932", "traffic_bytes": 1.051e7}
 # rocprofv3 average duration of that kernel at the default workload without event sampling
 # (profiles/kstats_cfg3_fgmres_fp32_pipeline.md), valid for the same kernel source.
-SWEEP_ROCPROF = {"config": "cfg3", "source_sha256_16": "edf3e1f027282742", "avg_us": 4.159}
+SWEEP_ROCPROF = {"config": "cfg3", "source_sha256_16": "17a2f7a3c39f8932", "avg_us": 4.12}
 
 
 def jacobian_kernel_digest():
@@ -621,9 +621,10 @@ def main():
     if (args.config == JAC_COUNTERS["config"] and nv == JAC_COUNTERS["j_slabs"]
             and jacobian_kernel_digest() == JAC_COUNTERS["source_sha256_16"]):
         jac["traffic"] = JAC_COUNTERS["traffic_bytes"]
-    if profiled:
-        psec, pn, pseen = sys32.profile_read()
-        p_avg = psec / max(pn, 1)
+    psec, pn, pseen = sys32.profile_read() if profiled else (0.0, 0, 0)
+    if pn > 0:
+        # (no paired sweep step runs when the sweeps take V-cycles: then J is the kernel reported)
+        p_avg = psec / pn
         achieved = sweep_bytes / p_avg / 1e9
         traffic = None
         if (args.config == SWEEP_COUNTERS["config"] and sweep_kernel_digest() == SWEEP_COUNTERS["source_sha256_16"]):
