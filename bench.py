@@ -447,6 +447,8 @@ def main():
                     help="Parareal iterations for the two sweeps of P_T (0: forward substitution in time)")
     ap.add_argument("--time-coarse", type=int, default=1,
                     help="Chebyshev steps of the Parareal coarse propagator per slab")
+    ap.add_argument("--sweep-chunk", type=int, default=0,
+                    help="slabs per chunk of the recorded P_T pipeline (0: library default)")
     ap.add_argument("--single-stream", action="store_true",
                     help="P_T step by step in program order instead of the recorded two-program replay")
     ap.add_argument("--inner", choices=["auto", "vcycle"], default="auto",
@@ -519,6 +521,8 @@ def main():
         solver.update(time_parallel=args.time_parallel, time_coarse_degree=args.time_coarse)
     if args.single_stream:
         solver.update(single_stream=True)
+    if args.sweep_chunk > 0:
+        solver.update(sweep_chunk=args.sweep_chunk)
     plan32 = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp32", autotune=tune,
                           max_restart=m, sweep_lanes=args.sweep_lanes, variant=args.variant, **solver)
     N = plan32.ns * cfg.nt
