@@ -98,6 +98,18 @@ def _oracle_worker(cfg_name, nt_sample, seed, rtol, keep_x, barrier, queue):
                "x": x if keep_x else None})
 
 
+def _get_result(queue, procs, poll=10.0):
+    """The next worker result; raises if a worker ended without delivering one."""
+    import queue as q
+    while True:
+        try:
+            return queue.get(timeout=poll)
+        except q.Empty:
+            dead = [p.exitcode for p in procs if p.exitcode not in (None, 0)]
+            if dead:
+                raise RuntimeError(f"an oracle worker process failed (exit codes {dead})")
+
+
 def cpu_baseline(cfg, nt_sample, rtol, workers):
     """The oracle (exact inner solves, GMRES(30)) on the first `nt_sample` slabs of
     the same workload, in `workers` single-threaded processes at once, each with
@@ -119,7 +131,7 @@ def cpu_baseline(cfg, nt_sample, rtol, workers):
     try:
         for p in procs:
             p.start()
-        res = [queue.get() for _ in procs]
+        res = [_get_result(queue, procs) for _ in procs]
         for p in procs:
             p.join()
     finally:
@@ -142,6 +154,61 @@ def cpu_baseline(cfg, nt_sample, rtol, workers):
            "one_process_dof_iters_per_s": one,
            "setup_s_per_process": max(r["setup_s"] for r in res)}
     return out, r0["x"], r0["its"]
+
+
+def _oracle_batch_worker(index, rtol, timed, queue):
+    """The oracle on uneven-batch member `index`, single-threaded: x* by the
+    direct forward substitution in time (sparse LU of every slab Jacobian), then
+    (if timed) GMRES(30) + P_T with exact inner solves, timed after its setup."""
+    import oracle
+    from paper_2309_00768_amd import inputs
+    c = inputs.batch_configs()[index]
+    ub, ab = inputs.state(c)
+    sysm = oracle.system_from_config(c, ub, ab)
+    b = inputs.rhs(c, c.rhs_seeds[0])
+    xs = sysm.direct_solve(b)
+    its, t1, t2 = 0, None, None
+    if timed:
+        sysm.apply_PT_inv(b)            # factorisations (setup) outside the timed solve
+        t1 = time.perf_counter()
+        _, its, _ = oracle.solve_fgmres(sysm, b, rtol=rtol, maxit=2000)
+        t2 = time.perf_counter()
+    queue.put({"index": index, "N": sysm.N, "its": its, "t_start": t1, "t_end": t2, "x": xs})
+
+
+def cpu_baseline_batch(members, timed, rtol):
+    """The oracle on the given uneven-batch members, one single-threaded process
+    each, started before the GPU is touched: every member's direct solution x*,
+    and GMRES + P_T timed on the members in `timed`; value = their DOF-iterations
+    over the wall time from the common start of their solves to the last one's end."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    queue = ctx.Queue()
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in env:
+        os.environ[k] = "1"
+    procs = [ctx.Process(target=_oracle_batch_worker, args=(i, rtol, i in timed, queue)) for i in members]
+    try:
+        for p in procs:
+            p.start()
+        res = [_get_result(queue, procs) for _ in procs]
+        for p in procs:
+            p.join()
+    finally:
+        for k, v in env.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    tres = [r for r in res if r["t_start"] is not None]
+    t0, t1 = min(r["t_start"] for r in tres), max(r["t_end"] for r in tres)
+    dof_its = sum(r["N"] * r["its"] for r in tres)
+    out = {"value": dof_its / (t1 - t0), "unit": "DOF-iter/s", "cores": len(tres), "kind": "oracle",
+           "sample": f"oracle GMRES(30)+P_T with sparse-LU inner solves to {rtol:g} on uneven-batch member(s) "
+                     f"{sorted(timed)}, one single-threaded process each; {dof_its:.3g} DOF-iterations in "
+                     f"{t1 - t0:.1f} s",
+           "iterations": {r["index"]: r["its"] for r in tres}}
+    return out, {r["index"]: r["x"] for r in res}
 
 
 def probe_jacobian(cfg, ub, ab, b, dev, launches=5, copy_bytes=1 << 30):
@@ -192,7 +259,7 @@ def probe_sweeps(cfg, ub, ab, b, dev, applies=3, copy_bytes=1 << 30):
                       "copy_bytes_read": copy_bytes, "copy_bytes_written": copy_bytes}), flush=True)
 
 
-def bench_batch(args, dev):
+def bench_batch(args, dev, cpu=None):
     """Uneven batch: 16 systems (n in {16,...,96}, Nt in {16,...,256}, dt = 1/Nt,
     Re = S = 300), FP32 preconditioner, solved together in lockstep; a step is
     one batched solve of every member.  The same systems solved one at a time
@@ -234,6 +301,8 @@ def bench_batch(args, dev):
     budget = args.batch_budget
     chunk = min(240, budget)
 
+    final = {}
+
     def solve_all(label):
         total = [0] * len(rhs)
         status = [1] * len(rhs)
@@ -254,6 +323,7 @@ def bench_batch(args, dev):
                     status[i], res[i] = st, inf.true_rel_residual
                 if rc == 0:
                     break
+            final.update(zip(g, xs))
             log(f"  {label}: group {g}: {sum(total[i] for i in g)} member iterations, open: "
                 f"{[(k, f'{res[k]:.1e}') for k in g if status[k] != 0]}")
         return total, status, res
@@ -283,6 +353,12 @@ def bench_batch(args, dev):
         "launches_per_arnoldi_step": {"lockstep": lock, "one_at_a_time": sep},
         "lockstep_groups": groups,
     }
+    if cpu is not None:
+        out["cpu_baseline"] = cpu[0]
+        out["error_vs_oracle"] = {
+            str(i): float(np.linalg.norm(final[i].cpu().numpy() - xs) / np.linalg.norm(xs)) for i, xs in cpu[1].items()}
+        out["error_vs_oracle"]["reference"] = "the oracle's direct forward substitution in time (sparse LU per slab)"
+        log(f"error vs oracle x*: {out['error_vs_oracle']}")
     if not args.no_separate:
         # the same systems one at a time, same budget (each with its own recorded pipeline)
         torch.cuda.synchronize()
@@ -480,6 +556,16 @@ def main():
     from paper_2309_00768_amd import inputs
 
     cpu = None
+    if args.config == "cfg4" and not args.no_cpu:
+        # the oracle on the smallest members (n = 16), before anything touches the GPU
+        # (x* of every n = 16 member; GMRES timed on the shortest of them)
+        bc = inputs.batch_configs()
+        members = [i for i, c in enumerate(bc) if c.n == 16]
+        timed = [min(members, key=lambda i: bc[i].nt)]
+        log(f"cpu baseline (oracle, members {members}, GMRES timed on {timed}) ...")
+        t0 = time.perf_counter()
+        cpu = cpu_baseline_batch(members, timed, args.rtol)
+        log(f"cpu baseline done in {time.perf_counter() - t0:.1f} s: {cpu[0]['value']:.3g} DOF-iter/s")
     if args.config not in ("cfg4", "cfg5", "newton") and not args.no_cpu and args.probe is None:
         # before anything touches the GPU: the oracle's worker processes start fresh
         cfg = inputs.CONFIGS[args.config]
@@ -494,7 +580,7 @@ def main():
 
     dev = torch.device("cuda:0")
     if args.config == "cfg4":
-        bench_batch(args, dev)
+        bench_batch(args, dev, cpu)
         return
     if args.config == "cfg5":
         bench_adjoint(args, dev)
