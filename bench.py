@@ -536,7 +536,7 @@ def main():
                     help="preconditioner: P_T (default), P-tilde or the full P (step by step)")
     ap.add_argument("--timestep", action="store_true",
                     help="also solve the workload by sequential time stepping with P_{T,k} (one-slab systems)")
-    ap.add_argument("--profile-every", type=int, default=8,
+    ap.add_argument("--profile-every", type=int, default=32,
                     help="time every k-th launch of the paired sweep-step kernel with HIP events")
     ap.add_argument("--no-separate", action="store_true", help="cfg4: skip the one-at-a-time comparison")
     ap.add_argument("--batch-budget", type=int, default=960, help="cfg4: FGMRES iterations per member")

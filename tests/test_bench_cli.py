@@ -25,3 +25,24 @@ def test_reported_traffic_is_the_committed_counter_summary():
     assert m, "traffic line missing from the counter summary"
     assert abs(float(m.group(1)) * 1e9 - bench.JAC_COUNTERS["traffic_bytes"]) <= 1e6
     assert bench.JAC_COUNTERS["config"] == "cfg3"
+
+
+def test_reported_sweep_traffic_and_duration_are_the_committed_summaries():
+    """The paired sweep step's traffic and rocprofv3 duration that bench.py uses
+    are those of the committed summaries, for the kernel source they measured."""
+    text = open(os.path.join(REPO, "profiles", "pmc_cfg3_sweep_step_fetch_write.md")).read()
+    m = re.search(r"calibrated traffic per launch \| \*\*([0-9.]+) MB\*\*", text)
+    assert m, "traffic line missing from the sweep counter summary"
+    assert abs(float(m.group(1)) * 1e6 - bench.SWEEP_COUNTERS["traffic_bytes"]) <= 1e4
+    d = re.search(r"`bench.sweep_kernel_digest\(\)`\): `([0-9a-f]{16})`", text)
+    assert d and d.group(1) == bench.SWEEP_COUNTERS["source_sha256_16"]
+    stats = open(os.path.join(REPO, "profiles", "kstats_cfg3_fgmres_fp32_pipeline.md")).read()
+    row = re.search(r"BodyStCheb<float>, st::BodyStCheb<float> >.*?\| (\d+) \| ([0-9.]+) \| ([0-9.]+) \|", stats)
+    assert row and abs(float(row.group(3)) - bench.SWEEP_ROCPROF["avg_us"]) <= 0.005
+    assert bench.SWEEP_ROCPROF["source_sha256_16"] == bench.SWEEP_COUNTERS["source_sha256_16"]
+
+
+def test_committed_kernel_figures_match_the_current_sources():
+    """The counter and duration figures are the current kernels': their source digests match."""
+    assert bench.jacobian_kernel_digest() == bench.JAC_COUNTERS["source_sha256_16"]
+    assert bench.sweep_kernel_digest() == bench.SWEEP_COUNTERS["source_sha256_16"]
