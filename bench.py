@@ -530,6 +530,8 @@ def main():
     ap.add_argument("--inner", choices=["auto", "vcycle"], default="auto",
                     help="spatial solves of the F_u and C_A sweeps: automatic (Chebyshev-Jacobi alone at the "
                          "default workload) or one SA-AMG V(1,1) cycle per sweep step")
+    ap.add_argument("--inner-degrees", default="",
+                    help="F,C: Chebyshev-Jacobi degrees of the F_u and C_A sweep solves (default: the plan's choice)")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32",
                     help="newton: preconditioner precision of the corrections")
     ap.add_argument("--variant", choices=["PT", "Ptilde", "P"], default="PT",
@@ -603,6 +605,9 @@ def main():
     # spatial solves of the sweeps: the automatic choice (Chebyshev-Jacobi alone where it reaches the
     # target reduction), or one SA-AMG V(1,1) cycle per sweep step on F_u,k and C_A,k
     solver = {"fu_solver": -1, "ca_solver": -1} if args.inner == "vcycle" else {}
+    if args.inner_degrees:
+        fu_d, ca_d = (int(v) for v in args.inner_degrees.split(","))
+        solver.update(fu_solver=fu_d, ca_solver=ca_d)
     if args.time_parallel > 0:
         solver.update(time_parallel=args.time_parallel, time_coarse_degree=args.time_coarse)
     if args.single_stream:
