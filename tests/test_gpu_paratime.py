@@ -48,7 +48,7 @@ def plan_of(cfg, ub, ab, **kw):
     return binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, **kw)
 
 
-@pytest.mark.parametrize("n,nt", [(6, 5), (3, 4)])
+@pytest.mark.parametrize("n,nt", [(6, 5), (3, 4), (4, 2), (3, 1)])
 def test_parareal_with_nt_iterations_is_PT(n, nt):
     say(f"[gpu] parareal sweeps, nt iterations, converged fine solves n={n} nt={nt}")
     from paper_2309_00768_amd import binding
@@ -78,6 +78,26 @@ def test_parareal_iterations_match_oracle(n, nt, iters, coarse):
     exact = ref.apply_PT_inv(r)
     say(f"    distance to P_T^-1 r: {np.linalg.norm(z_ref - exact) / np.linalg.norm(exact):.2e}")
     assert_blocks(z, z_ref, sysg.offsets, nt, 1e-9, f"P_T^-1 parareal({iters}, coarse {coarse})")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_parareal_tiled_and_per_step_coarse_sweeps_agree(precision, tol):
+    """The coarse sweeps of the Parareal iterations through the tiled multi-step
+    solve (the correction entering its first step as a predictor term) give what
+    one launch per step gives (coarse degree 2, F_u grid 23 x 23)."""
+    say(f"[gpu] parareal coarse sweeps tiled vs per step {precision}")
+    from paper_2309_00768_amd import binding
+    cfg, ub, ab, ref = case(12, 6)
+    r = np.random.default_rng(24).standard_normal(ref.N)
+    out = []
+    for fuse in (False, True):
+        plan = plan_of(cfg, ub, ab, precision=precision, fu_solver=5, ca_solver=6, time_parallel=2,
+                       time_coarse_degree=2, sweep_fuse=fuse, sweep_chain=False)
+        sysg = binding.System(plan, "cuda:0")
+        out.append(sysg.apply_precond(dev(r)).cpu().numpy())
+    rel = np.linalg.norm(out[0] - out[1]) / np.linalg.norm(out[0])
+    say(f"    rel {rel:.1e}")
+    assert rel <= tol
 
 
 @pytest.mark.parametrize("iters", [1, 2])
