@@ -533,7 +533,8 @@ def main():
     ap.add_argument("--inner-degrees", default="",
                     help="F,C: Chebyshev-Jacobi degrees of the F_u and C_A sweep solves (default: the plan's choice)")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32",
-                    help="newton: preconditioner precision of the corrections")
+                    help="preconditioner precision of the timed solves (cfg1-cfg3; fp64 leaves out the second, "
+                         "all-FP64 comparison) and of the Newton corrections")
     ap.add_argument("--variant", choices=["PT", "Ptilde", "P"], default="PT",
                     help="preconditioner: P_T (default), P-tilde or the full P (step by step)")
     ap.add_argument("--timestep", action="store_true",
@@ -571,6 +572,7 @@ def main():
     if args.config not in ("cfg4", "cfg5", "newton") and not args.no_cpu and args.probe is None:
         # before anything touches the GPU: the oracle's worker processes start fresh
         cfg = inputs.CONFIGS[args.config]
+        args.cpu_slabs = min(args.cpu_slabs, cfg.nt)
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
         log(f"cpu baseline (oracle, {workers} processes, first {args.cpu_slabs} slabs) ...")
         t0 = time.perf_counter()
@@ -614,7 +616,9 @@ def main():
         solver.update(single_stream=True)
     if args.sweep_chunk > 0:
         solver.update(sweep_chunk=args.sweep_chunk)
-    plan32 = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp32", autotune=tune,
+    prec = args.precision
+    fp32 = prec == "fp32"
+    plan32 = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision=prec, autotune=tune,
                           max_restart=m, sweep_lanes=args.sweep_lanes, variant=args.variant, **solver)
     N = plan32.ns * cfg.nt
     jbytes, nnz_state, nnz_const = jacobian_bytes(plan32, cfg.nt, N)
@@ -627,9 +631,9 @@ def main():
                   f"{args.time_coarse} Chebyshev step(s) per slab), step by step")
     sys32 = binding.System(plan32, dev)
     plan32.close()
-    log(f"setup fp32 {time.perf_counter() - t0:.1f} s, N={N}, launches {sys32.tuning()}")
+    log(f"setup {prec} {time.perf_counter() - t0:.1f} s, N={N}, launches {sys32.tuning()}")
     sys64 = None
-    if not args.no_fp64:
+    if fp32 and not args.no_fp64:
         t0 = time.perf_counter()
         plan64 = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp64",
                               autotune=tune, max_restart=m, sweep_lanes=args.sweep_lanes, variant=args.variant,
@@ -668,21 +672,23 @@ def main():
     jac_n = sum(i.jacobian_calls for i in infos)
     jac_avg = jac_s / max(jac_n, 1)
     res = max(i.true_rel_residual for i in infos)
-    log(f"fp32 precond: {its / args.steps:.1f} its/solve, {elapsed / args.steps:.3f} s/solve, residual {res:.2e}")
+    log(f"{prec} precond: {its / args.steps:.1f} its/solve, {elapsed / args.steps:.3f} s/solve, residual {res:.2e}")
 
     out = {
         "metric": METRIC, "value": value, "unit": "DOF-iter/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32-precond/f64-krylov", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32-precond/f64-krylov" if fp32 else "f64",
+        "data": "synthetic",
         "config": {"workload": f"{cfg.name}: {cfg.n}x{cfg.n} Q2-Q1/Q1/Q1, Nt={cfg.nt}, dt={cfg.dt}, "
-                               f"Re=S={cfg.re:g}; FGMRES({m}) to {args.rtol:g}, {variant_name(args.variant)} in FP32: {inner}",
+                               f"Re=S={cfg.re:g}; FGMRES({m}) to {args.rtol:g}, {variant_name(args.variant)} in "
+                               f"{prec.upper()}: {inner}",
                    "N": N, "nt": cfg.nt, "n": cfg.n},
         "time_to_1e8_s": elapsed / args.steps if converged else None,
         "converged": converged,
         "fgmres_iters": its / args.steps,
         "true_rel_residual": res,
         "precond_share": sum(i.precond_seconds for i in infos) / elapsed,
-        "launch_choices": {"fp32": sys32.tuning(), "autotuned": tune},
+        "launch_choices": {prec: sys32.tuning(), "autotuned": tune},
     }
     x64 = None
     if sys64 is not None:
@@ -703,11 +709,12 @@ def main():
     # Roofline of the dominant kernel: the paired sweep-step kernel (one
     # Chebyshev-Jacobi step of an F_u,k solve and one of a C_A,k solve per
     # launch).  Algorithmic bytes per launch: every true nonzero of the two
-    # slab operators once (4 B in FP32) and 7 vector passes per row (r, x read
-    # and written; d_old, D^{-1} read; d_new written).
+    # slab operators once (4 B in FP32, 8 in FP64) and 7 vector passes per row
+    # (r, x read and written; d_old, D^{-1} read; d_new written).
     nnz_fu, nnz_ca = plan_nnz["Fu"], plan_nnz["C0"]
     nu, na = sys32.offsets[2] - sys32.offsets[0], sys32.offsets[5] - sys32.offsets[4]
-    sweep_bytes = 4 * (nnz_fu + nnz_ca) + 7 * 4 * (nu + na)
+    wb = 4 if fp32 else 8
+    sweep_bytes = wb * (nnz_fu + nnz_ca) + 7 * wb * (nu + na)
     jac = {"kernel": (f"k_spmv_slabs<{sys32.tuning()['j_slabs']}, 4> (space-time Jacobian apply)"),
            "bytes_per_launch": jbytes, "avg_launch_ms": jac_avg * 1e3, "launches": jac_n,
            "achieved_GBs": jbytes / jac_avg / 1e9, "frac": jbytes / jac_avg / 1e9 / HBM_PEAK_GBS,
@@ -722,16 +729,18 @@ def main():
         p_avg = psec / pn
         achieved = sweep_bytes / p_avg / 1e9
         traffic = None
-        if (args.config == SWEEP_COUNTERS["config"] and sweep_kernel_digest() == SWEEP_COUNTERS["source_sha256_16"]):
+        if (fp32 and args.config == SWEEP_COUNTERS["config"]
+                and sweep_kernel_digest() == SWEEP_COUNTERS["source_sha256_16"]):
             traffic = SWEEP_COUNTERS["traffic_bytes"]
         frac_rp = None
-        if (args.config == SWEEP_ROCPROF["config"] and sweep_kernel_digest() == SWEEP_ROCPROF["source_sha256_16"]):
+        if (fp32 and args.config == SWEEP_ROCPROF["config"]
+                and sweep_kernel_digest() == SWEEP_ROCPROF["source_sha256_16"]):
             frac_rp = sweep_bytes / (SWEEP_ROCPROF["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS
         out["roofline"] = {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "frac_rocprof": frac_rp,
-            "kernel": "k_two<BodyStCheb<float>, BodyStCheb<float>> (paired sweep step: one Chebyshev-Jacobi step "
-                      "of a C_A,k solve and one of an F_u,k solve)",
+            "kernel": f"k_two<BodyStCheb<{'float' if fp32 else 'double'}>, BodyStCheb<{'float' if fp32 else 'double'}>> "
+                      "(paired sweep step: one Chebyshev-Jacobi step of a C_A,k solve and one of an F_u,k solve)",
             "bytes_per_launch": sweep_bytes, "avg_launch_ms": p_avg * 1e3, "launches_timed": pn,
             "launches": pseen, "share_of_solve_time": pseen * p_avg / elapsed,
             "nnz_Fu_per_slab": nnz_fu, "nnz_CA_per_slab": nnz_ca, "rows_u": nu, "rows_A": na,
@@ -772,7 +781,7 @@ def main():
         def err(xg):
             return None if xg is None else float(np.linalg.norm(xg[:nk].cpu().numpy() - ref) / np.linalg.norm(ref))
         out["error_vs_oracle"] = {
-            "fp32_precond": err(x32), "fp64_precond": err(x64),
+            f"{prec}_precond": err(x32), **({"fp64_precond": err(x64)} if fp32 else {}),
             "reference": f"the oracle's solution of the first {k} slabs (GMRES to {args.cpu_rtol:g} with exact "
                          f"inner solves, {its_cpu} iterations); J is block lower-bidiagonal in time, so it is the "
                          f"full system's x* on those slabs"}
