@@ -34,7 +34,7 @@ JAC_COUNTERS = {"config": "cfg3", "j_slabs": 8, "source_sha256_16": "9e73605d16a
 SWEEP_COUNTERS = {"config": "cfg3", "source_sha256_16": "17a2f7a3c39f8932", "traffic_bytes": 1.051e7}
 # rocprofv3 average duration of that kernel at the default workload without event sampling
 # (profiles/kstats_cfg3_fgmres_fp32_pipeline.md), valid for the same kernel source.
-SWEEP_ROCPROF = {"config": "cfg3", "source_sha256_16": "17a2f7a3c39f8932", "avg_us": 4.12}
+SWEEP_ROCPROF = {"config": "cfg3", "source_sha256_16": "17a2f7a3c39f8932", "avg_us": 4.13}
 
 
 def jacobian_kernel_digest():
@@ -56,6 +56,11 @@ def sweep_kernel_digest():
 
 GROUPING = {"all": "every member in one lockstep batch", "mesh": "one lockstep batch per mesh size",
             "split": "members with n < 64 in one lockstep batch, the others one at a time"}
+
+
+def orth_name(orth, m, N):
+    delayed = orth == "delayed" or (orth == "auto" and (m > 64 or N >= 1 << 20))
+    return "CGS2 with delayed reorthogonalisation" if delayed else "CGS2"
 
 
 def variant_name(v):
@@ -511,6 +516,9 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=1000, help="FGMRES iteration cap of a solve (cfg3 workloads)")
     ap.add_argument("--restart", type=int, default=30, help="FGMRES restart length m (cfg3 workloads)")
+    ap.add_argument("--orth", choices=["auto", "cgs2", "delayed"], default="auto",
+                    help="Gram-Schmidt of the Arnoldi steps (auto: delayed reorthogonalisation above restart 64 "
+                         "or from 2^20 unknowns)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-slabs", type=int, default=16)
@@ -647,7 +655,7 @@ def main():
     statuses = []
 
     def solve(sysg):
-        _, info, rc, _ = sysg.solve(bt, x, rtol=args.rtol, restart=m, maxit=args.maxit)
+        _, info, rc, _ = sysg.solve(bt, x, rtol=args.rtol, restart=m, maxit=args.maxit, orth=args.orth)
         if rc < 0:
             raise RuntimeError(f"solve failed: status {rc}")
         statuses.append(rc)
@@ -680,7 +688,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32-precond/f64-krylov" if fp32 else "f64",
         "data": "synthetic",
         "config": {"workload": f"{cfg.name}: {cfg.n}x{cfg.n} Q2-Q1/Q1/Q1, Nt={cfg.nt}, dt={cfg.dt}, "
-                               f"Re=S={cfg.re:g}; FGMRES({m}) to {args.rtol:g}, {variant_name(args.variant)} in "
+                               f"Re=S={cfg.re:g}; FGMRES({m}, {orth_name(args.orth, m, N)}) to {args.rtol:g}, {variant_name(args.variant)} in "
                                f"{prec.upper()}: {inner}",
                    "N": N, "nt": cfg.nt, "n": cfg.n},
         "time_to_1e8_s": elapsed / args.steps if converged else None,

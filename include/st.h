@@ -175,6 +175,20 @@ typedef struct st_opts {
   int x0_given;       /* 1: x holds the initial guess; 0: start from zero     */
   int history_len;    /* capacity of `history` (may be 0)                     */
   double* history;    /* host; estimated relative residual per iteration      */
+  int orth;           /* Gram-Schmidt of the Arnoldi steps (st_fgmres_solve,
+                         st_adjoint_solve, the time-stepping and Newton solves;
+                         a batch takes 1 and rejects 2):
+                         0: automatic, 2 when restart > 64 or N >= 2^20
+                            (bandwidth-bound basis reads), else 1;
+                         1: classical Gram-Schmidt with a second pass (CGS2),
+                            four reads of the basis per step;
+                         2: CGS2 with the second pass of each direction delayed
+                            to the next step and fused with that step's first
+                            pass: two reads of the basis per step.  Each column
+                            of the Hessenberg matrix completes one step later,
+                            so a solve that stops inside a cycle has applied
+                            P_T^{-1} and J once more than it counts
+                            iterations.  Other values: ST_EINVAL.           */
 } st_opts;
 
 typedef struct st_info {

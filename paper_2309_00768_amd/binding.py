@@ -41,10 +41,14 @@ class StProblem(ctypes.Structure):
     ]
 
 
+ORTH = {"auto": 0, "cgs2": 1, "delayed": 2}
+
+
 class StOpts(ctypes.Structure):
     _fields_ = [
         ("restart", ctypes.c_int), ("maxit", ctypes.c_int), ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
         ("x0_given", ctypes.c_int), ("history_len", ctypes.c_int), ("history", ctypes.POINTER(ctypes.c_double)),
+        ("orth", ctypes.c_int),
     ]
 
 
@@ -344,12 +348,15 @@ class System:
         return y
 
     def solve(self, b, x=None, restart=30, rtol=1e-8, atol=0.0, maxit=1000, x0=False, history=0,
-              adjoint=False, stream=None):
-        """FGMRES on J x = b (or the adjoint J^T x = b).  Returns (x, info, status, history)."""
+              adjoint=False, stream=None, orth="auto"):
+        """FGMRES on J x = b (or the adjoint J^T x = b).  Returns (x, info, status, history).
+        ``orth``: Gram-Schmidt of the Arnoldi steps, "auto", "cgs2" or "delayed" (``st_opts.orth``;
+        automatic: delayed reorthogonalisation above restart 64 or from 2^20 unknowns)."""
         import torch
         x = torch.zeros_like(b) if x is None else x
         o = StOpts()
         o.restart, o.maxit, o.rtol, o.atol, o.x0_given = restart, maxit, rtol, atol, int(x0)
+        o.orth = ORTH[orth]
         hist = np.zeros(max(history, 0))
         o.history_len = hist.size
         o.history = _dptr(hist) if hist.size else ctypes.POINTER(ctypes.c_double)()
@@ -540,8 +547,10 @@ class Batch:
         _check(lib().st_batch_launch_counts(self.ptr, ctypes.byref(a), ctypes.byref(b)), "launch_counts")
         return a.value, b.value
 
-    def solve(self, bs, xs=None, rtol=1e-8, atol=0.0, maxit=1000, x0=False, history=0, stream=None):
-        """Solves every member; returns (xs, infos, statuses, rc, histories)."""
+    def solve(self, bs, xs=None, rtol=1e-8, atol=0.0, maxit=1000, x0=False, history=0, stream=None,
+              orth="auto"):
+        """Solves every member; returns (xs, infos, statuses, rc, histories).  The
+        lockstep steps use CGS2 ("auto" or "cgs2"; "delayed" is rejected)."""
         import torch
         n = len(self.systems)
         assert len(bs) == n
@@ -553,6 +562,7 @@ class Batch:
         xarr = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
         o = StOpts()
         o.restart, o.maxit, o.rtol, o.atol, o.x0_given = self.restart, maxit, rtol, atol, int(x0)
+        o.orth = ORTH[orth]
         hist = np.zeros((n, max(history, 0)))
         o.history_len = hist.shape[1]
         o.history = _dptr(hist) if hist.size else ctypes.POINTER(ctypes.c_double)()

@@ -216,6 +216,176 @@ __device__ inline void combine_body(const CombineArgs& a, int bx, int gx) {
   }
 }
 
+// ------------------------------- Arnoldi with delayed reorthogonalisation ---
+// Step j of a cycle holds u_j, the newest basis direction after one classical
+// Gram-Schmidt pass, in V_j, and w = J z_j with z_j = P^{-1} u_j.  One read of
+// the finished basis Q = V_0..V_{j-1} gives both a = Q^T u_j (the second pass
+// of u_j) and b = Q^T w (the first pass of w); a second read forms
+// q~ = u_j - Q a and w'' = w - Q b with ||q~||^2 and q~ . w''.  Then
+// q_j = q~ / ||q~|| and u_{j+1} = w'' - (q_j . w'') q_j.  Every direction
+// still gets two full passes, as in CGS2, but the basis is read twice per
+// step instead of four times.
+//
+// The pending vector is kept at unit scale: u_{j+1} is stored as
+// u_{j+1} / s_{j+1} with s_{j+1}^2 = ||w''||^2 - c^2 (its norm; ||w''|| where
+// that difference loses too much to cancellation, any positive scale being
+// exact), and s enters the entries that complete its Hessenberg column.
+// Unscaled, the pending vector grows or shrinks by the subdiagonal entries
+// step after step and leaves the floating-point range on long restarts
+// when ||J P_T^{-1}|| is far from 1.
+
+constexpr int kDotGroup = 16;   // basis vectors per workgroup of the dot pass
+
+// partial[(2i + 0) * gx + bx] = rows of V_i . u, partial[(2i + 1) * gx + bx] =
+// rows of V_i . w (0 without w), i in the workgroup's group of kDotGroup.
+struct Mdot2Args {
+  const double* V;
+  int64_t N;
+  int nv;
+  const double* u;
+  const double* w;   // nullptr: only V^T u
+  double* partial;
+};
+
+__device__ inline void mdot2_body(const Mdot2Args& a, int bx, int grp, int gx) {
+  __shared__ double part[2 * kDotGroup][kBlock / kWave];
+  const int i0 = grp * kDotGroup;
+  const int cnt = min(kDotGroup, a.nv - i0);
+  const bool hw = a.w != nullptr;
+  double au[kDotGroup], aw[kDotGroup];
+#pragma unroll
+  for (int g = 0; g < kDotGroup; ++g) au[g] = aw[g] = 0.0;
+  const double* v0 = a.V + int64_t(i0) * a.N;
+  for (int64_t r = bx * int64_t(kBlock) + threadIdx.x; r < a.N; r += int64_t(gx) * kBlock) {
+    const double ur = a.u[r];
+    const double wr = hw ? a.w[r] : 0.0;
+#pragma unroll
+    for (int g = 0; g < kDotGroup; ++g) {
+      if (g < cnt) {
+        const double v = v0[int64_t(g) * a.N + r];
+        au[g] += v * ur;
+        aw[g] += v * wr;
+      }
+    }
+  }
+  const int wv = threadIdx.x / kWave, l = threadIdx.x % kWave;
+#pragma unroll
+  for (int g = 0; g < kDotGroup; ++g) {
+    const double su = wave_sum(au[g]), sw = wave_sum(aw[g]);
+    if (l == 0) {
+      part[2 * g][wv] = su;
+      part[2 * g + 1][wv] = sw;
+    }
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < 2 * cnt) {
+    double acc = 0.0;
+    for (int k = 0; k < kBlock / kWave; ++k) acc += part[t][k];
+    a.partial[int64_t(2 * i0 + t) * gx + bx] = acc;
+  }
+}
+
+// q~ = u - sum_i a_i V_i in place of u, w'' = w - sum_i b_i V_i into wout
+// (a_i = dots[2i], b_i = dots[2i + 1], i < nv); partial[k * gx + bx] = rows of
+// ||q~||^2, q~ . w'' and ||w''||^2 for k = 0, 1, 2 (the last two 0 without w).
+struct UpdDelayedArgs {
+  const double* V;
+  int64_t N;
+  int nv;
+  const double* dots;
+  double* u;
+  const double* w;   // nullptr on the closing pass of a cycle
+  double* wout;
+  double* partial;
+};
+
+__device__ inline void upd_delayed_body(const UpdDelayedArgs& a, int bx, int gx) {
+  double qq = 0.0, qw = 0.0, ww = 0.0;
+  const bool hw = a.w != nullptr;
+  for (int64_t r = bx * int64_t(kBlock) + threadIdx.x; r < a.N; r += int64_t(gx) * kBlock) {
+    double su = 0.0, sw = 0.0;
+#pragma unroll 4
+    for (int i = 0; i < a.nv; ++i) {
+      const double v = a.V[int64_t(i) * a.N + r];
+      su += a.dots[2 * i] * v;
+      sw += a.dots[2 * i + 1] * v;
+    }
+    const double q = a.u[r] - su;
+    a.u[r] = q;
+    qq += q * q;
+    if (hw) {
+      const double w2 = a.w[r] - sw;
+      a.wout[r] = w2;
+      qw += q * w2;
+      ww += w2 * w2;
+    }
+  }
+  qq = block_sum(qq);
+  qw = block_sum(qw);
+  ww = block_sum(ww);
+  if (threadIdx.x == 0) {
+    a.partial[bx] = qq;
+    a.partial[int64_t(gx) + bx] = qw;
+    a.partial[2 * int64_t(gx) + bx] = ww;
+  }
+}
+
+// Hessenberg entries of step j from the reduced sums nrm = (||q~||^2, q~ . w'',
+// ||w''||^2): nu = ||q~|| (1 at j = 0, where V_0 is already normalised) and
+// c = q~ . w'' / nu.  With s = s_j = sm[8 + j % 2], the scale of the pending
+// vector held in V_j, column j - 1 gains s a and H[j, j-1] = s nu; column j gets
+// its first-pass coefficients b and H[j, j] = c (has_w), and s_{j+1} goes to
+// sm[8 + (j + 1) % 2].  sm[1] = s nu, sm[3] = nu, sm[4] = c.  One workgroup.
+struct FinDelayedArgs {
+  const double* dots;
+  const double* nrm;
+  double* H;
+  int ldh, j, has_w;
+  double* sm;
+};
+
+__device__ inline void fin_delayed_body(const FinDelayedArgs& a) {
+  const int j = a.j;
+  const double nu = j == 0 ? 1.0 : std::sqrt(fmax(a.nrm[0], 0.0));
+  const double s = j == 0 ? 1.0 : a.sm[8 + (j & 1)];
+  for (int i = threadIdx.x; i < j; i += blockDim.x) {
+    a.H[int64_t(j - 1) * a.ldh + i] += s * a.dots[2 * i];
+    if (a.has_w) a.H[int64_t(j) * a.ldh + i] = a.dots[2 * i + 1];
+  }
+  if (threadIdx.x == 0) {
+    const double c = nu > 0.0 ? a.nrm[1] / nu : 0.0;
+    if (j > 0) a.H[int64_t(j - 1) * a.ldh + j] = s * nu;
+    if (a.has_w) {
+      a.H[int64_t(j) * a.ldh + j] = c;
+      const double ww = fmax(a.nrm[2], 0.0), s2 = ww - c * c;
+      a.sm[8 + ((j + 1) & 1)] = s2 > 1e-8 * ww ? std::sqrt(s2) : std::sqrt(ww);
+    }
+    a.sm[1] = s * nu;
+    a.sm[3] = nu;
+    a.sm[4] = c;
+  }
+}
+
+// q_j = q~ / nu in place (zero if nu is zero), then wn = (wn - c q_j) / s_{j+1}
+// (nu = sm[3], c = sm[4], s_{j+1} = *snew; zero if it is zero).
+struct NextDelayedArgs {
+  double* q;
+  double* wn;
+  int64_t N;
+  const double* sm;
+  const double* snew;
+};
+
+__device__ inline void next_delayed_body(const NextDelayedArgs& a, int bx, int gx) {
+  const double nu = a.sm[3], c = a.sm[4], s = *a.snew;
+  for (int64_t r = bx * int64_t(kBlock) + threadIdx.x; r < a.N; r += int64_t(gx) * kBlock) {
+    const double q = nu != 0.0 ? a.q[r] / nu : 0.0;
+    a.q[r] = q;
+    a.wn[r] = s != 0.0 ? (a.wn[r] - c * q) / s : 0.0;
+  }
+}
+
 // dst = src / *nrm (zero if the norm is zero)
 struct ScaleArgs {
   double* dst;
@@ -342,6 +512,14 @@ __global__ __launch_bounds__(kBlock) void k_mdot_partial(MdotArgs a) {
 }
 __global__ __launch_bounds__(kBlock) void k_reduce(ReduceArgs a) { reduce_body(a, blockIdx.x); }
 __global__ __launch_bounds__(kBlock) void k_combine(CombineArgs a) { combine_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kBlock) void k_mdot2(Mdot2Args a) { mdot2_body(a, blockIdx.x, blockIdx.y, gridDim.x); }
+__global__ __launch_bounds__(kBlock) void k_upd_delayed(UpdDelayedArgs a) {
+  upd_delayed_body(a, blockIdx.x, gridDim.x);
+}
+__global__ __launch_bounds__(kBlock) void k_fin_delayed(FinDelayedArgs a) { fin_delayed_body(a); }
+__global__ __launch_bounds__(kBlock) void k_next_delayed(NextDelayedArgs a) {
+  next_delayed_body(a, blockIdx.x, gridDim.x);
+}
 __global__ __launch_bounds__(kBlock) void k_scale(ScaleArgs a) { scale_body(a, blockIdx.x, gridDim.x); }
 __global__ __launch_bounds__(kBlock) void k_givens(GivensArgs a) { givens_body(a); }
 __global__ __launch_bounds__(kBlock) void k_trisolve(TrisolveArgs a) { trisolve_body(a); }

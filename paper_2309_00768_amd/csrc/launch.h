@@ -49,6 +49,10 @@ enum Kind : int {
   kKSpmvSlabs4,     // SpmvSlabsArgs (J apply, 4 slabs per wavefront)
   kKSpmvSlabs8,     // SpmvSlabsArgs (J apply, 8 slabs per wavefront)
   kKStSolve,        // StSolveArgs<T>
+  kKMdot2,          // Mdot2Args (Arnoldi with delayed reorthogonalisation)
+  kKUpdDelayed,     // UpdDelayedArgs
+  kKFinDelayed,     // FinDelayedArgs
+  kKNextDelayed,    // NextDelayedArgs
   kKNumKinds
 };
 
@@ -280,6 +284,22 @@ template <class T> struct KB<kKSpmvSlabs8, T> {
     int bx, by;
     if (slabs_block(a, b, bx, by)) spmv_slabs_body<8>(a, bx, by);
   }
+};
+template <class T> struct KB<kKMdot2, T> {
+  using Args = Mdot2Args;
+  __device__ static void run(const Args& a, int b, int gx) { mdot2_body(a, b % gx, b / gx, gx); }
+};
+template <class T> struct KB<kKUpdDelayed, T> {
+  using Args = UpdDelayedArgs;
+  __device__ static void run(const Args& a, int b, int gx) { upd_delayed_body(a, b, gx); }
+};
+template <class T> struct KB<kKFinDelayed, T> {
+  using Args = FinDelayedArgs;
+  __device__ static void run(const Args& a, int, int) { fin_delayed_body(a); }
+};
+template <class T> struct KB<kKNextDelayed, T> {
+  using Args = NextDelayedArgs;
+  __device__ static void run(const Args& a, int b, int gx) { next_delayed_body(a, b, gx); }
 };
 template <class T> struct KB<kKSetPtrs, T> {
   using Args = SetPtrsArgs;

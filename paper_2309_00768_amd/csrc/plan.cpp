@@ -132,8 +132,10 @@ WsLayout workspace_layout(const Plan& P) {
   L.w = take(8 * N);
   L.r = take(8 * N);
   L.hess = take(8 * size_t(m + 1) * (m + 1));
-  L.small = take(8 * 64 + 8 * 4 * size_t(m + 2));
-  L.partial = take(8 * size_t(kPartialBlocks) * (m + 2));
+  // small: 64 scalars, g, cs, sn, y (m + 2 each), then the 2m dot products of
+  // the Arnoldi step with delayed reorthogonalisation
+  L.small = take(8 * 64 + 8 * 4 * size_t(m + 2) + 8 * 2 * size_t(m + 1));
+  L.partial = take(8 * size_t(kPartialBlocks) * (2 * size_t(m) + 2));
   L.psum = take(8 * size_t(d.nt) * 2);
   L.pt_begin = L.psum;
   const size_t nt = d.nt;

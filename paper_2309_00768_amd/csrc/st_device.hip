@@ -1231,6 +1231,7 @@ struct Krylov {
   int m = 0, ldh = 0;
   double *V = nullptr, *Z = nullptr, *w = nullptr, *bp = nullptr, *Hc = nullptr, *sm = nullptr;
   double *g = nullptr, *cs = nullptr, *sn = nullptr, *y = nullptr, *psum = nullptr, *partial = nullptr;
+  double* dots = nullptr;   // 2m dot products of a delayed-reorthogonalisation step
   const double** rslot = nullptr;   // input/output slots of the recorded preconditioner
   double** zslot = nullptr;
 };
@@ -1252,6 +1253,7 @@ Krylov krylov(Handle& H, int m) {
   K.cs = K.g + (m + 2);
   K.sn = K.cs + (m + 2);
   K.y = K.sn + (m + 2);
+  K.dots = at<double>(B, L.small) + 64 + 4 * (H.max_restart + 2);
   K.psum = at<double>(B, L.psum);
   K.partial = at<double>(B, L.partial);
   K.rslot = at<const double*>(B, L.io);
@@ -1318,6 +1320,39 @@ void emit_arnoldi(Ctx& c, const Krylov& K, int j) {
   }
 }
 
+// Arnoldi step j with delayed reorthogonalisation (see the kernels): after
+// w = J z_j, the dot pass over V_0..V_{j-1} with u_j = V_j and w, then the
+// update pass writing q~ over V_j and w'' to V_{j+1}, and the Hessenberg
+// entries (column j-1 completed, column j's first pass).  Without w (the
+// closing pass of a cycle) only u_j = V_j is reorthogonalised and measured.
+void emit_delayed_passes(Ctx& c, const Krylov& K, int j, const double* w) {
+  double* u = K.V + int64_t(j) * K.N;
+  if (j > 0) {
+    Mdot2Args a{K.V, K.N, j, u, w, K.partial};
+    emit(c, kKMdot2, dim3(kPartialBlocks, (j + kDotGroup - 1) / kDotGroup), &k_mdot2, a);
+    ReduceArgs r{K.partial, kPartialBlocks, K.dots, 0, nullptr};
+    emit(c, kKReduce, dim3(2 * j), &k_reduce, r);
+  }
+  UpdDelayedArgs up{K.V, K.N, j, K.dots, u, w, w ? K.V + int64_t(j + 1) * K.N : nullptr, K.partial};
+  emit(c, kKUpdDelayed, dim3(kPartialBlocks), &k_upd_delayed, up);
+  ReduceArgs r2{K.partial, kPartialBlocks, K.sm + 5, 0, nullptr};
+  emit(c, kKReduce, dim3(3), &k_reduce, r2);
+  FinDelayedArgs f{K.dots, K.sm + 5, K.Hc, K.ldh, j, w ? 1 : 0, K.sm};
+  emit(c, kKFinDelayed, dim3(1), &k_fin_delayed, f);
+}
+
+// Givens update of the completed column j (estimate in sm[2]).
+void emit_givens(Ctx& c, const Krylov& K, int j) {
+  GivensArgs gv{K.Hc, j, K.ldh, K.g, K.cs, K.sn, K.sm + 2};
+  emit(c, kKGivens, dim3(1), &k_givens, gv);
+}
+
+// q_j = q~ / nu over V_j, then u_{j+1} = (w'' - c q_j) / s_{j+1} in V_{j+1}.
+void emit_delayed_next(Ctx& c, const Krylov& K, int j) {
+  NextDelayedArgs a{K.V + int64_t(j) * K.N, K.V + int64_t(j + 1) * K.N, K.N, K.sm, K.sm + 8 + ((j + 1) & 1)};
+  emit(c, kKNextDelayed, dim3(grid_for(K.N)), &k_next_delayed, a);
+}
+
 // x += Z y with y from the rotated Hessenberg system of size mused.
 void emit_cycle_end(Ctx& c, const Krylov& K, double* x, int mused) {
   TrisolveArgs ts{K.Hc, mused, K.ldh, K.g, K.y};
@@ -1371,7 +1406,9 @@ int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* 
   if (m > H.max_restart) return ST_EINVAL;
   if (adjoint && !H.adjoint) return ST_EINVAL;
   const int maxit = o->maxit > 0 ? o->maxit : 1000;
+  if (o->orth < 0 || o->orth > 2) return ST_EINVAL;
   const Krylov K = krylov(H, m);
+  const bool delayed = o->orth == 2 || (o->orth == 0 && (m > kDelayedFrom || K.N >= kDelayedRows));
   Ctx c{s, nullptr};
   double* hs = H.host_small;
   EventPairs evs(s), jevs(s);
@@ -1424,18 +1461,41 @@ int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* 
     if (o->history && its < o->history_len && its == 0) o->history[0] = beta / bnorm;
     emit_cycle_head(c, K);
     int mused = 0;
-    for (int j = 0; j < m; ++j) {
-      precond(K.V + int64_t(j) * K.N, K.Z + int64_t(j) * K.N);
-      jac(K.Z + int64_t(j) * K.N, K.w, 1.0, nullptr);
-      emit_arnoldi(c, K, j);
-      rc = fetch(K.sm, 3);
-      if (rc) return rc;
+    // a finished Hessenberg column: count it, record and test the estimate
+    auto column_done = [&](int cols, bool& stop) -> int {
+      const int rc2 = fetch(K.sm, 3);
+      if (rc2) return rc2;
       ++its;
-      mused = j + 1;
+      mused = cols;
       const double est = hs[2];
       if (o->history && its < o->history_len) o->history[its] = est / bnorm;
       if (!std::isfinite(est) || !std::isfinite(hs[1])) return ST_EBREAKDOWN;
-      if (est <= tol || its >= maxit) break;
+      stop = est <= tol || its >= maxit;
+      return ST_OK;
+    };
+    bool stop = false;
+    for (int j = 0; j < m && !stop; ++j) {
+      precond(K.V + int64_t(j) * K.N, K.Z + int64_t(j) * K.N);
+      jac(K.Z + int64_t(j) * K.N, K.w, 1.0, nullptr);
+      if (!delayed) {
+        emit_arnoldi(c, K, j);
+        if ((rc = column_done(j + 1, stop))) return rc;
+        continue;
+      }
+      // column j-1 completes in this step; z_j is unused if the solve stops here
+      emit_delayed_passes(c, K, j, K.w);
+      if (j > 0) {
+        emit_givens(c, K, j - 1);
+        if ((rc = column_done(j, stop))) return rc;
+        if (stop) break;
+      }
+      emit_delayed_next(c, K, j);
+    }
+    if (delayed && !stop) {
+      // closing pass: u_m against V_0..V_{m-1} completes column m-1
+      emit_delayed_passes(c, K, m, nullptr);
+      emit_givens(c, K, m - 1);
+      if ((rc = column_done(m, stop))) return rc;
     }
     emit_cycle_end(c, K, x, mused);
     info->restarts++;
@@ -1986,6 +2046,7 @@ int batch_solve(Batch& Bt, const double* const* b, double* const* x, const st_op
   const int ns = int(Bt.sys.size());
   const int m = Bt.m;
   if ((o->restart > 0 && o->restart != m)) return ST_EINVAL;
+  if (o->orth < 0 || o->orth > 1) return ST_EINVAL;   // lockstep steps use CGS2
   const int maxit = o->maxit > 0 ? o->maxit : 1000;
   for (int i = 0; i < ns; ++i)
     if (!b[i] || !x[i] || b[i] == x[i]) return ST_EINVAL;

@@ -234,6 +234,10 @@ struct WsLayout {
   size_t pt_begin = 0;
 };
 constexpr int kPartialBlocks = 1024;   // blocks of the two-stage reductions
+// automatic Gram-Schmidt: delayed reorthogonalisation above this restart, or
+// from this many unknowns on (where reading the basis is bandwidth-bound)
+constexpr int kDelayedFrom = 64;
+constexpr int64_t kDelayedRows = int64_t(1) << 20;
 constexpr int kOpArgBytes = 448;       // largest argument block of a recorded launch
 WsLayout workspace_layout(const Plan& p);
 
