@@ -43,12 +43,28 @@ def chebyshev_jacobi(A, dinv, r, deg, theta, delta):
     theta + delta] (Saad, Iterative Methods for Sparse Linear Systems, Sec. 12.3):
     d_0 = D^{-1} r / theta; then r_i = r_{i-1} - A d_{i-1},
     rho_i = 1 / (2 sigma - rho_{i-1}) with sigma = theta / delta, rho_0 = 1 / sigma,
-    d_i = rho_i rho_{i-1} d_{i-1} + (2 rho_i / delta) D^{-1} r_i; x = sum of the d_i."""
-    sigma = theta / delta
-    rho = 1.0 / sigma
+    d_i = rho_i rho_{i-1} d_{i-1} + (2 rho_i / delta) D^{-1} r_i; x = sum of the d_i.
+
+    delta <= 0 stands for an ellipse with imaginary foci theta -+ i|delta|
+    (Manteuffel, Numer. Math. 28, 1977): the same recursion with c = i|delta| in
+    place of delta, written in g_i = rho_i / c so that only c^2 = -delta^2 enters:
+    g_0 = 1 / theta, g_i = 1 / (2 theta - c^2 g_{i-1}),
+    d_i = c^2 g_i g_{i-1} d_{i-1} + 2 g_i D^{-1} r_i."""
     res = np.array(r, dtype=np.float64)
     d = dinv * res / theta
     x = d.copy()
+    if delta <= 0.0:
+        csq = -delta * delta
+        g = 1.0 / theta
+        for _ in range(1, deg):
+            res = res - A @ d
+            g_new = 1.0 / (2.0 * theta - csq * g)
+            d = csq * g_new * g * d + 2.0 * g_new * (dinv * res)
+            g = g_new
+            x = x + d
+        return x
+    sigma = theta / delta
+    rho = 1.0 / sigma
     for _ in range(1, deg):
         res = res - A @ d
         rho_new = 1.0 / (2.0 * sigma - rho)

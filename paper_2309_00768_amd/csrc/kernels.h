@@ -16,6 +16,38 @@ constexpr int kBlock = 256;      // 4 slices per workgroup
 // of serialising them to reach maximum occupancy.
 #define ST_LATENCY_KERNEL __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
 
+// Coefficients of the Chebyshev iteration for D^{-1} A x = D^{-1} b whose
+// spectrum lies in an ellipse of centre theta with foci theta -+ c (Manteuffel,
+// Numer. Math. 28, 1977; Saad, Iterative Methods for Sparse Linear Systems,
+// Sec. 12.3): d_0 = D^{-1} r_0 / theta, then for step i >= 1
+//   d_i = c1 d_{i-1} + c2 D^{-1} r_i,  x_i = x_{i-1} + d_i.
+// delta > 0: real foci, c = delta (the interval [theta - delta, theta + delta]
+//   when the ellipse is flat), rho_i = 1 / (2 theta/delta - rho_{i-1}),
+//   rho_0 = delta / theta, c1 = rho_i rho_{i-1}, c2 = 2 rho_i / delta.
+// delta <= 0: imaginary foci, c^2 = -delta^2 (an ellipse taller than wide, for
+//   spectra of non-normal blocks), g_i = rho_i / c = 1 / (2 theta - c^2 g_{i-1}),
+//   g_0 = 1 / theta, c1 = c^2 g_i g_{i-1}, c2 = 2 g_i: real arithmetic only.
+struct ChebRec {
+  double theta, delta, a, b;   // a, b: rho (or g) of the previous and current step
+  __host__ __device__ ChebRec(double th, double de) : theta(th), delta(de) {
+    a = b = de > 0.0 ? 1.0 / (th / de) : 1.0 / th;
+  }
+  // Advances to the next step and returns its coefficients.
+  __host__ __device__ void next(double& c1, double& c2) {
+    a = b;
+    if (delta > 0.0) {
+      b = 1.0 / (2.0 * (theta / delta) - a);
+      c1 = b * a;
+      c2 = 2.0 * b / delta;
+    } else {
+      const double csq = -delta * delta;
+      b = 1.0 / (2.0 * theta - csq * a);
+      c1 = csq * b * a;
+      c2 = 2.0 * b;
+    }
+  }
+};
+
 // One segment of a multi-segment SELL SpMV.  For vector v (blockIdx.y) it adds
 //   alpha * A_seg(values of set `set_base + v*set_step`) * x[(v + xshift) * xstride + :]
 // when vlo <= v < vhi.
@@ -331,14 +363,11 @@ __device__ inline void cheb_body(const ChebArgs<T>& a, int bx, int v) {
   a.r[o + row] = rn;
   if (a.mode == 2) return;
   const T dg = a.dinv[(a.dstride ? int64_t(set) * a.dstride : 0) + row];
-  // Chebyshev recurrence coefficients for step `step` (rho_0 = delta/theta).
-  const double sigma = theta / delta;
-  double rho_prev = 1.0 / sigma, rho = rho_prev;
-  for (int i = 1; i <= a.step; ++i) {
-    rho_prev = rho;
-    rho = 1.0 / (2.0 * sigma - rho_prev);
-  }
-  const T c1 = T(rho * rho_prev), c2 = T(2.0 * rho / delta);
+  // Chebyshev recurrence coefficients for step `step`
+  ChebRec cr(theta, delta);
+  double k1 = 0.0, k2 = 0.0;
+  for (int i = 1; i <= a.step; ++i) cr.next(k1, k2);
+  const T c1 = T(k1), c2 = T(k2);
   const T d = c1 * d0[row] + c2 * dg * rn;
   a.dnew[o + row] = d;
   a.x[o + row] += d;
@@ -705,12 +734,9 @@ __device__ inline void st_solve_body(const StSolveArgs<T>& a, int bx) {
   const int ew = a.tx + 2 * H, ea = ew * (a.ty + 2 * H);
   const int ex0 = X0 - H, ey0 = Y0 - H;
   const int ta = a.tx * a.ty;
-  const double sigma = in.theta / a.delta;
-  double rho_prev = 1.0 / sigma, rho = rho_prev;
-  for (int i = 1; i < s0; ++i) {
-    rho_prev = rho;
-    rho = 1.0 / (2.0 * sigma - rho_prev);
-  }
+  ChebRec cr(in.theta, a.delta);
+  double k1 = 0.0, k2 = 0.0;
+  for (int i = 1; i < s0; ++i) cr.next(k1, k2);
   // A continued solve reads d_{s0-1} on the whole grown tile, r and x where
   // its first step computes.
   if (s0 > 0) {
@@ -735,10 +761,9 @@ __device__ inline void st_solve_body(const StSolveArgs<T>& a, int bx) {
     const bool last = s == s1 - 1;
     T c1 = T(0), c2 = T(0);
     if (s >= 1) {
-      rho_prev = rho;
-      rho = 1.0 / (2.0 * sigma - rho_prev);
-      c1 = T(rho * rho_prev);
-      c2 = T(2.0 * rho / a.delta);
+      cr.next(k1, k2);
+      c1 = T(k1);
+      c2 = T(k2);
     }
     for (int e = threadIdx.x; e < n; e += kSolveBlock) {
       const int c = e / wh, rem = e - c * wh;
@@ -852,12 +877,11 @@ __global__ __launch_bounds__(kChainBlock) void k_ca_chain(ChainArgs<T> a) {
     }
     __syncthreads();
     {
-      const double sigma = theta / delta;
-      double rho_prev = 1.0 / sigma, rho = rho_prev;
+      ChebRec cr(theta, delta);
       for (int i = 1; i < a.deg; ++i) {
-        rho_prev = rho;
-        rho = 1.0 / (2.0 * sigma - rho_prev);
-        const T c1 = T(rho * rho_prev), c2 = T(2.0 * rho / delta);
+        double k1, k2;
+        cr.next(k1, k2);
+        const T c1 = T(k1), c2 = T(k2);
         const T* dold = (i - 1) % 2 ? a.d1 : a.d0;
         T* dnew = i % 2 ? a.d1 : a.d0;
         for (int row = tid; row < na; row += kChainBlock) {
@@ -883,12 +907,11 @@ __global__ __launch_bounds__(kChainBlock) void k_ca_chain(ChainArgs<T> a) {
     }
     __syncthreads();
     {
-      const double sigma = a.mth / a.mde;
-      double rho_prev = 1.0 / sigma, rho = rho_prev;
+      ChebRec cr(a.mth, a.mde);
       for (int i = 1; i < a.mit; ++i) {
-        rho_prev = rho;
-        rho = 1.0 / (2.0 * sigma - rho_prev);
-        const T c1 = T(rho * rho_prev), c2 = T(2.0 * rho / a.mde);
+        double k1, k2;
+        cr.next(k1, k2);
+        const T c1 = T(k1), c2 = T(k2);
         const T* dold = (i - 1) % 2 ? a.d1 : a.d0;
         T* dnew = i % 2 ? a.d1 : a.d0;
         for (int row = tid; row < nj; row += kChainBlock) {

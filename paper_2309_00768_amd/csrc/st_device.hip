@@ -582,13 +582,12 @@ void sweep_step_stencil(Ctx& c, Handle& H, DAmg& a, const StencilOp& A, const St
   ca.rpb = rpb;
   ca.lanes = lanes;
   T* d[2] = {d0, d1};
-  const double sigma = theta / delta;
-  double rho_prev = 1.0 / sigma, rho = rho_prev;
+  ChebRec cr(theta, delta);
   for (int i = 1; i < deg; ++i) {
-    rho_prev = rho;
-    rho = 1.0 / (2.0 * sigma - rho_prev);
-    ca.c1 = rho * rho_prev;
-    ca.c2 = 2.0 * rho / delta;
+    double k1, k2;
+    cr.next(k1, k2);
+    ca.c1 = k1;
+    ca.c2 = k2;
     ca.dold = d[(i - 1) % 2];
     ca.dnew = d[i % 2];
     if (role == 1) emit(c, kKStCheb, grid, &k_st_cheb<T, 1>, ca);

@@ -4,7 +4,9 @@ the F_u and C_A sweeps of P_T).
 * Chebyshev-Jacobi: after d steps from zero the preconditioned residual is the
   scaled Chebyshev polynomial T_d((theta - t) / delta) / T_d(theta / delta) of
   D^{-1} A applied to the first one (checked through the eigendecomposition of
-  the symmetric D^{-1/2} A D^{-1/2}, with T_d from numpy's Chebyshev series).
+  the symmetric D^{-1/2} A D^{-1/2}, with T_d from numpy's Chebyshev series);
+  with imaginary foci theta -+ i c the same with i c for delta, checked on a
+  non-normal matrix with complex eigenvalues.
 * The slab steps with exact spatial solves are the forward substitutions of
   P_T's sweeps (``solve_Fu``, ``solve_CA``).
 * Parareal's finite termination: after j iterations the first j slabs are the
@@ -53,6 +55,36 @@ def test_chebyshev_jacobi_is_the_chebyshev_residual_polynomial(deg):
     # x = A^{-1} (I - p(D^{-1} A)) r, in the symmetric frame
     x_ref = Dh * (V @ (((1.0 - p) / lam) * (V.T @ (Dh * r))))
     assert np.allclose(x, x_ref, rtol=1e-12, atol=1e-12 * np.abs(x_ref).max())
+
+
+@pytest.mark.parametrize("deg", [1, 2, 5, 9])
+def test_chebyshev_jacobi_on_an_ellipse_with_imaginary_foci(deg):
+    """A non-normal D^{-1} A with eigenvalues well off the real axis, foci
+    theta -+ i c: the residual polynomial is T_d((theta - lambda)/(i c)) /
+    T_d(theta/(i c)), evaluated through the (complex) eigendecomposition."""
+    rng = np.random.default_rng(8)
+    n = 10
+    # eigenvalues 1 +- 0.6i, 0.8 +- 0.4i, ... as 2x2 rotation blocks, in a random basis
+    blocks = np.zeros((n, n))
+    for k in range(n // 2):
+        re, im = 0.7 + 0.1 * k, 0.2 + 0.15 * k
+        blocks[2 * k:2 * k + 2, 2 * k:2 * k + 2] = [[re, im], [-im, re]]
+    Q = rng.standard_normal((n, n)) + 3 * np.eye(n)
+    M = Q @ blocks @ np.linalg.inv(Q)          # D^{-1} A
+    d = rng.uniform(1.0, 2.0, n)
+    A = d[:, None] * M
+    lam, V = np.linalg.eig(M)
+    assert np.abs(lam.imag).max() > 0.5
+    theta, c = 0.9, 0.5                          # foci 0.9 -+ 0.5i
+    r = rng.standard_normal(n)
+    x = paratime.chebyshev_jacobi(A, 1.0 / d, r, deg, theta, -c)
+    Td = np.zeros(deg + 1)
+    Td[deg] = 1.0
+    p = C.chebval((theta - lam) / (1j * c), Td) / C.chebval(theta / (1j * c), Td)
+    # x = A^{-1} (I - p(D^{-1} A)) r = M^{-1} (I - p(M)) D^{-1} r
+    y = np.linalg.solve(V, r / d)
+    x_ref = (V @ (((1.0 - p) / lam) * y)).real
+    assert np.allclose(x, x_ref, rtol=1e-10, atol=1e-10 * np.abs(x_ref).max())
 
 
 def test_slab_steps_with_exact_solves_are_the_forward_substitutions():
