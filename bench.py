@@ -325,17 +325,19 @@ def bench_batch(args, dev, cpu=None):
             return x
         t1 = time.perf_counter()
         c = cfgs[i]
+        # restart within the memory given to the long-restart Krylov vectors (V and Z, FP64)
+        m_i = max(30, min(long_m, int(args.long_mem_gb * 1e9 / (16 * systems[i].N))))
         ub, ab = inputs.state(c)
         plan = binding.Plan(c.n, c.nt, c.dt, c.mu, c.eta, c.mu0, ub, ab, precision="fp32",
-                            autotune=not args.no_autotune, max_restart=long_m)
+                            autotune=not args.no_autotune, max_restart=m_i)
         sg = binding.System(plan, dev)
         plan.close()
         torch.cuda.synchronize()
         setup_in_timed[0] += time.perf_counter() - t1
-        x, info, rc, _ = sg.solve(rhs[i], x, restart=long_m, rtol=args.rtol, maxit=args.long_maxit, x0=True)
+        x, info, rc, _ = sg.solve(rhs[i], x, restart=m_i, rtol=args.rtol, maxit=args.long_maxit, x0=True)
         if rc < 0:
             raise RuntimeError(f"long-restart solve of member {i}: status {rc}")
-        log(f"  member {i}: FGMRES({long_m}) {info.iterations} its, {info.seconds:.2f} s, "
+        log(f"  member {i}: FGMRES({m_i}) {info.iterations} its, {info.seconds:.2f} s, "
             f"residual {info.true_rel_residual:.1e}")
         total[i] += info.iterations
         status[i], res[i] = rc, info.true_rel_residual
@@ -396,8 +398,9 @@ def bench_batch(args, dev, cpu=None):
                                f"{[(c.n, c.nt) for c in cfgs]}, dt = 1/Nt, Re=S=300; lockstep FGMRES(30) "
                                f"({GROUPING[args.batch_groups]}) to "
                                f"{args.rtol:g} within {budget} iterations per member"
-                               + (f", then FGMRES({long_m}) alone for the members still open (at most "
-                                  f"{args.long_maxit} iterations)" if long_m > 0 else "") + ", P_T in FP32",
+                               + (f", then FGMRES(m <= {long_m}, Krylov vectors within {args.long_mem_gb:g} GB) alone "
+                                  f"for the members still open (at most {args.long_maxit} iterations)"
+                                  if long_m > 0 else "") + ", P_T in FP32",
                    "N_total": ntot},
         "time_to_1e8_s": elapsed / args.steps if all(converged) else None,
         "fgmres_iters": its, "converged": converged, "true_rel_residual": res,
@@ -607,10 +610,12 @@ def main():
     ap.add_argument("--no-separate", action="store_true", help="cfg4: skip the one-at-a-time comparison")
     ap.add_argument("--batch-budget", type=int, default=480,
                     help="cfg4: lockstep FGMRES(30) iterations per member")
-    ap.add_argument("--long-restart", type=int, default=600,
+    ap.add_argument("--long-restart", type=int, default=1200,
                     help="cfg4: restart of the second phase for members still open after the lockstep budget "
                          "(0: none)")
     ap.add_argument("--long-maxit", type=int, default=2400, help="cfg4: iteration cap of the second phase")
+    ap.add_argument("--long-mem-gb", type=float, default=150.0,
+                    help="cfg4: device memory for the second phase's Krylov vectors (caps its restart per member)")
     ap.add_argument("--batch-groups", choices=sorted(GROUPING), default="all",
                     help="cfg4: " + "; ".join(f"{k}: {v}" for k, v in GROUPING.items()))
     ap.add_argument("--no-fd", action="store_true", help="cfg5: skip the finite-difference check")
