@@ -561,7 +561,8 @@ def bench_adjoint(args, dev):
     print(json.dumps(out), flush=True)
 
 
-def main():
+def parse_args(argv=None):
+    """The command line, with the per-workload defaults of the options left unset."""
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
@@ -623,13 +624,18 @@ def main():
                     help="default launch choices instead of timing them at st_create")
     ap.add_argument("--probe", choices=["jacobian", "sweeps"], default=None,
                     help="run only a few J applies (or P_T applies) and a copy of known size (for hardware-counter runs)")
-    args = ap.parse_args()
+    args = ap.parse_args(argv)
     # per-workload defaults of the options left unset
     dflt = {"restart": 30, "maxit": 1000, "precision": "fp32"}
     dflt.update(CONFIG_DEFAULTS.get(args.config, {}))
     for k, v in dflt.items():
         if getattr(args, k) is None:
             setattr(args, k, v)
+    return args
+
+
+def main():
+    args = parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (one system is not sharded "
               f"across GPUs in this build)", file=sys.stderr)

@@ -17,6 +17,22 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert "one GPU" in p.stderr
 
 
+def test_per_workload_defaults():
+    """Restarts past the residual plateau where FGMRES(30) stalls (cfg2's shear
+    layer, Re = S = 1000), all-FP64 at Re = S = 1000; explicit options win."""
+    a = bench.parse_args([])
+    assert (a.config, a.restart, a.maxit, a.precision, a.orth) == ("cfg3", 30, 1000, "fp32", "auto")
+    a = bench.parse_args(["--config", "cfg2"])
+    assert (a.restart, a.maxit, a.precision) == (1000, 3000, "fp32")
+    a = bench.parse_args(["--config", "cfg3_re1000"])
+    assert (a.restart, a.maxit, a.precision) == (2000, 2500, "fp64")
+    a = bench.parse_args(["--config", "cfg3_re1000", "--precision", "fp32", "--restart", "500"])
+    assert (a.restart, a.precision) == (500, "fp32")
+    assert bench.orth_name("auto", 30, 5_718_656).endswith("delayed reorthogonalisation")
+    assert bench.orth_name("auto", 30, 5288) == "CGS2"
+    assert bench.orth_name("auto", 2000, 5288).endswith("delayed reorthogonalisation")
+
+
 def test_reported_traffic_is_the_committed_counter_summary():
     """The J traffic bench.py reports is the calibrated FETCH_SIZE + WRITE_SIZE
     figure of the committed rocprofv3 summary."""
