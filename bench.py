@@ -637,8 +637,8 @@ def parse_args(argv=None):
 def main():
     args = parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (one system is not sharded "
-              f"across GPUs in this build)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the solve of one system "
+              f"is not sharded across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     from paper_2309_00768_amd import inputs
