@@ -150,6 +150,18 @@ def test_delayed_zero_rhs_and_caps():
         assert np.all(np.isfinite(hist)) and hist[-1] < hist[0]
 
 
+def test_unknown_orth_is_rejected():
+    from paper_2309_00768_amd import binding
+    sysg = system(8, 8)
+    b = dev(inputs.rhs(case(8, 8)[0], 1))
+    binding.ORTH["bad"] = 3
+    try:
+        with pytest.raises(RuntimeError):
+            sysg.solve(b, maxit=5, orth="bad")
+    finally:
+        del binding.ORTH["bad"]
+
+
 def test_batch_rejects_delayed():
     from paper_2309_00768_amd import binding
     sysg = system(8, 8)
