@@ -8,8 +8,8 @@ imaginary foci there.
 
 * Converged Chebyshev solves (degree 100 on F_u,k, 320 on C_A,k; the slowest
   factor on the true eigenvalues is 0.92), with EXACT mode converging the K_p
-  and mass solves, give the oracle's exact-solve P_T^{-1} r to 1e-9 per block,
-  in FP64.
+  and mass solves, give the oracle's exact-solve P_T^{-1} r and P_T^{-T} r to
+  1e-9 per block, in FP64.
 * Production FP32 solves: FGMRES reaches a true residual of 1e-8 (checked by
   the oracle).
 * A member of the uneven batch (32 x 32 mesh, 16 slabs, dt = 1/16,
@@ -58,12 +58,15 @@ def test_converged_ellipse_sweeps_give_PT():
     say("[gpu] non-normal blocks: converged Chebyshev sweeps (ellipses) vs exact P_T^-1")
     from paper_2309_00768_amd import binding
     cfg, ub, ab, ref = case("small")
-    plan = plan_of(cfg, ub, ab, precision="fp64", inner="exact", fu_solver=100, ca_solver=320)
+    plan = plan_of(cfg, ub, ab, precision="fp64", inner="exact", fu_solver=100, ca_solver=320, adjoint=True)
     assert min(d for _, d in plan.cheb_intervals("Fu")) <= 0.0
     sysg = binding.System(plan, "cuda:0")
     r = np.random.default_rng(41).standard_normal(ref.N)
     z = sysg.apply_precond(dev(r)).cpu().numpy()
     assert_blocks(z, ref.apply_PT_inv(r), sysg.offsets, cfg.nt, 1e-9, "P_T^-1 (ellipse sweeps)")
+    # the transposed sweeps reuse the ellipses (D^{-1} A^T has the spectrum of D^{-1} A)
+    zt = sysg.apply_precond(dev(r), transpose=True).cpu().numpy()
+    assert_blocks(zt, ref.apply_PT_invT(r), sysg.offsets, cfg.nt, 1e-9, "P_T^-T (ellipse sweeps)")
 
 
 def test_non_normal_fgmres_production_fp32():
