@@ -604,6 +604,11 @@ def parse_args(argv=None):
                          "2000-vector basis leaves no room for a second system) and of the Newton corrections")
     ap.add_argument("--variant", choices=["PT", "Ptilde", "P"], default="PT",
                     help="preconditioner: P_T (default), P-tilde or the full P (step by step)")
+    ap.add_argument("--window", type=int, default=1,
+                    help="with --timestep: slabs per step (1: sequential time stepping with P_{T,k}; W > 1: "
+                         "windows of W slabs solved all at once in turn)")
+    ap.add_argument("--window-restart", type=int, default=0,
+                    help="with --timestep: FGMRES restart per step (0: 30 for single slabs, 200 for windows)")
     ap.add_argument("--timestep", action="store_true",
                     help="also solve the workload by sequential time stepping with P_{T,k} (one-slab systems)")
     ap.add_argument("--profile-every", type=int, default=32,
@@ -848,9 +853,11 @@ def main():
         # the same workload by sequential time stepping with P_{T,k}: one one-slab
         # system per slab (FP32 preconditioner), each step to ||r_k|| <= rtol ||b|| / sqrt(Nt)
         t0 = time.perf_counter()
+        W = max(1, args.window)
+        wm = args.window_restart or (30 if W == 1 else 200)
         ts = binding.TimeStepping(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, device=dev,
-                                  precision="fp32")
-        log(f"time stepping setup {time.perf_counter() - t0:.1f} s ({cfg.nt} one-slab systems)")
+                                  precision="fp32", window=W, restart=wm)
+        log(f"time stepping setup {time.perf_counter() - t0:.1f} s ({len(ts.systems)} systems of {W} slab(s))")
         bt = bts[0]
         xts = torch.zeros_like(bt)
         ts.solve(bt, xts, rtol=args.rtol)        # warm-up
@@ -862,7 +869,10 @@ def main():
         step_its = [i.iterations for i in tinfos]
         avg = sum(step_its) / len(step_its)
         out["time_stepping"] = {
-            "preconditioner": "P_{T,k} (single step), FP32, FGMRES(30) per step, warm start",
+            "preconditioner": (f"P_{{T,k}} (single step), FP32, FGMRES({wm}) per step, warm start" if W == 1 else
+                               f"P_T of each window of {W} slabs (windowed space-time), FP32, FGMRES({wm}) per "
+                               f"window, warm start"),
+            "window": W,
             "time_s": tts, "converged": trc == 0, "iterations_total": sum(step_its),
             "iterations_per_step_avg": avg, "iterations_per_step_max": max(step_its),
             # against the first right-hand side's space-time solves

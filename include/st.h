@@ -339,15 +339,20 @@ int st_adjoint_solve(st_handle* h, const double* g, double* lam, const st_opts* 
  * single-step Jacobian of eq. (jacobianDiscrete), by FGMRES(m)
  * right-preconditioned with the single-step P_{T,k} of eq. (PTTS) (with eq.
  * (ASchurApproxTS)).  hs[k] is a handle created from a one-slab plan (Nt = 1)
- * of slab k's state, whose P_T is P_{T,k}; all handles share n.  b, x: device,
- * length nt * Ns, slab-major, the same layout as the all-at-once system.
- * Step k stops on ||r_k||_2 <= max(rtol ||b||_2, atol) / sqrt(nt) (the paper's
- * scaling of the step tolerance; the step residuals are the rows of the
- * space-time residual, so x meets ||b - J x|| <= max(rtol ||b||, atol)).  With
- * o->x0_given = 1 each step k >= 2 starts from x^{k-1} (the paper's warm
- * start), else from zero.  infos[k] receives step k's result.  Blocks until
- * done.  Returns ST_OK if every step converged, ST_ENOTCONV if some did not
- * (later steps still run from that iterate), else an error. */
+ * of slab k's state, whose P_T is P_{T,k}; all handles share n.  A handle of
+ * W_k > 1 slabs (a plan of those slabs' states) makes step k a window solved
+ * all at once with its own P_T (windowed space-time), coupled to the previous
+ * window's last slab in the same way; nt is then the number of windows and
+ * Nt = sum W_k.  b, x: device, length Nt * Ns, slab-major, the same layout as
+ * the all-at-once system.  Step k stops on
+ * ||r_k||_2 <= max(rtol ||b||_2, atol) sqrt(W_k / Nt) (the paper's scaling of
+ * the step tolerance; the step residuals are the rows of the space-time
+ * residual, so x meets ||b - J x|| <= max(rtol ||b||, atol)).  With
+ * o->x0_given = 1 every slab of step k >= 2 starts from the previous step's
+ * last slab (the paper's warm start), else from zero.  infos[k] receives step
+ * k's result.  Blocks until done.  Returns ST_OK if every step converged,
+ * ST_ENOTCONV if some did not (later steps still run from that iterate), else
+ * an error. */
 int st_timestep_solve(st_handle* const* hs, int nt, const double* b, double* x, const st_opts* o,
                       st_info* infos, void* stream);
 

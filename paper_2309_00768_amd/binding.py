@@ -400,22 +400,25 @@ class System:
 
 class TimeStepping:
     """Sequential time stepping with the single-step preconditioner P_{T,k}
-    (``st_timestep_solve``): one one-slab system per slab of the state."""
+    (``st_timestep_solve``): one one-slab system per slab of the state; with
+    ``window`` W > 1, windows of W slabs (the last one shorter), each solved all
+    at once with its own P_T (windowed space-time)."""
 
     def __init__(self, n, nt, dt, mu, eta, mu0, ubar, abar, device="cuda:0", precision="fp64", inner="amg",
-                 restart=30, **plan_kw):
+                 restart=30, window=1, **plan_kw):
         self.systems = []
-        for k in range(nt):
-            plan = Plan(n, 1, dt, mu, eta, mu0, ubar[k:k + 1], abar[k:k + 1], precision=precision, inner=inner,
-                        max_restart=restart, **plan_kw)
+        for k0 in range(0, nt, window):
+            w = min(window, nt - k0)
+            plan = Plan(n, w, dt, mu, eta, mu0, ubar[k0:k0 + w], abar[k0:k0 + w], precision=precision,
+                        inner=inner, max_restart=restart, **plan_kw)
             self.systems.append(System(plan, device))
             plan.close()
-        self.nt, self.ns, self.restart = nt, self.systems[0].ns, restart
+        self.nt, self.ns, self.restart, self.window = nt, self.systems[0].ns, restart, window
         self.N = self.nt * self.ns
         self.offsets = self.systems[0].offsets
 
     def solve(self, b, x=None, rtol=1e-8, atol=0.0, maxit=1000, warm_start=True, stream=None):
-        """Returns (x, per-step infos, status)."""
+        """Returns (x, per-step (per-window) infos, status)."""
         import torch
         assert b.dtype == torch.float64 and b.is_cuda and b.is_contiguous() and b.numel() == self.N
         x = torch.zeros_like(b) if x is None else x
@@ -423,9 +426,10 @@ class TimeStepping:
         o.restart, o.maxit, o.rtol, o.atol, o.x0_given = self.restart, maxit, rtol, atol, int(warm_start)
         o.history_len = 0
         o.history = ctypes.POINTER(ctypes.c_double)()
-        infos = (StInfo * self.nt)()
-        arr = (ctypes.c_void_p * self.nt)(*[s.ptr.value for s in self.systems])
-        rc = _check(lib().st_timestep_solve(arr, self.nt, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+        nw = len(self.systems)
+        infos = (StInfo * nw)()
+        arr = (ctypes.c_void_p * nw)(*[s.ptr.value for s in self.systems])
+        rc = _check(lib().st_timestep_solve(arr, nw, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
                                             ctypes.byref(o), infos, _stream_ptr(stream)), "st_timestep_solve")
         return x, list(infos), rc
 

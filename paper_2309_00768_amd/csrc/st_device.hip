@@ -1521,20 +1521,27 @@ int fgmres(Handle& H, const double* b_in, double* x, const st_opts* o, st_info* 
 // right-preconditioned by the single-step P_{T,k} of eq. (PTTS), which is P_T
 // of a one-slab system, so hs[k] is a one-slab handle of slab k's state:
 //   J_k x^k = b^k + diag(M_u/dt, 0, 0, M_A/dt) x^{k-1}.
-// Each step stops on ||r_k|| <= max(rtol ||b||, atol) / sqrt(Nt) (the step
-// residuals are the rows of the space-time residual, so the whole x meets
-// the space-time tolerance).  With o->x0_given each step starts from the
-// previous step's solution.
+// A handle of W > 1 slabs makes step k a window of W slabs solved all at once
+// with its own P_T (windowed space-time), coupled to the previous window's
+// last slab the same way.  Window k of W_k slabs stops on
+// ||r_k|| <= max(rtol ||b||, atol) sqrt(W_k / Nt) (the window residuals are
+// the rows of the space-time residual, so the whole x meets the space-time
+// tolerance).  With o->x0_given every slab of a window starts from the
+// previous window's last slab.
 int timestep_solve(st_handle* const* hs, int nt, const double* b, double* x, const st_opts* o, st_info* infos,
                    hipStream_t s) {
   const Dims& d0 = hs[0]->h.d;
   const int ns = d0.ns;
+  // window k holds slabs [first[k], first[k] + W_k) of the horizon
+  std::vector<int64_t> first(size_t(nt) + 1, 0);
   for (int k = 0; k < nt; ++k) {
     const Dims& d = hs[k]->h.d;
-    if (d.nt != 1 || d.ns != ns || d.n != d0.n) return ST_EINVAL;
+    if (d.nt < 1 || d.ns != ns || d.n != d0.n) return ST_EINVAL;
     for (int i = 0; i < 6; ++i)
       if (d.off[i] != d0.off[i]) return ST_EINVAL;
+    first[size_t(k) + 1] = first[size_t(k)] + d.nt;
   }
+  const double total = double(first[size_t(nt)]);
   const int m = o->restart > 0 ? o->restart : 30;
   Ctx c{s, nullptr};
   // ||b|| with every slab's pressure rows projected to zero sum
@@ -1543,34 +1550,40 @@ int timestep_solve(st_handle* const* hs, int nt, const double* b, double* x, con
     Handle& H = hs[k]->h;
     if (m > H.max_restart) return ST_EINVAL;
     const Krylov K = krylov(H, m);
-    emit_fgmres_init(c, H, K, b + int64_t(k) * ns, x + int64_t(k) * ns, false);
+    emit_fgmres_init(c, H, K, b + first[size_t(k)] * ns, x + first[size_t(k)] * ns, false);
     HIP_TRY(hipMemcpyAsync(H.host_small, K.sm, sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (!std::isfinite(H.host_small[0])) return ST_EBREAKDOWN;
     bb += H.host_small[0] * H.host_small[0];
   }
-  const double tol = std::max(o->rtol * std::sqrt(bb), o->atol) / std::sqrt(double(nt));
+  const double tol_all = std::max(o->rtol * std::sqrt(bb), o->atol);
   int status = ST_OK;
   for (int k = 0; k < nt; ++k) {
     Handle& H = hs[k]->h;
+    const int w = H.d.nt;
     const Krylov K = krylov(H, m);
-    const double* bk = b + int64_t(k) * ns;
-    double* xk = x + int64_t(k) * ns;
+    const double* bk = b + first[size_t(k)] * ns;
+    double* xk = x + first[size_t(k)] * ns;
     const double* rhs = bk;
     if (k > 0) {
-      // rhs = b^k - J_{k,k-1} x^{k-1}, formed in handle k's Arnoldi work vector
-      // (FGMRES reads its right-hand side only when it projects it, before its
-      // first Arnoldi step)
-      const double* xprev = x + int64_t(k - 1) * ns;
+      // rhs = b^k - J_{k,k-1} x^{k-1} on the window's first slab (its coupling to
+      // the previous window's last slab), the window's other slabs as in b;
+      // formed in handle k's Arnoldi work vector (FGMRES reads its right-hand
+      // side only when it projects it, before its first Arnoldi step)
+      const double* xprev = x + (first[size_t(k)] - 1) * ns;
+      if (w > 1)
+        HIP_TRY(hipMemcpyAsync(K.w + ns, bk + ns, sizeof(double) * size_t(w - 1) * ns, hipMemcpyDeviceToDevice, s));
       Seg<double> sg = seg<double>(H.J, 2, 0, 0, xprev, ns, 0, 0, 1, -1.0);
       spmv<double, double>(c, H.J, 1, 1, &sg, bk, ns, 1.0, K.w, ns, kRoleJ);
       rhs = K.w;
-      if (o->x0_given) HIP_TRY(hipMemcpyAsync(xk, xprev, sizeof(double) * ns, hipMemcpyDeviceToDevice, s));
+      if (o->x0_given)
+        for (int j = 0; j < w; ++j)
+          HIP_TRY(hipMemcpyAsync(xk + int64_t(j) * ns, xprev, sizeof(double) * ns, hipMemcpyDeviceToDevice, s));
     }
     st_opts ok = *o;
     ok.restart = m;
     ok.rtol = 0.0;
-    ok.atol = tol;
+    ok.atol = tol_all * std::sqrt(double(w) / total);
     ok.x0_given = (o->x0_given && k > 0) ? 1 : 0;
     ok.history = nullptr;
     ok.history_len = 0;

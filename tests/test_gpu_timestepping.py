@@ -8,6 +8,8 @@
 * Production inner solves, FP32 and FP64 preconditioner: the space-time
   residual recomputed by the oracle meets 1e-8, on a ragged 5-slab horizon.
 * Cold and warm starts give the same solution to the tolerance.
+* Windows of several slabs (windowed space-time, each window with its own P_T):
+  EXACT mode equals x*, production FP32 meets the space-time tolerance.
 """
 import functools
 import sys
@@ -84,3 +86,25 @@ def test_warm_and_cold_starts_agree():
     xs = ref.direct_solve(b)
     assert_blocks(xw.cpu().numpy(), xs, ts.offsets, cfg.nt, 1e-9, "warm")
     assert_blocks(xc.cpu().numpy(), xs, ts.offsets, cfg.nt, 1e-9, "cold")
+
+
+@pytest.mark.parametrize("window", [2, 3])
+def test_windowed_space_time_matches_direct_solution(window):
+    """Windows of W slabs solved all at once in turn (the last one shorter:
+    7 slabs in windows of 2 or 3), each coupled to the previous window's last
+    slab: EXACT mode reaches the direct x* per block; production FP32 solves meet
+    the space-time tolerance (oracle residual)."""
+    say(f"[gpu] windowed space-time, windows of {window} slabs, n=6 nt=7")
+    cfg, ub, ab, ref = case(6, 7)
+    b = inputs.rhs(cfg, 1)
+    ts = stepping(cfg, ub, ab, inner="exact", window=window)
+    assert len(ts.systems) == -(-cfg.nt // window)
+    x, infos, rc = ts.solve(dev(b), rtol=1e-13)
+    assert rc == 0 and all(i.converged for i in infos)
+    assert_blocks(x.cpu().numpy(), ref.direct_solve(b), ts.offsets, cfg.nt, 1e-10, f"x vs x* (windows of {window})")
+    ts32 = stepping(cfg, ub, ab, precision="fp32", window=window, restart=60)
+    x, infos, rc = ts32.solve(dev(b), rtol=1e-8)
+    bp = ref.project_pressure(b)
+    res = np.linalg.norm(bp - ref.apply_J(x.cpu().numpy())) / np.linalg.norm(bp)
+    say(f"    fp32: iterations per window {[i.iterations for i in infos]}, oracle residual {res:.2e}")
+    assert rc == 0 and res <= 1.05e-8
