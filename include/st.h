@@ -229,14 +229,20 @@ int st_plan_export_block(const st_plan* plan, int block, int k, int* nrows, int*
                          int64_t* nnz, int* rowptr, int* colind, double* val);
 
 /* Inner solvers chosen by the setup: Chebyshev degree used alone on F_u,k and
- * C_A,k (0 = SA-AMG V-cycle) and the estimated condition numbers of D^{-1} A. */
+ * C_A,k (0 = SA-AMG V-cycle) and the estimated condition numbers of D^{-1} A
+ * (for a slab on an ellipse, or whose interval contracts slower than its
+ * condition number says, the condition number of an interval with the same
+ * convergence factor). */
 int st_plan_solver_info(const st_plan* plan, int* fu_degree, int* ca_degree, double* fu_kappa,
                         double* ca_kappa);
 
 /* Chebyshev-alone intervals of the sweep blocks, host: which = 0 for F_u,k,
- * 1 for C_A,k; out[2 k] = theta and out[2 k + 1] = delta of slab k (nt pairs),
- * the interval [theta - delta, theta + delta] the Chebyshev-Jacobi steps of
- * that slab's spatial solve assume for the eigenvalues of D^{-1} A. */
+ * 1 for C_A,k; out[2 k] = theta and out[2 k + 1] = delta of slab k (nt pairs).
+ * delta > 0: the Chebyshev-Jacobi steps of that slab's spatial solve assume
+ * the eigenvalues of D^{-1} A in an ellipse with foci theta -+ delta (the
+ * interval [theta - delta, theta + delta] when flat); delta <= 0: foci
+ * theta -+ i|delta| (a non-normal block with eigenvalues far off the real
+ * axis; Manteuffel, Numer. Math. 28, 1977). */
 int st_plan_cheb_intervals(const st_plan* plan, int which, double* out);
 
 /* The current state used (either given or computed), host [nt][(n+1)^2]. */
