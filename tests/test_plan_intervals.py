@@ -11,6 +11,8 @@ c = delta for delta > 0 and c = i |delta| otherwise.
   dt = 1/8, Re = S = 1000; the real interval's iteration diverges there) gets
   ellipses with imaginary foci on F_u, and the iteration contracts every
   eigenvalue of every slab, at about the factor the degree choice assumes.
+* The C_A,k blocks of a member of the uneven batch get ellipses with
+  imaginary foci that contract every eigenvalue.
 * The cfg1 blocks keep real intervals that contract every eigenvalue.
 """
 import numpy as np
@@ -33,7 +35,7 @@ def factor(ev, theta, delta):
     return float((level(ev) / level(0.0)).max())
 
 
-def spectra(cfg):
+def spectra(cfg, blocks=("Fu", "CA")):
     ub, ab = inputs.state(cfg)
     plan = binding.Plan(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, precision="fp32")
     ref = oracle.system_from_config(cfg, ub, ab)
@@ -41,6 +43,8 @@ def spectra(cfg):
     out = {}
     for name, ivs, block in (("Fu", plan.cheb_intervals("Fu"), lambda k: ref.slabs[k].Fu),
                              ("CA", plan.cheb_intervals("CA"), lambda k: st.C0[k])):
+        if name not in blocks:
+            continue
         rows = []
         for k in range(cfg.nt):
             A = block(k)
@@ -51,6 +55,18 @@ def spectra(cfg):
         out[name] = rows
     fu_k, ca_k = plan.solver_info()[2:]
     return out, {"Fu": fu_k, "CA": ca_k}
+
+
+def test_uneven_batch_member_wave_blocks_get_contracting_ellipses():
+    """Member 2 of the uneven batch (32 x 32 mesh, 16 slabs, dt = 1/16,
+    Re = S = 300): eigenvalues of D^{-1} C_A,k up to 1.1 off the real axis.  The
+    chosen ellipses (imaginary foci) contract every eigenvalue of every slab."""
+    out, kap = spectra(inputs.batch_configs()[2], blocks=("CA",))
+    rows = out["CA"]
+    assert any(d <= 0.0 for _, d, _, _ in rows)
+    worst = max(f for _, _, f, _ in rows)
+    print(f"C_A: worst factor {worst:.3f}, model {model_factor(kap['CA']):.3f}")
+    assert worst < 1.0
 
 
 def model_factor(kappa):
