@@ -851,12 +851,13 @@ def main():
                            "bytes_per_launch": jbytes, "avg_launch_ms": jac_avg * 1e3, "launches": jac_n}
     if args.timestep:
         # the same workload by sequential time stepping with P_{T,k}: one one-slab
-        # system per slab (FP32 preconditioner), each step to ||r_k|| <= rtol ||b|| / sqrt(Nt)
+        # system per slab (or one per window of W slabs; the preconditioner in the
+        # precision of the timed solves), each step to ||r_k|| <= rtol ||b|| sqrt(W / Nt)
         t0 = time.perf_counter()
         W = max(1, args.window)
         wm = args.window_restart or (30 if W == 1 else 200)
         ts = binding.TimeStepping(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, device=dev,
-                                  precision="fp32", window=W, restart=wm)
+                                  precision=prec, window=W, restart=wm)
         log(f"time stepping setup {time.perf_counter() - t0:.1f} s ({len(ts.systems)} systems of {W} slab(s))")
         bt = bts[0]
         xts = torch.zeros_like(bt)
@@ -869,9 +870,10 @@ def main():
         step_its = [i.iterations for i in tinfos]
         avg = sum(step_its) / len(step_its)
         out["time_stepping"] = {
-            "preconditioner": (f"P_{{T,k}} (single step), FP32, FGMRES({wm}) per step, warm start" if W == 1 else
-                               f"P_T of each window of {W} slabs (windowed space-time), FP32, FGMRES({wm}) per "
-                               f"window, warm start"),
+            "preconditioner": (f"P_{{T,k}} (single step), {prec.upper()}, FGMRES({wm}) per step, warm start"
+                               if W == 1 else
+                               f"P_T of each window of {W} slabs (windowed space-time), {prec.upper()}, "
+                               f"FGMRES({wm}) per window, warm start"),
             "window": W,
             "time_s": tts, "converged": trc == 0, "iterations_total": sum(step_its),
             "iterations_per_step_avg": avg, "iterations_per_step_max": max(step_its),
