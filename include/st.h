@@ -320,7 +320,8 @@ int st_apply_initial_coupling(st_handle* h, const double* a0, double* y, void* s
 /* Right-preconditioned FGMRES(m) on J x = b with P_T, the Krylov method the
  * paper wraps around eq. (PT) (Sec. "Performance of preconditioner", GMRES
  * right-preconditioned; flexible here because the inner solves are
- * iterative); residual, Arnoldi (CGS2) and the Hessenberg least-squares
+ * iterative); residual, Arnoldi (CGS2, or CGS2 with delayed
+ * reorthogonalisation: st_opts.orth) and the Hessenberg least-squares
  * problem in FP64 on the device.  b, x device, length N, slab-major; the
  * pressure rows of b are projected to zero sum per slab and x is normalised
  * to 1^T M_p p^k = 0.  Stops when ||b - J x||_2 <= max(rtol ||b||_2, atol) (true
