@@ -18,6 +18,12 @@ rtol ||b|| / sqrt(Nt): the per-step residuals are exactly the rows of the
 space-time residual, so the whole solution then meets ||b - J x|| <= rtol ||b||.
 Each step may start from the previous step's solution (the paper reuses it as
 the next step's initial guess).
+
+Between the two extremes, windows of W slabs can be solved one after the other,
+each all at once with the P_T of eq. (PT) on its own slabs and coupled to the
+previous window's last slab in the same way; window k then stops on
+rtol ||b|| sqrt(W_k / Nt), which again bounds the whole space-time residual.
+W = 1 is time stepping, W = Nt the all-at-once solve.
 """
 from __future__ import annotations
 
@@ -62,3 +68,37 @@ def solve_time_stepping(n, nt, dt, mu, eta, mu0, ubar, Abar, b, rtol=1e-8, resta
         its.append(ik)
         res.append(float(np.linalg.norm(rhs - sk.apply_J(X[k]))))
     return X.ravel(), its, {"atol": atol, "step_residuals": res}
+
+
+def solve_windows(n, nt, dt, mu, eta, mu0, ubar, Abar, b, window, rtol=1e-8, restart=30, maxit=2000,
+                  warm_start=True):
+    """x = J^{-1} b by windows of `window` slabs (the last one shorter), each by
+    GMRES right-preconditioned with the P_T of its own slabs.
+
+    Returns (x, iterations per window, stats) like solve_time_stepping; with a
+    warm start every slab of a window starts from the previous window's last
+    slab."""
+    first = slab_system(n, dt, mu, eta, mu0, ubar[0], Abar[0])
+    ns = first.ns
+    B = np.asarray(b, dtype=np.float64).reshape(nt, ns)
+    Bp = np.stack([first.project_pressure(B[k]) for k in range(nt)])
+    bnorm = np.linalg.norm(Bp)
+    C = first.coupling()
+    X = np.zeros((nt, ns))
+    its, res = [], []
+    for k0 in range(0, nt, window):
+        w = min(window, nt - k0)
+        sw = SpaceTimeSystem(n, w, dt, mu, eta, mu0, ubar[k0:k0 + w], Abar[k0:k0 + w])
+        rhs = Bp[k0:k0 + w].copy()
+        if k0 > 0:
+            rhs[0] -= C @ X[k0 - 1]
+        rhs = rhs.ravel()
+        x0 = np.tile(X[k0 - 1], w) if (warm_start and k0 > 0) else None
+        atol = rtol * bnorm * np.sqrt(w / nt)
+        rn = np.linalg.norm(rhs)
+        tol = atol / rn if rn > 0 else 0.0
+        xw, iw, _ = gmres(sw.apply_J, sw.apply_PT_inv, rhs, restart=restart, rtol=tol, maxit=maxit, x0=x0)
+        X[k0:k0 + w] = sw.normalise_pressure(xw).reshape(w, ns)
+        its.append(iw)
+        res.append(float(np.linalg.norm(rhs - sw.apply_J(X[k0:k0 + w].ravel()))))
+    return X.ravel(), its, {"step_residuals": res}

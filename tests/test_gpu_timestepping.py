@@ -9,7 +9,8 @@
   residual recomputed by the oracle meets 1e-8, on a ragged 5-slab horizon.
 * Cold and warm starts give the same solution to the tolerance.
 * Windows of several slabs (windowed space-time, each window with its own P_T):
-  EXACT mode equals x*, production FP32 meets the space-time tolerance.
+  EXACT mode equals x* with the oracle's per-window iteration counts (+-1),
+  production FP32 meets the space-time tolerance.
 """
 import functools
 import sys
@@ -18,7 +19,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle.timestepping import solve_time_stepping
+from oracle.timestepping import solve_time_stepping, solve_windows
 from paper_2309_00768_amd import inputs
 from parity_util import assert_blocks
 
@@ -102,6 +103,10 @@ def test_windowed_space_time_matches_direct_solution(window):
     x, infos, rc = ts.solve(dev(b), rtol=1e-13)
     assert rc == 0 and all(i.converged for i in infos)
     assert_blocks(x.cpu().numpy(), ref.direct_solve(b), ts.offsets, cfg.nt, 1e-10, f"x vs x* (windows of {window})")
+    its = [i.iterations for i in infos]
+    _, its_ref, _ = solve_windows(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, b, window, rtol=1e-13)
+    say(f"    its per window gpu {its} oracle {its_ref}")
+    assert all(abs(a - r) <= 1 for a, r in zip(its, its_ref)), (its, its_ref)
     ts32 = stepping(cfg, ub, ab, precision="fp32", window=window, restart=60)
     x, infos, rc = ts32.solve(dev(b), rtol=1e-8)
     bp = ref.project_pressure(b)

@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle.timestepping import slab_system, solve_time_stepping
+from oracle.timestepping import slab_system, solve_time_stepping, solve_windows
 from paper_2309_00768_amd import inputs
 
 
@@ -90,3 +90,30 @@ def test_first_slab_of_PT_is_the_single_step_preconditioner():
     R2[1:] = rng.standard_normal((nt - 1, full.ns))
     z2 = full.apply_PT_inv(R2.ravel()).reshape(nt, full.ns)
     assert rel(z2[0], z[0]) <= 1e-13
+
+
+@pytest.mark.parametrize("window", [2, 3])
+def test_windows_reach_the_all_at_once_solution(window):
+    """Windows of W slabs in turn (7 slabs: the last window shorter) reach x*, and
+    the whole residual meets the space-time tolerance."""
+    cfg = inputs.Config("win", 4, 7, 0.1, 100.0, 100.0)
+    ub, ab = inputs.state(cfg)
+    sysm = oracle.system_from_config(cfg, ub, ab)
+    b = inputs.rhs(cfg, 3)
+    x, its, _ = solve_windows(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, b, window, rtol=1e-12)
+    assert len(its) == -(-cfg.nt // window)
+    xs = sysm.direct_solve(b)
+    assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+def test_one_slab_windows_are_time_stepping_and_one_window_is_all_at_once():
+    cfg = inputs.Config("win1", 4, 5, 0.1, 100.0, 100.0)
+    ub, ab = inputs.state(cfg)
+    b = inputs.rhs(cfg, 4)
+    _, its1, _ = solve_windows(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, b, 1, rtol=1e-10)
+    _, its_ts, _ = solve_time_stepping(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, b, rtol=1e-10)
+    assert its1 == its_ts
+    _, its_all, _ = solve_windows(cfg.n, cfg.nt, cfg.dt, cfg.mu, cfg.eta, cfg.mu0, ub, ab, b, cfg.nt, rtol=1e-10)
+    sysm = oracle.system_from_config(cfg, ub, ab)
+    _, its_st, _ = oracle.solve_fgmres(sysm, b, rtol=1e-10)
+    assert its_all == [its_st]
