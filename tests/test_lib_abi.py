@@ -157,3 +157,39 @@ def test_chebyshev_intervals_are_exported_per_slab():
         # D^{-1} A of these blocks has a positive spectrum: 0 < theta - delta < theta + delta
         assert np.all(delta > 0) and np.all(theta - delta > 0), iv
     plan.close()
+
+
+STRUCTS = {"st_problem": "StProblem", "st_opts": "StOpts", "st_info": "StInfo", "st_nl_problem": "StNlProblem",
+           "st_newton_opts": "StNewtonOpts", "st_newton_info": "StNewtonInfo"}
+
+
+def test_binding_structures_match_the_header_layout(tmp_path):
+    """The ctypes mirrors of the header's structures have the C compiler's size
+    and field offsets (the header compiled as C by gcc)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "st.h"', 'int main(void) {']
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(binding, pyname)
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True,
+                   capture_output=True, timeout=120)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True, timeout=60).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            cname, field, value = line.split()
+            got[(cname, field)] = int(value)
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(binding, pyname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
