@@ -406,6 +406,8 @@ class TimeStepping:
 
     def __init__(self, n, nt, dt, mu, eta, mu0, ubar, abar, device="cuda:0", precision="fp64", inner="amg",
                  restart=30, window=1, **plan_kw):
+        if int(window) < 1:
+            raise ValueError(f"window must be at least 1 slab, got {window}")
         self.systems = []
         for k0 in range(0, nt, window):
             w = min(window, nt - k0)

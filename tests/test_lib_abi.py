@@ -193,3 +193,8 @@ def test_binding_structures_match_the_header_layout(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for fname, _ in cls._fields_:
             assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_time_stepping_window_must_hold_a_slab():
+    with pytest.raises(ValueError):
+        binding.TimeStepping(4, 3, 0.1, 0.01, 0.01, 1.0, None, None, window=0)
